@@ -1,0 +1,279 @@
+"""PEOs oracle -- TEST INFRASTRUCTURE ONLY.
+
+A plain CPU implementation of what the PEOs-routed graph search computes,
+written from the paper (Lu, Xiao, Ishikawa, ICML 2024) to check the HIP
+library.  It shares no code with that library and never imports it.  Only the
+test suite, the smoke entry and the CPU-baseline leg of the benchmark may use
+it; the product path never does.
+
+Parts:
+  * ``peos_oracle.c`` (loaded here through ctypes): edge records of PEOs steps
+    (1)-(3), the projection table of step (5), the routing test of steps (4)
+    and (6) / Alg. 2, and the search loop of Alg. 1 -- double precision, with
+    the edge codes decided in single precision (see that file's header).
+  * this module: exact brute-force k-NN in float64 (the recall reference) and
+    the closed forms of the analysis section used as pins.
+
+Every function below is pinned by a test in tests/test_oracle_*.py.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+L2 = 0
+ANGULAR = 1
+MODE_PEOS = 0
+MODE_EXHAUSTIVE = 1
+
+COUNTERS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0",
+            "test_h", "test_zero", "passes", "ndist", "inserted")
+F_HT, F_A1, F_A0, F_DELTA, F_ORDER = 1, 2, 4, 8, 16
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "peos_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C part with gcc (no fp contraction, so the single-precision
+    code decisions follow the stated fmaf order exactly)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f64 = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        lib.oracle_norm_ppf.argtypes = [f64]
+        lib.oracle_norm_ppf.restype = f64
+        lib.oracle_threshold.argtypes = [f64, f64, f64, i32, f64, f64]
+        lib.oracle_threshold.restype = f64
+        lib.oracle_edge_record.argtypes = [P, P, i32, i32, i32, P, P, P, P, P]
+        lib.oracle_edge_record.restype = i32
+        lib.oracle_build_tables.argtypes = [P, i64, i32, P, i32, i32, i32, P, P, P, P, P, i32]
+        lib.oracle_build_tables.restype = i32
+        lib.oracle_query_table.argtypes = [P, i32, i32, i32, P, P, P]
+        lib.oracle_query_table.restype = None
+        lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, P]
+        lib.oracle_test_edge.restype = i32
+        lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
+                                      i32, i32, f64, i32, f64, i32, P, P, P, P, P]
+        lib.oracle_search.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+# ---------------------------------------------------------------------------
+# constants
+# ---------------------------------------------------------------------------
+def norm_ppf(p: float) -> float:
+    """Standard normal quantile (bisection on the erfc form of the CDF)."""
+    return _load().oracle_norm_ppf(float(p))
+
+
+def eta(L: int, m: int) -> float:
+    """sqrt(2 L ln m): the mean scale of N_min^{e,x} in step (4)."""
+    return math.sqrt(2.0 * L * math.log(m))
+
+
+def threshold(A: float, w_reg: float, w_res: float, L: int, m: int, eps: float) -> float:
+    """T_r of step (6): eps-quantile of N(A eta, w_reg^2 + L w_res^2 - L A^2/(L+1))."""
+    return _load().oracle_threshold(float(A), float(w_reg), float(w_res), int(L), eta(L, m),
+                                    norm_ppf(eps))
+
+
+# ---------------------------------------------------------------------------
+# steps (1)-(3), (5), (6)
+# ---------------------------------------------------------------------------
+def edge_record(xv, xu, L, m, A, B):
+    """Codes (L+1 bytes; [0] residual, [1..L] blocks), scalars
+    {|e|, w_reg, w_res, g_e=(|u|^2-|v|^2)/2} and the smallest top-2 margin."""
+    xv, xu, A, B = _f32(xv), _f32(xu), _f32(A), _f32(B)
+    d = xv.shape[0]
+    codes = np.zeros(L + 1, np.uint8)
+    scal = np.zeros(4, np.float64)
+    margin = np.zeros(1, np.float64)
+    rc = _load().oracle_edge_record(_p(xv), _p(xu), d, L, m, _p(A), _p(B), _p(codes), _p(scal),
+                                    _p(margin))
+    if rc:
+        raise ValueError("bad edge-record arguments")
+    return codes, scal, float(margin[0])
+
+
+def build_tables(base, graph, L, m, A, B, nthreads=None):
+    """Records of every edge: codes (n, R, L+1) uint8, scal (n, R, 4) float64,
+    margin (n, R) float64.  Padding edges are zero."""
+    base, A, B = _f32(base), _f32(A), _f32(B)
+    graph = np.ascontiguousarray(graph, dtype=np.int32)
+    n, d = base.shape
+    R = graph.shape[1]
+    codes = np.zeros((n, R, L + 1), np.uint8)
+    scal = np.zeros((n, R, 4), np.float64)
+    margin = np.zeros((n, R), np.float64)
+    nt = nthreads or min(16, os.cpu_count() or 1)
+    rc = _load().oracle_build_tables(_p(base), n, d, _p(graph), R, L, m, _p(A), _p(B), _p(codes),
+                                     _p(scal), _p(margin), nt)
+    if rc:
+        raise ValueError("bad build arguments")
+    return codes, scal, margin
+
+
+def query_table(q, L, m, A, B):
+    """(L+1) x m projection table of step (5) in float64: row 0 = q'.b_j,
+    row i = q'_i . a^i_j."""
+    q, A, B = _f32(q), _f32(A), _f32(B)
+    out = np.zeros((L + 1, m), np.float64)
+    _load().oracle_query_table(_p(q), q.shape[0], L, m, _p(A), _p(B), _p(out))
+    return out
+
+
+def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps):
+    """One routing test of edge (v, u) against furthest result p.
+    Returns (pass, A_r, H, T, kind) with kind 0 zero edge / 1 A>=1 / 2 A<=0 / 3 H-vs-T."""
+    xv, xu, xp, q, A, B = map(_f32, (xv, xu, xp, q, A, B))
+    out = np.zeros(4, np.float64)
+    ok = _load().oracle_test_edge(_p(xv), _p(xu), _p(xp), _p(q), q.shape[0], L, m, _p(A), _p(B),
+                                  metric, float(eps), _p(out))
+    return bool(ok), out[0], out[1], out[2], int(out[3])
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1
+# ---------------------------------------------------------------------------
+def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MODE_PEOS,
+           tau=1e-5, nthreads=None, kstride=None, pool=0):
+    """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
+    pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
+    pool <= ef = the HNSW stopping rule.
+    Returns dict(ids (nq, kstride) int64, dist float64, counters (nq, 11) int64,
+    fragile (nq,) int32 flag words, status (nq,) int32)."""
+    base, queries = _f32(base), _f32(queries)
+    A = _f32(A) if A is not None else np.zeros(1, np.float32)
+    B = _f32(B) if B is not None else np.zeros(1, np.float32)
+    graph = np.ascontiguousarray(graph, dtype=np.int32)
+    n, d = base.shape
+    nq = queries.shape[0]
+    karr = np.ascontiguousarray(np.broadcast_to(np.asarray(k, np.int32), (nq,)))
+    efarr = np.ascontiguousarray(np.broadcast_to(np.asarray(ef, np.int32), (nq,)))
+    ks = int(kstride or (karr.max() if nq else 1))
+    ids = np.zeros((nq, ks), np.int64)
+    dist = np.zeros((nq, ks), np.float64)
+    cnt = np.zeros((nq, len(COUNTERS)), np.int64)
+    frag = np.zeros(nq, np.int32)
+    status = np.zeros(nq, np.int32)
+    nt = nthreads or min(16, os.cpu_count() or 1)
+    rc = _load().oracle_search(_p(base), n, d, _p(graph), graph.shape[1], int(entry), L, m, _p(A),
+                               _p(B), metric, _p(queries), nq, _p(karr), _p(efarr), ks,
+                               int(pool), float(eps), mode, float(tau), nt, _p(ids), _p(dist), _p(cnt),
+                               _p(frag), _p(status))
+    if rc:
+        raise ValueError("bad search arguments")
+    return dict(ids=ids, dist=dist, counters=cnt, fragile=frag, status=status)
+
+
+# ---------------------------------------------------------------------------
+# exact k-NN (recall reference)
+# ---------------------------------------------------------------------------
+def brute_force(base, queries, k, metric):
+    """Exact top-k in float64 by (distance, id): squared l2, or 1 - x.q/|q|."""
+    xb = np.asarray(base, np.float64)
+    ids_out = np.full((len(queries), k), -1, np.int64)
+    d_out = np.full((len(queries), k), np.inf)
+    for i, q in enumerate(np.asarray(queries, np.float64)):
+        if metric == L2:
+            dd = ((xb - q) ** 2).sum(1)
+        else:
+            dd = 1.0 - xb @ q / np.linalg.norm(q)
+        order = np.lexsort((np.arange(len(dd)), dd))[:k]
+        ids_out[i, :len(order)] = order
+        d_out[i, :len(order)] = dd[order]
+    return ids_out, d_out
+
+
+# ---------------------------------------------------------------------------
+# closed forms of the analysis section (pins)
+# ---------------------------------------------------------------------------
+def ewreg_exact(L: int, d: int) -> float:
+    """E[w_reg] for e uniform on the sphere: sqrt(L) E[sqrt(X)] with
+    X ~ Beta(d'/2, (d-d')/2), written with Gamma functions (proof of the
+    lemma bounding w_reg)."""
+    dp = d // L
+    lg = math.lgamma
+    return math.sqrt(L) * (dp - 1) / (d - 1) * math.exp(
+        lg((dp - 1) / 2) + lg(d / 2) - lg(dp / 2) - lg((d - 1) / 2))
+
+
+def ewreg_bound(L: int, d: int) -> float:
+    """The lemma's lower bound (d'-1) sqrt(2Ld-3L) / ((d-1) sqrt(2d'+2 sqrt3-6))."""
+    dp = d / L
+    return (dp - 1) * math.sqrt(2 * L * d - 3 * L) / ((d - 1) * math.sqrt(2 * dp + 2 * math.sqrt(3) - 6))
+
+
+def rceos_min_m(n_hash: int, theta: float) -> float:
+    """RCEOs beats SimHash with n hash functions when m > exp(n / (2 theta (pi - theta)))."""
+    return math.exp(n_hash / (2 * theta * (math.pi - theta)))
+
+
+def peos_opt_min_L(n_hash: int, theta: float, m: int) -> float:
+    """PEOs(opt): L ln m > n / (2 theta (pi - theta))."""
+    return n_hash / (2 * theta * (math.pi - theta)) / math.log(m)
+
+
+def peos_crossing_L(n_hash: int, theta: float, m: int, d: int) -> float:
+    """Smallest real L with L ln m > (w_reg^2 + L w_res^2) n / (2 theta (pi-theta)),
+    w_res^2 taken as E[w_res^2] = 1 - E[w_reg^2] under the isotropic law, with
+    E[w_reg^2] = L E[X], X ~ Beta(d'/2, (d-d')/2) = L (d'/d) = 1 for integer d';
+    for real L the expectation is evaluated with d' = d/L through
+    E[w_reg]^2 + Var, approximated here by E[w_reg]^2 (Table 5 setting)."""
+    c = n_hash / (2 * theta * (math.pi - theta))
+
+    def f(L):
+        dp = d / L
+        lg = math.lgamma
+        ew = math.sqrt(L) * (dp - 1) / (d - 1) * math.exp(
+            lg((dp - 1) / 2) + lg(d / 2) - lg(dp / 2) - lg((d - 1) / 2))
+        wres2 = max(0.0, 1.0 - ew * ew)
+        return L * math.log(m) - (ew * ew + L * wres2) * c
+
+    lo, hi = 1.01, 50.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0:
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def max_abs_normal_moments(m: int):
+    """Mean and variance of M_m = max of m iid |N(0,1)| (numerical integration
+    of its CDF (2 Phi(x) - 1)^m)."""
+    from scipy import integrate, stats
+
+    cdf = lambda x: (2 * stats.norm.cdf(x) - 1) ** m
+    mean = integrate.quad(lambda x: 1 - cdf(x), 0, np.inf, epsabs=1e-13)[0]
+    ex2 = integrate.quad(lambda x: 2 * x * (1 - cdf(x)), 0, np.inf, epsabs=1e-13)[0]
+    return mean, ex2 - mean * mean

@@ -1,0 +1,710 @@
+/*
+ * PEOs oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, scalar CPU implementation of what the PEOs-routed graph
+ * search computes (Lu, Xiao, Ishikawa, "Probabilistic Routing for
+ * Graph-Based Approximate Nearest Neighbor Search", ICML 2024).  It exists to
+ * check the HIP library and shares no code with it.  Only the test suite, the
+ * smoke entry and the CPU-baseline leg of the benchmark may load it.
+ *
+ * Arithmetic is double precision, except for the one place where floating
+ * point decides an integer: the edge codes of PEOs step (3) are argmaxes, and
+ * they are decided in single precision with the fixed operation order given
+ * in edge_codes_fp32() below -- the precision the GPU builder uses -- so both
+ * sides take the same integer decisions.
+ *
+ * Paper sections followed:
+ *   - Alg. 1 (graph-based ANNS with routing) and its text in Sec. 3;
+ *   - Sec. 4.2 "PEOs Test", steps (1)-(6), and Alg. 2;
+ *   - the residual-edge remedy of Sec. 4.1 (test on e = u - v, q normalized);
+ *   - Appendix "Extension to MIPS" for the angular numerator.
+ * Readings where the paper is silent (visited-on-distance, delta snapshot per
+ * expansion, (dist, id) order, single sorted list with expanded flags,
+ * zero-block handling, closed-form quantile) are stated where they apply.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_L2 0
+#define OR_ANGULAR 1
+#define OR_MODE_PEOS 0
+#define OR_MODE_EXHAUSTIVE 1
+
+/* counters, per query */
+enum {
+    C_EXPANSIONS = 0, /* nodes popped and expanded                        */
+    C_EDGES,          /* valid neighbour ids enumerated                   */
+    C_VISITED_SKIPS,  /* neighbours skipped because already visited       */
+    C_TESTS,          /* PEOs tests run (R full, neighbour unvisited)     */
+    C_TEST_GE1,       /* tests decided by A >= 1 (fail)                   */
+    C_TEST_LE0,       /* tests decided by A <= 0 (pass)                   */
+    C_TEST_H,         /* tests decided by H >= T                          */
+    C_TEST_ZERO,      /* tests on a zero-length edge (decided by sign)    */
+    C_PASSES,         /* tests that passed                                */
+    C_NDIST,          /* exact distances computed (entry included)        */
+    C_INSERTED,       /* distances that entered the merge                 */
+    C_NCOUNT
+};
+
+/* fragile-decision flags, per query */
+#define F_HT 1     /* |H - T| tiny                                     */
+#define F_A1 2     /* A close to 1                                     */
+#define F_A0 4     /* A close to 0                                     */
+#define F_DELTA 8  /* d_u close to delta                               */
+#define F_ORDER 16 /* two list entries with nearly equal distances     */
+
+/* ------------------------------------------------------------------ */
+/* inverse standard normal CDF, by bisection on the CDF written with erfc */
+/* ------------------------------------------------------------------ */
+static double norm_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+double oracle_norm_ppf(double p)
+{
+    if (!(p > 0.0) || !(p < 1.0)) return NAN;
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 400; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (norm_cdf(mid) < p) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* ------------------------------------------------------------------ */
+/* Steps (1)-(3): one edge record                                      */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Codes of PEOs step (3), decided in single precision.  Operation order:
+ *   e_k   = x_u[k] - x_v[k]
+ *   s_i   = sqrtf(sum_k e_k*e_k)         (fmaf chain over the block, k ascending)
+ *   p_ij  = sum_t e_{i,t} * a^i_j[t]     (fmaf chain, t ascending, from 0)
+ *   code_i: j* = first j maximizing |p_ij|; sign negative iff p_ij* < 0
+ *   L'    = number of blocks with s_i > 0
+ *   c     = (s_1 + ... + s_L) / L'       (sequential adds, one divide)
+ *   r_i   = c / s_i  (0 when s_i == 0)
+ *   eres_k = fmaf(-r_i, e_k, e_k)
+ *   code_0 as code_i, over eres and the full-space vectors b_j (fmaf chain
+ *          over k = 0..d-1).
+ * The encoding is (j* - 1) + m * [sign < 0] with j* counted from 1, i.e. a
+ * byte in [0, 2m).  Block 0 is the residual code e[0], blocks 1..L are e[i].
+ * margin[i] returns the relative gap between the two largest |p| (a near-tie
+ * diagnostic only).
+ */
+static void edge_codes_fp32(const float* xv, const float* xu, int d, int L, int m,
+                            const float* A, const float* B, float* ework, float* eres,
+                            uint8_t* codes, double* margin)
+{
+    const int dp = d / L;
+    float s[256];
+    for (int k = 0; k < d; ++k) ework[k] = xu[k] - xv[k];
+    int nonzero = 0;
+    for (int i = 0; i < L; ++i) {
+        float ss = 0.0f;
+        for (int t = 0; t < dp; ++t) ss = fmaf(ework[i * dp + t], ework[i * dp + t], ss);
+        s[i] = sqrtf(ss);
+        if (s[i] > 0.0f) ++nonzero;
+    }
+    for (int i = 0; i < L; ++i) {
+        int best = 0;
+        float bv = -1.0f, second = -1.0f, bp = 0.0f;
+        for (int j = 0; j < m; ++j) {
+            const float* a = A + ((size_t)i * m + j) * dp;
+            float p = 0.0f;
+            for (int t = 0; t < dp; ++t) p = fmaf(ework[i * dp + t], a[t], p);
+            float ap = fabsf(p);
+            if (ap > bv) { second = bv; bv = ap; best = j; bp = p; }
+            else if (ap > second) second = ap;
+        }
+        codes[1 + i] = (uint8_t)(best + (bp < 0.0f ? m : 0));
+        if (margin) margin[1 + i] = bv > 0.0f ? (double)(bv - second) / (double)bv : 1.0;
+    }
+    float c = 0.0f;
+    if (nonzero > 0) {
+        float sum = 0.0f;
+        for (int i = 0; i < L; ++i) sum = sum + s[i];
+        c = sum / (float)nonzero;
+    }
+    for (int i = 0; i < L; ++i) {
+        float r = s[i] > 0.0f ? c / s[i] : 0.0f;
+        for (int t = 0; t < dp; ++t) {
+            float ek = ework[i * dp + t];
+            eres[i * dp + t] = fmaf(-r, ek, ek);
+        }
+    }
+    {
+        int best = 0;
+        float bv = -1.0f, second = -1.0f, bp = 0.0f;
+        for (int j = 0; j < m; ++j) {
+            const float* b = B + (size_t)j * d;
+            float p = 0.0f;
+            for (int k = 0; k < d; ++k) p = fmaf(eres[k], b[k], p);
+            float ap = fabsf(p);
+            if (ap > bv) { second = bv; bv = ap; best = j; bp = p; }
+            else if (ap > second) second = ap;
+        }
+        codes[0] = (uint8_t)(best + (bp < 0.0f ? m : 0));
+        if (margin) margin[0] = bv > 0.0f ? (double)(bv - second) / (double)bv : 1.0;
+    }
+}
+
+/*
+ * Scalars of steps (1) and (6), in double precision, from the definitions.
+ * Step (1): e = e_reg + e_res with e_reg the orthogonal projection of e on
+ * the direction g = [e_i / (sqrt(L) |e_i|)]_i.  When every block is nonzero g
+ * is a unit vector and w_reg = sum_i |e_i| / (sqrt(L) |e|); a zero block
+ * contributes a zero component to g (the paper leaves this case open), and
+ * the projection is still taken on the line spanned by g.
+ * out[0] = |e|, out[1] = w_reg, out[2] = w_res, out[3] = |u|^2, out[4] = |v|^2.
+ */
+static void edge_scalars_fp64(const float* xv, const float* xu, int d, int L, double* ework,
+                              double* out)
+{
+    const int dp = d / L;
+    double s[256];
+    double ne2 = 0.0, nu2 = 0.0, nv2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        ework[k] = (double)xu[k] - (double)xv[k];
+        ne2 += ework[k] * ework[k];
+        nu2 += (double)xu[k] * (double)xu[k];
+        nv2 += (double)xv[k] * (double)xv[k];
+    }
+    for (int i = 0; i < L; ++i) {
+        double ss = 0.0;
+        for (int t = 0; t < dp; ++t) ss += ework[i * dp + t] * ework[i * dp + t];
+        s[i] = sqrt(ss);
+    }
+    double ne = sqrt(ne2);
+    double wreg = 1.0, wres = 0.0;
+    if (ne > 0.0) {
+        /* g and e.g, |g|^2 */
+        double eg = 0.0, gg = 0.0;
+        for (int i = 0; i < L; ++i) {
+            if (s[i] <= 0.0) continue;
+            for (int t = 0; t < dp; ++t) {
+                double g = ework[i * dp + t] / (sqrt((double)L) * s[i]);
+                eg += ework[i * dp + t] * g;
+                gg += g * g;
+            }
+        }
+        /* e_reg = (e.g / g.g) g ; e_res = e - e_reg */
+        double nreg2 = 0.0, nres2 = 0.0;
+        for (int i = 0; i < L; ++i) {
+            for (int t = 0; t < dp; ++t) {
+                double g = s[i] > 0.0 ? ework[i * dp + t] / (sqrt((double)L) * s[i]) : 0.0;
+                double ereg = (eg / gg) * g;
+                double eres = ework[i * dp + t] - ereg;
+                nreg2 += ereg * ereg;
+                nres2 += eres * eres;
+            }
+        }
+        wreg = sqrt(nreg2) / ne;
+        wres = sqrt(nres2) / ne;
+    }
+    out[0] = ne;
+    out[1] = wreg;
+    out[2] = wres;
+    out[3] = nu2;
+    out[4] = nv2;
+}
+
+typedef struct {
+    uint8_t codes[257];
+    double norm_e, w_reg, w_res, nu2, nv2;
+    double margin_min;
+} edge_rec;
+
+static void edge_record(const float* xv, const float* xu, int d, int L, int m, const float* A,
+                        const float* B, float* fw1, float* fw2, double* dw, edge_rec* r)
+{
+    double margin[257];
+    edge_codes_fp32(xv, xu, d, L, m, A, B, fw1, fw2, r->codes, margin);
+    double sc[5];
+    edge_scalars_fp64(xv, xu, d, L, dw, sc);
+    r->norm_e = sc[0];
+    r->w_reg = sc[1];
+    r->w_res = sc[2];
+    r->nu2 = sc[3];
+    r->nv2 = sc[4];
+    double mm = 1.0;
+    for (int i = 0; i <= L; ++i) if (margin[i] < mm) mm = margin[i];
+    r->margin_min = mm;
+}
+
+/*
+ * Public: records of every edge of a graph.  codes: n*R*(L+1) bytes, edge
+ * (v, j) at [(v*R + j)*(L+1) + i], i = 0 residual code, 1..L block codes.
+ * scal: n*R*4 doubles {|e|, w_reg, w_res, g_e = (|u|^2 - |v|^2)/2}.
+ * margin: n*R doubles.  Padding edges (id < 0) are left zero.
+ */
+typedef struct {
+    const float *base, *A, *B;
+    const int32_t* graph;
+    int64_t n, v0, v1;
+    int d, R, L, m;
+    uint8_t* codes;
+    double *scal, *margin;
+} build_job;
+
+static void* build_worker(void* arg)
+{
+    build_job* j = (build_job*)arg;
+    float* fw1 = (float*)malloc(sizeof(float) * j->d);
+    float* fw2 = (float*)malloc(sizeof(float) * j->d);
+    double* dw = (double*)malloc(sizeof(double) * j->d);
+    edge_rec r;
+    for (int64_t v = j->v0; v < j->v1; ++v) {
+        for (int e = 0; e < j->R; ++e) {
+            int32_t u = j->graph[v * j->R + e];
+            size_t idx = (size_t)v * j->R + e;
+            if (u < 0) continue;
+            edge_record(j->base + (size_t)v * j->d, j->base + (size_t)u * j->d, j->d, j->L, j->m,
+                        j->A, j->B, fw1, fw2, dw, &r);
+            memcpy(j->codes + idx * (j->L + 1), r.codes, (size_t)j->L + 1);
+            j->scal[idx * 4 + 0] = r.norm_e;
+            j->scal[idx * 4 + 1] = r.w_reg;
+            j->scal[idx * 4 + 2] = r.w_res;
+            j->scal[idx * 4 + 3] = 0.5 * (r.nu2 - r.nv2);
+            if (j->margin) j->margin[idx] = r.margin_min;
+        }
+    }
+    free(fw1);
+    free(fw2);
+    free(dw);
+    return NULL;
+}
+
+int oracle_build_tables(const float* base, int64_t n, int d, const int32_t* graph, int R, int L,
+                        int m, const float* A, const float* B, uint8_t* codes, double* scal,
+                        double* margin, int nthreads)
+{
+    if (L <= 0 || d % L || L > 255 || m <= 0 || 2 * m > 256 || d / L > 4096) return -1;
+    if (nthreads < 1) nthreads = 1;
+    memset(codes, 0, (size_t)n * R * (L + 1));
+    memset(scal, 0, sizeof(double) * (size_t)n * R * 4);
+    if (margin) memset(margin, 0, sizeof(double) * (size_t)n * R);
+    pthread_t th[256];
+    build_job jobs[256];
+    if (nthreads > 256) nthreads = 256;
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (build_job){base, A, B, graph, n, n * t / nthreads, n * (t + 1) / nthreads,
+                              d, R, L, m, codes, scal, margin};
+        pthread_create(&th[t], NULL, build_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* Public: one edge record (tests). scal as in oracle_build_tables. */
+int oracle_edge_record(const float* xv, const float* xu, int d, int L, int m, const float* A,
+                       const float* B, uint8_t* codes, double* scal, double* margin_min)
+{
+    if (L <= 0 || d % L || L > 255 || 2 * m > 256) return -1;
+    float* fw1 = (float*)malloc(sizeof(float) * d);
+    float* fw2 = (float*)malloc(sizeof(float) * d);
+    double* dw = (double*)malloc(sizeof(double) * d);
+    edge_rec r;
+    edge_record(xv, xu, d, L, m, A, B, fw1, fw2, dw, &r);
+    memcpy(codes, r.codes, (size_t)L + 1);
+    scal[0] = r.norm_e;
+    scal[1] = r.w_reg;
+    scal[2] = r.w_res;
+    scal[3] = 0.5 * (r.nu2 - r.nv2);
+    if (margin_min) *margin_min = r.margin_min;
+    free(fw1);
+    free(fw2);
+    free(dw);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Step (5): projection table of one query                             */
+/* ------------------------------------------------------------------ */
+/*
+ * T[0][j] = q'.b_j and T[i][j] = q'_i . a^i_j (i = 1..L), q' = q/|q| and q'_i
+ * the i-th block of q' (not renormalized: the combination in Sec. 5.1 needs
+ * sum_i |q'_i|^2 = 1).  table: (L+1) x m doubles.
+ */
+void oracle_query_table(const float* q, int d, int L, int m, const float* A, const float* B,
+                        double* table)
+{
+    const int dp = d / L;
+    double qn = 0.0;
+    for (int k = 0; k < d; ++k) qn += (double)q[k] * (double)q[k];
+    qn = sqrt(qn);
+    for (int j = 0; j < m; ++j) {
+        double acc = 0.0;
+        for (int k = 0; k < d; ++k) acc += ((double)q[k] / qn) * (double)B[(size_t)j * d + k];
+        table[j] = acc;
+    }
+    for (int i = 0; i < L; ++i)
+        for (int j = 0; j < m; ++j) {
+            double acc = 0.0;
+            for (int t = 0; t < dp; ++t)
+                acc += ((double)q[i * dp + t] / qn) * (double)A[((size_t)i * m + j) * dp + t];
+            table[(size_t)(1 + i) * m + j] = acc;
+        }
+}
+
+/* signed table lookup for a code byte: sgn(e[i]) * T[i][|e[i]|] */
+static double lookup(const double* table, int m, int i, uint8_t c)
+{
+    int j = c % m;
+    double v = table[(size_t)i * m + j];
+    return c >= m ? -v : v;
+}
+
+/* ------------------------------------------------------------------ */
+/* Steps (4) and (6): the routing test                                 */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double eta;   /* sqrt(2 L ln m)                       */
+    double c_eps; /* standard-normal eps-quantile          */
+    double tau;   /* relative width of a fragile decision  */
+    int L, m, metric;
+} test_params;
+
+/*
+ * Threshold of step (4)/(6): the eps-quantile of
+ * N(x sqrt(2 L ln m), w_reg^2 + L w_res^2 - L x^2/(L+1)), written in closed
+ * form as mean + sd * Phi^{-1}(eps) (the normal quantile identity used in the
+ * proof of the guarantee).  The paper reads it from a lookup table; the
+ * closed form is that table's exact value.
+ */
+double oracle_threshold(double A, double w_reg, double w_res, int L, double eta, double c_eps)
+{
+    double var = w_reg * w_reg + (double)L * w_res * w_res - (double)L * A * A / (double)(L + 1);
+    return A * eta + c_eps * sqrt(var);
+}
+
+/*
+ * Step (6) for edge e = (v, u) against the furthest result p.  num is the
+ * numerator of A_r written as in the paper: |u|^2/2 - r - v.q with
+ * r = |p|^2/2 - p.q for l2, and with the two squared norms removed for the
+ * angular metric (= p.q - v.q, the MIPS form).  A_r = num / (|q| |e|).
+ * Returns 1 = pass, 0 = fail.  kind: 0 zero-length edge, 1 A>=1, 2 A<=0,
+ * 3 H-vs-T.  flags receives the fragile bits of this decision.
+ */
+static int routing_test(const test_params* tp, const edge_rec* er, const double* table,
+                        double num, double qnorm, double* outA, double* outH, double* outT,
+                        int* kind, int* flags)
+{
+    const double tau = tp->tau;
+    *outA = NAN;
+    *outH = NAN;
+    *outT = NAN;
+    if (er->norm_e == 0.0) {
+        *kind = 0;
+        if (fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
+        return num < 0.0;
+    }
+    double A = num / (qnorm * er->norm_e);
+    *outA = A;
+    if (fabs(A - 1.0) < tau) *flags |= F_A1;
+    if (fabs(A) < tau) *flags |= F_A0;
+    if (A >= 1.0) { *kind = 1; return 0; }
+    if (A <= 0.0) { *kind = 2; return 1; }
+    *kind = 3;
+    double H1 = 0.0;
+    for (int i = 1; i <= tp->L; ++i) H1 += lookup(table, tp->m, i, er->codes[i]);
+    double H2 = lookup(table, tp->m, 0, er->codes[0]);
+    double H = er->w_reg * H1 + sqrt((double)tp->L) * er->w_res * H2;
+    double T = oracle_threshold(A, er->w_reg, er->w_res, tp->L, tp->eta, tp->c_eps);
+    *outH = H;
+    *outT = T;
+    if (fabs(H - T) < tau * (fabs(H) + fabs(T) + 1e-30)) *flags |= F_HT;
+    return H >= T;
+}
+
+/* ------------------------------------------------------------------ */
+/* Alg. 1 with the routing hook                                        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    double dist;
+    int32_t id;
+    int32_t expanded;
+} rentry;
+
+static int rcmp(const void* a, const void* b)
+{
+    const rentry* x = (const rentry*)a;
+    const rentry* y = (const rentry*)b;
+    if (x->dist < y->dist) return -1;
+    if (x->dist > y->dist) return 1;
+    return (x->id > y->id) - (x->id < y->id);
+}
+
+static double dot64(const float* a, const float* b, int d)
+{
+    double s = 0.0;
+    for (int k = 0; k < d; ++k) s += (double)a[k] * (double)b[k];
+    return s;
+}
+
+static double dist64(const float* x, const float* q, double qnorm, int d, int metric)
+{
+    if (metric == OR_L2) {
+        double s = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double t = (double)x[k] - (double)q[k];
+            s += t * t;
+        }
+        return s;
+    }
+    return 1.0 - dot64(x, q, d) / qnorm;
+}
+
+typedef struct {
+    const float *base, *A, *B, *queries;
+    const int32_t *graph, *k, *ef;
+    int64_t n, q0, q1;
+    int d, R, L, m, metric, mode, entry, kstride, pool;
+    double eps, tau;
+    int64_t* out_ids;
+    double* out_dist;
+    int64_t* counters;
+    int32_t* fragile;
+    int32_t* status;
+} search_job;
+
+/*
+ * One query of Alg. 1.  Readings (where the paper leaves a choice):
+ *  - the entry node is distance-computed, put in R and marked visited first;
+ *  - R (results, at most ef) and the priority queue P are kept as ONE list
+ *    sorted by (distance, id) whose entries carry an "expanded" flag.  Its
+ *    first ef entries are R.  An entry beyond position ef stays only while
+ *    unexpanded (it is in P but was pushed out of R).  Popping P = taking the
+ *    first unexpanded entry of the list; the loop ends when there is none
+ *    ("until P is empty").  The list holds at most `pool` entries (the worst
+ *    unexpanded ones beyond that are dropped from P); pool = ef is the HNSW
+ *    stopping rule, an unbounded pool is Alg. 1 as printed;
+ *  - delta (and p, the entry at position ef) are read once per expansion,
+ *    before v's neighbours are tested, and the survivors are merged after all
+ *    of them (the paper tests 16 edges at once with SIMD);
+ *  - a neighbour is visited (never distance-computed again) only once its
+ *    exact distance has been computed, so one that fails the test from v can
+ *    pass from a later node (the residual-edge remedy);
+ *  - a survivor enters the list when R was not full or its distance is
+ *    < delta.
+ */
+static void search_one(const search_job* j, int64_t qi, const test_params* tp, uint8_t* visited,
+                       rentry* R, rentry* S, double* table, float* fw1, float* fw2, double* dw)
+{
+    const int d = j->d;
+    const float* q = j->queries + (size_t)qi * d;
+    const int kq = j->k ? j->k[qi] : 1;
+    int efq = j->ef ? j->ef[qi] : kq;
+    if (efq < kq) efq = kq;
+    const int cap = j->pool > efq ? j->pool : (j->pool > 0 ? efq : (int)(j->n < INT32_MAX ? j->n : INT32_MAX));
+    int64_t* cnt = j->counters + (size_t)qi * C_NCOUNT;
+    int flags = 0;
+    memset(cnt, 0, sizeof(int64_t) * C_NCOUNT);
+    double qnorm = sqrt(dot64(q, q, d));
+    if (!(qnorm > 0.0) || !isfinite(qnorm)) {
+        j->status[qi] = -1;
+        for (int t = 0; t < j->kstride; ++t) {
+            j->out_ids[(size_t)qi * j->kstride + t] = -1;
+            j->out_dist[(size_t)qi * j->kstride + t] = INFINITY;
+        }
+        return;
+    }
+    if (j->mode == OR_MODE_PEOS) oracle_query_table(q, d, j->L, j->m, j->A, j->B, table);
+
+    memset(visited, 0, (size_t)j->n);
+    int size = 0;
+    const float* x0 = j->base + (size_t)j->entry * d;
+    R[0].dist = dist64(x0, q, qnorm, d, j->metric);
+    R[0].id = j->entry;
+    R[0].expanded = 0;
+    size = 1;
+    visited[j->entry] = 1;
+    cnt[C_NDIST]++;
+
+    edge_rec er;
+    for (;;) {
+        int pos = -1;
+        for (int i = 0; i < size; ++i)
+            if (!R[i].expanded) { pos = i; break; }
+        if (pos < 0) break;
+        R[pos].expanded = 1;
+        cnt[C_EXPANSIONS]++;
+        const int32_t v = R[pos].id;
+        const float* xv = j->base + (size_t)v * d;
+        const int full = (size >= efq);
+        const double delta = full ? R[efq - 1].dist : INFINITY;
+        const int32_t p = full ? R[efq - 1].id : -1;
+        double vq = 0.0, r = 0.0;
+        if (full && j->mode == OR_MODE_PEOS) {
+            const float* xp = j->base + (size_t)p * d;
+            vq = dot64(xv, q, d);
+            if (j->metric == OR_L2) r = 0.5 * dot64(xp, xp, d) - dot64(xp, q, d);
+            else r = -dot64(xp, q, d);
+        }
+        int ns = 0;
+        for (int e = 0; e < j->R; ++e) {
+            int32_t u = j->graph[(size_t)v * j->R + e];
+            if (u < 0) continue;
+            cnt[C_EDGES]++;
+            if (visited[u]) { cnt[C_VISITED_SKIPS]++; continue; }
+            const float* xu = j->base + (size_t)u * d;
+            int pass = 1;
+            if (full && j->mode == OR_MODE_PEOS) {
+                edge_record(xv, xu, d, j->L, j->m, j->A, j->B, fw1, fw2, dw, &er);
+                double num;
+                if (j->metric == OR_L2) num = 0.5 * er.nu2 - r - vq;
+                else num = -r - vq;
+                double A, H, T;
+                int kind;
+                pass = routing_test(tp, &er, table, num, qnorm, &A, &H, &T, &kind, &flags);
+                cnt[C_TESTS]++;
+                cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
+                if (pass) cnt[C_PASSES]++;
+            }
+            if (!pass) continue;
+            visited[u] = 1;
+            cnt[C_NDIST]++;
+            double du = dist64(xu, q, qnorm, d, j->metric);
+            if (full && fabs(du - delta) < j->tau * fabs(delta)) flags |= F_DELTA;
+            if (!full || du < delta) {
+                S[ns].dist = du;
+                S[ns].id = u;
+                S[ns].expanded = 0;
+                ++ns;
+                cnt[C_INSERTED]++;
+            }
+        }
+        /* list := sort(list u S) by (distance, id); keep the first ef, keep
+           later entries only while unexpanded, at most `pool` in total */
+        memcpy(R + size, S, sizeof(rentry) * (size_t)ns);
+        int tot = size + ns;
+        qsort(R, (size_t)tot, sizeof(rentry), rcmp);
+        int w = 0;
+        for (int i = 0; i < tot; ++i) {
+            if (i >= efq && R[i].expanded) continue;
+            if (w >= cap) break;
+            R[w++] = R[i];
+        }
+        size = w;
+        for (int i = 1; i < size; ++i) {
+            double a = R[i - 1].dist, b = R[i].dist;
+            double sc = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+            if (a != b && fabs(a - b) < j->tau * sc) flags |= F_ORDER;
+        }
+    }
+    for (int t = 0; t < j->kstride; ++t) {
+        int64_t o = (size_t)qi * j->kstride + t;
+        if (t < kq && t < size) {
+            j->out_ids[o] = R[t].id;
+            j->out_dist[o] = R[t].dist;
+        } else {
+            j->out_ids[o] = -1;
+            j->out_dist[o] = INFINITY;
+        }
+    }
+    j->fragile[qi] = flags;
+    j->status[qi] = 0;
+}
+
+static void* search_worker(void* arg)
+{
+    search_job* j = (search_job*)arg;
+    int efmax = 1;
+    for (int64_t qi = j->q0; qi < j->q1; ++qi) {
+        int kq = j->k ? j->k[qi] : 1;
+        int e = j->ef ? j->ef[qi] : kq;
+        if (e < kq) e = kq;
+        if (e > efmax) efmax = e;
+    }
+    test_params tp;
+    tp.L = j->L;
+    tp.m = j->m;
+    tp.metric = j->metric;
+    tp.tau = j->tau;
+    tp.eta = sqrt(2.0 * (double)j->L * log((double)j->m));
+    tp.c_eps = oracle_norm_ppf(j->eps);
+    uint8_t* visited = (uint8_t*)malloc((size_t)j->n);
+    int64_t lcap = j->pool > 0 ? (j->pool > efmax ? j->pool : efmax) : j->n;
+    rentry* R = (rentry*)malloc(sizeof(rentry) * (size_t)(lcap + j->R + 1));
+    rentry* S = (rentry*)malloc(sizeof(rentry) * (size_t)(j->R + 1));
+    double* table = (double*)malloc(sizeof(double) * (size_t)(j->L + 1) * j->m);
+    float* fw1 = (float*)malloc(sizeof(float) * j->d);
+    float* fw2 = (float*)malloc(sizeof(float) * j->d);
+    double* dw = (double*)malloc(sizeof(double) * j->d);
+    for (int64_t qi = j->q0; qi < j->q1; ++qi)
+        search_one(j, qi, &tp, visited, R, S, table, fw1, fw2, dw);
+    free(visited);
+    free(R);
+    free(S);
+    free(table);
+    free(fw1);
+    free(fw2);
+    free(dw);
+    return NULL;
+}
+
+/*
+ * Public: batched search.  k and ef are per-query arrays (ef := max(ef, k)).
+ * pool: capacity of the candidate list (<= 0: unbounded, Alg. 1 as printed;
+ * values below ef act as ef, the HNSW stopping rule).
+ * out_ids / out_dist: nq x kstride, first k entries of R, padded (-1, +inf).
+ * Distances: squared l2, or 1 - x.q/|q| for the angular metric.
+ * counters: nq x C_NCOUNT int64; fragile: nq flag words; status: 0 ok, -1
+ * zero/non-finite query.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,
+                  int L, int m, const float* A, const float* B, int metric, const float* queries,
+                  int64_t nq, const int32_t* k, const int32_t* ef, int kstride, int pool,
+                  double eps, int mode, double tau, int nthreads, int64_t* out_ids,
+                  double* out_dist, int64_t* counters, int32_t* fragile, int32_t* status)
+{
+    if (n <= 0 || d <= 0 || R <= 0 || entry < 0 || entry >= n) return -1;
+    if (mode == OR_MODE_PEOS && (L <= 0 || d % L || L > 255 || m < 2 || 2 * m > 256)) return -1;
+    if (mode == OR_MODE_PEOS && !(eps > 0.0 && eps <= 0.5)) return -1;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (nthreads > nq) nthreads = (int)(nq > 0 ? nq : 1);
+    pthread_t th[256];
+    search_job jobs[256];
+    for (int t = 0; t < nthreads; ++t) {
+        jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
+                               nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
+                               pool, eps, tau, out_ids, out_dist, counters, fragile, status};
+        pthread_create(&th[t], NULL, search_worker, &jobs[t]);
+    }
+    for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* Public: one routing test, for the pins.  Returns pass (1/0); out = {A, H, T, kind}. */
+int oracle_test_edge(const float* xv, const float* xu, const float* xp, const float* q, int d,
+                     int L, int m, const float* A, const float* B, int metric, double eps,
+                     double* out)
+{
+    float* fw1 = (float*)malloc(sizeof(float) * d);
+    float* fw2 = (float*)malloc(sizeof(float) * d);
+    double* dw = (double*)malloc(sizeof(double) * d);
+    double* table = (double*)malloc(sizeof(double) * (size_t)(L + 1) * m);
+    edge_rec er;
+    edge_record(xv, xu, d, L, m, A, B, fw1, fw2, dw, &er);
+    oracle_query_table(q, d, L, m, A, B, table);
+    test_params tp = {sqrt(2.0 * L * log((double)m)), oracle_norm_ppf(eps), 1e-5, L, m, metric};
+    double qnorm = sqrt(dot64(q, q, d));
+    double vq = dot64(xv, q, d);
+    double r = metric == OR_L2 ? 0.5 * dot64(xp, xp, d) - dot64(xp, q, d) : -dot64(xp, q, d);
+    double num = metric == OR_L2 ? 0.5 * er.nu2 - r - vq : -r - vq;
+    double a, h, t;
+    int kind, flags = 0;
+    int pass = routing_test(&tp, &er, table, num, qnorm, &a, &h, &t, &kind, &flags);
+    out[0] = a;
+    out[1] = h;
+    out[2] = t;
+    out[3] = kind;
+    free(fw1);
+    free(fw2);
+    free(dw);
+    free(table);
+    return pass;
+}

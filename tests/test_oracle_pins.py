@@ -1,0 +1,653 @@
+"""Pins of the oracle against what the paper and mathematics fix.
+
+Each test ties one oracle function to something other than itself: values
+printed in the paper (tests/golden/), closed forms of the analysis section,
+special inputs that reduce a step to its textbook definition, brute force on
+tiny inputs, and invariants of the search (disabling the test reproduces
+exhaustive-neighbour search; the single sorted list equals the two-heap
+formulation).
+"""
+import heapq
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+from scipy.spatial.distance import cdist
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_printed_values.txt")
+
+
+def golden():
+    out = {}
+    for line in open(GOLDEN):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        key, val = line.split()[:2]
+        out[key] = float(val)
+    return out
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib(oracle_lib):
+    return oracle_lib
+
+
+# ---------------------------------------------------------------------------
+# P8: threshold closed form, quantile constants, eta
+# ---------------------------------------------------------------------------
+def test_norm_ppf_matches_scipy():
+    for p in [1e-12, 1e-4, 0.05, 0.1, 0.2, 0.3, 0.5]:
+        assert O.norm_ppf(p) == pytest.approx(stats.norm.ppf(p), rel=1e-12, abs=1e-13)
+    # textbook values
+    assert O.norm_ppf(0.05) == pytest.approx(-1.644853626951473, abs=1e-12)
+    assert O.norm_ppf(0.1) == pytest.approx(-1.281551565544601, abs=1e-12)
+    assert O.norm_ppf(0.2) == pytest.approx(-0.841621233572914, abs=1e-12)
+
+
+def test_eta_values():
+    assert O.eta(4, 16) == pytest.approx(4.709640, abs=1e-6)
+    assert O.eta(8, 16) == pytest.approx(6.660437, abs=1e-6)
+    assert O.eta(16, 16) == pytest.approx(9.419280, abs=1e-6)
+
+
+@pytest.mark.parametrize("L,m,eps", [(4, 16, 0.1), (8, 16, 0.05), (16, 16, 0.2), (8, 128, 0.2), (1, 128, 0.5)])
+def test_threshold_is_normal_quantile(L, m, eps):
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        A = rng.uniform(0.001, 0.999)
+        wreg = rng.uniform(0.5, 1.0)
+        wres = math.sqrt(1 - wreg * wreg)
+        var = wreg ** 2 + L * wres ** 2 - L * A * A / (L + 1)
+        ref = stats.norm.ppf(eps, loc=A * math.sqrt(2 * L * math.log(m)), scale=math.sqrt(var))
+        assert O.threshold(A, wreg, wres, L, m, eps) == pytest.approx(ref, rel=1e-11, abs=1e-11)
+
+
+def test_threshold_monotone_in_A():
+    for eps in (0.05, 0.2, 0.5):
+        A = np.linspace(0.001, 0.999, 400)
+        T = [O.threshold(a, 0.97, math.sqrt(1 - 0.97 ** 2), 8, 16, eps) for a in A]
+        assert np.all(np.diff(T) > 0)
+
+
+# ---------------------------------------------------------------------------
+# P9: closed forms of the analysis section vs the printed values
+# ---------------------------------------------------------------------------
+def test_wreg_bound_and_exact_mean_vs_printed():
+    g = golden()
+    bound = O.ewreg_bound(8, 128)
+    assert bound == pytest.approx(0.97892, abs=5e-6)
+    assert math.floor(bound * 1000) / 1000 == g["wreg_bound_d128_L8"]
+    assert O.ewreg_exact(8, 128) == pytest.approx(0.98643, abs=5e-6)
+    assert O.ewreg_exact(8, 128) >= bound
+
+
+def test_table5_values():
+    g = golden()
+    assert math.ceil(O.rceos_min_m(64, math.pi / 2)) == g["table5_rceos_min_m"]
+    assert round(O.peos_opt_min_L(64, math.pi / 2, 128), 2) == g["table5_peos_opt_min_L"]
+    crossing = O.peos_crossing_L(64, math.pi / 2, 128, 384)
+    assert crossing > O.peos_opt_min_L(64, math.pi / 2, 128)
+    assert abs(crossing - g["table5_peos_min_L"]) < 0.01
+
+
+def test_max_abs_normal_moments():
+    mean, var = O.max_abs_normal_moments(16)
+    assert mean == pytest.approx(2.0772, abs=1e-4) and var == pytest.approx(0.2347, abs=1e-4)
+    # Monte Carlo cross-check
+    z = np.abs(np.random.default_rng(0).standard_normal((400000, 16))).max(1)
+    assert z.mean() == pytest.approx(mean, abs=4e-3)
+    mean128, _ = O.max_abs_normal_moments(128)
+    assert mean128 == pytest.approx(2.8276, abs=1e-4)
+
+
+# ---------------------------------------------------------------------------
+# P6: edge records (steps (1)-(3))
+# ---------------------------------------------------------------------------
+def _blocks(e, L):
+    return e.reshape(L, -1)
+
+
+def test_edge_scalars_closed_forms():
+    rng = np.random.default_rng(11)
+    L, m, d = 8, 16, 128
+    A, B = W.make_directions(L, m, d, 3)
+    for _ in range(200):
+        xv = rng.standard_normal(d).astype(np.float32)
+        xu = (xv + rng.standard_normal(d) * rng.uniform(0.1, 3)).astype(np.float32)
+        codes, scal, _ = O.edge_record(xv, xu, L, m, A, B)
+        e = xu.astype(np.float64) - xv.astype(np.float64)
+        s = np.linalg.norm(_blocks(e, L), axis=1)
+        assert scal[0] == pytest.approx(np.linalg.norm(e), rel=1e-12)
+        assert scal[1] ** 2 + scal[2] ** 2 == pytest.approx(1.0, abs=1e-12)
+        assert scal[1] == pytest.approx(s.sum() / (math.sqrt(L) * np.linalg.norm(e)), rel=1e-12)
+        g_e = 0.5 * (xu.astype(np.float64) @ xu - xv.astype(np.float64) @ xv)
+        assert scal[3] == pytest.approx(g_e, rel=1e-12, abs=1e-9)
+
+
+def test_equal_block_norms_give_wreg_one():
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 4)
+    rng = np.random.default_rng(2)
+    blocks = rng.standard_normal((L, d // L))
+    blocks /= np.linalg.norm(blocks, axis=1, keepdims=True)
+    xu = blocks.reshape(-1).astype(np.float32)
+    _, scal, _ = O.edge_record(np.zeros(d, np.float32), xu, L, m, A, B)
+    assert scal[1] == pytest.approx(1.0, abs=1e-7) and scal[2] == pytest.approx(0.0, abs=1e-3)
+
+
+def test_codes_are_argmax_of_projections():
+    """Codes equal the float64 argmax of |e_i . a^i_j| (and of |e_res . b_j|
+    with e_res = e - (sum_k s_k / L)[e_i / s_i]) wherever the top two are not
+    within 1e-5 relative."""
+    rng = np.random.default_rng(12)
+    L, m, d = 8, 16, 128
+    A, B = W.make_directions(L, m, d, 5)
+    checked = 0
+    for _ in range(300):
+        xv = rng.standard_normal(d).astype(np.float32)
+        xu = (xv + rng.standard_normal(d)).astype(np.float32)
+        codes, _, margin = O.edge_record(xv, xu, L, m, A, B)
+        if margin < 1e-5:
+            continue
+        e = xu.astype(np.float64) - xv.astype(np.float64)
+        eb = _blocks(e, L)
+        for i in range(L):
+            p = A[i].astype(np.float64) @ eb[i]
+            j = int(np.argmax(np.abs(p)))
+            assert codes[1 + i] == j + (m if p[j] < 0 else 0)
+        s = np.linalg.norm(eb, axis=1)
+        eres = (eb - (s.sum() / L) * eb / s[:, None]).reshape(-1)
+        p = B.astype(np.float64) @ eres
+        j = int(np.argmax(np.abs(p)))
+        assert codes[0] == j + (m if p[j] < 0 else 0)
+        checked += 1
+    assert checked > 250
+
+
+def test_basis_edge_code_reduces_to_direction_entry():
+    """e = +/- basis vector t of block i: |e_i . a^i_j| = |a^i_j[t]|."""
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 6)
+    dp = d // L
+    for i in range(L):
+        for t in range(dp):
+            for sgn in (1.0, -1.0):
+                xu = np.zeros(d, np.float32)
+                xu[i * dp + t] = sgn
+                codes, scal, _ = O.edge_record(np.zeros(d, np.float32), xu, L, m, A, B)
+                col = sgn * A[i, :, t].astype(np.float64)
+                j = int(np.argmax(np.abs(col)))
+                assert codes[1 + i] == j + (m if col[j] < 0 else 0)
+                # blocks other than i are zero: code (+, first direction)
+                for i2 in range(L):
+                    if i2 != i:
+                        assert codes[1 + i2] == 0
+                # one nonzero block: e is its own regular part
+                assert scal[1] == pytest.approx(1.0) and scal[2] == pytest.approx(0.0, abs=1e-12)
+                assert codes[0] == 0
+
+
+def test_zero_edge_record():
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 7)
+    x = np.random.default_rng(1).standard_normal(d).astype(np.float32)
+    codes, scal, _ = O.edge_record(x, x, L, m, A, B)
+    assert np.all(codes == 0) and scal[0] == 0 and scal[1] == 1 and scal[2] == 0
+
+
+def test_single_subspace_is_rceos():
+    """L = 1: w_reg = 1, w_res = 0, and the code is the RCEOs argmax over the
+    full-space directions."""
+    rng = np.random.default_rng(3)
+    m, d = 16, 32
+    A, B = W.make_directions(1, m, d, 8)
+    for _ in range(50):
+        xv = rng.standard_normal(d).astype(np.float32)
+        xu = rng.standard_normal(d).astype(np.float32)
+        codes, scal, margin = O.edge_record(xv, xu, 1, m, A, B)
+        assert scal[1] == pytest.approx(1.0, abs=1e-12) and scal[2] == pytest.approx(0.0, abs=1e-7)
+        if margin < 1e-5:
+            continue
+        p = A[0].astype(np.float64) @ (xu.astype(np.float64) - xv)
+        j = int(np.argmax(np.abs(p)))
+        assert codes[1] == j + (m if p[j] < 0 else 0)
+
+
+def test_isotropic_wreg_mean_matches_gamma_form():
+    rng = np.random.default_rng(21)
+    L, m, d = 8, 16, 128
+    A, B = W.make_directions(L, m, d, 9)
+    N = 6000
+    w = np.empty(N)
+    z = np.zeros(d, np.float32)
+    for t in range(N):
+        _, scal, _ = O.edge_record(z, rng.standard_normal(d).astype(np.float32), L, m, A, B)
+        w[t] = scal[1]
+    se = w.std() / math.sqrt(N)
+    assert abs(w.mean() - O.ewreg_exact(L, d)) < 4 * se
+    assert w.mean() >= golden()["wreg_bound_d128_L8"]
+
+
+def test_zero_block_projection_reading():
+    """A zero block: e_reg is the projection on the line of
+    g = [e_i/(sqrt(L)|e_i|)] with a zero component there, so
+    w_reg = sum_i |e_i| / (sqrt(L') |e|), L' = nonzero blocks."""
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 10)
+    rng = np.random.default_rng(4)
+    xu = rng.standard_normal(d).astype(np.float32)
+    xu[8:16] = 0.0
+    codes, scal, _ = O.edge_record(np.zeros(d, np.float32), xu, L, m, A, B)
+    e = xu.astype(np.float64)
+    s = np.linalg.norm(e.reshape(L, -1), axis=1)
+    assert scal[1] == pytest.approx(s.sum() / (math.sqrt(3) * np.linalg.norm(e)), rel=1e-12)
+    assert scal[1] ** 2 + scal[2] ** 2 == pytest.approx(1.0, abs=1e-12)
+    assert codes[2] == 0
+
+
+# ---------------------------------------------------------------------------
+# step (5): projection table
+# ---------------------------------------------------------------------------
+def test_table_of_basis_query_is_direction_entry():
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 11)
+    dp = d // L
+    for k in range(d):
+        q = np.zeros(d, np.float32)
+        q[k] = 3.0  # normalization removes the 3
+        T = O.query_table(q, L, m, A, B)
+        np.testing.assert_allclose(T[0], B[:, k], rtol=0, atol=1e-12)
+        i, t = divmod(k, dp)
+        np.testing.assert_allclose(T[1 + i], A[i, :, t], rtol=0, atol=1e-12)
+        for i2 in range(L):
+            if i2 != i:
+                assert np.all(T[1 + i2] == 0)
+
+
+# ---------------------------------------------------------------------------
+# P7: the projection estimate has the closed-form mean and variance
+# ---------------------------------------------------------------------------
+def _H_moments(e, q, L, m, wreg, wres):
+    Mm, Mv = O.max_abs_normal_moments(m)
+    qn = q / np.linalg.norm(q)
+    eb, qb = e.reshape(L, -1), qn.reshape(L, -1)
+    mu1 = var1 = 0.0
+    for i in range(L):
+        nq = np.linalg.norm(qb[i])
+        c = eb[i] @ qb[i] / (np.linalg.norm(eb[i]) * nq)
+        mu1 += nq * c * Mm
+        var1 += nq * nq * (c * c * Mv + 1 - c * c)
+    s = np.linalg.norm(eb, axis=1)
+    eres = (eb - (s.sum() / L) * eb / s[:, None]).reshape(-1)
+    c0 = eres @ qn / np.linalg.norm(eres)
+    mu = wreg * mu1 + math.sqrt(L) * wres * c0 * Mm
+    var = wreg ** 2 * var1 + L * wres ** 2 * (c0 * c0 * Mv + 1 - c0 * c0)
+    return mu, var
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_projection_estimate_moments(metric):
+    """Over random direction draws, H of the test has the mean and variance
+    the extreme-value argument gives (per block: |q'_i| cos(theta_i) M_m plus
+    an independent N(0, |q'_i|^2 sin^2) term; M_m = max of m |N(0,1)|)."""
+    rng = np.random.default_rng(31)
+    L, m, d = 4, 16, 32
+    xv = rng.standard_normal(d).astype(np.float32)
+    xu = (xv + rng.standard_normal(d) * np.repeat([0.6, 1.0, 1.4, 0.8], d // L)).astype(np.float32)
+    q = (xv + 0.8 * (xu - xv) + 0.9 * rng.standard_normal(d)).astype(np.float32)
+    # choose p so that 0 < A < 1 for this edge: p at the distance that puts A mid-range
+    N = 5000
+    Hs = []
+    wreg = wres = None
+    for t in range(N):
+        A, B = W.make_directions(L, m, d, 10_000 + t)
+        codes, scal, _ = O.edge_record(xv, xu, L, m, A, B)
+        T = O.query_table(q, L, m, A, B)
+        lk = lambda i, c: (-1.0 if c >= m else 1.0) * T[i, c % m]
+        H1 = sum(lk(i, codes[i]) for i in range(1, L + 1))
+        H2 = lk(0, codes[0])
+        wreg, wres = scal[1], scal[2]
+        Hs.append(wreg * H1 + math.sqrt(L) * wres * H2)
+    Hs = np.array(Hs)
+    e = xu.astype(np.float64) - xv
+    mu, var = _H_moments(e, q.astype(np.float64), L, m, wreg, wres)
+    assert abs(Hs.mean() - mu) < 4 * math.sqrt(var / N)
+    assert Hs.var() == pytest.approx(var, rel=0.08)
+
+
+def test_routing_test_H_matches_table_sum():
+    """The H reported by the routing test is w_reg H1 + sqrt(L) w_res H2 built
+    from the same codes and table (ties test_edge to the P7 pin)."""
+    rng = np.random.default_rng(8)
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 12)
+    n_h = 0
+    for _ in range(300):
+        xv, q = rng.standard_normal((2, d)).astype(np.float32)
+        xu = (xv + 0.5 * rng.standard_normal(d)).astype(np.float32)
+        xp = (q + rng.standard_normal(d) * rng.uniform(0.5, 2)).astype(np.float32)
+        ok, Ar, H, T, kind = O.test_edge(xv, xu, xp, q, L, m, A, B, W.L2, 0.1)
+        if kind != 3:
+            continue
+        codes, scal, _ = O.edge_record(xv, xu, L, m, A, B)
+        tab = O.query_table(q, L, m, A, B)
+        lk = lambda i, c: (-1.0 if c >= m else 1.0) * tab[i, c % m]
+        H_ref = scal[1] * sum(lk(i, codes[i]) for i in range(1, L + 1)) + math.sqrt(L) * scal[2] * lk(0, codes[0])
+        assert H == pytest.approx(H_ref, rel=1e-12, abs=1e-12)
+        assert T == pytest.approx(O.threshold(Ar, scal[1], scal[2], L, m, 0.1), rel=1e-12)
+        assert ok == (H >= T)
+        n_h += 1
+    assert n_h > 50
+
+
+# ---------------------------------------------------------------------------
+# P5: A_r algebra
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_A_r_literal_equals_distance_form_and_is_exact_cosine_threshold(metric):
+    rng = np.random.default_rng(13 + metric)
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 13)
+    n_checked = 0
+    for _ in range(2000):
+        xv, xu, xp, q = rng.standard_normal((4, d)) * rng.uniform(0.3, 3, size=(4, 1))
+        if metric == W.ANGULAR:
+            xv, xu, xp = [x / np.linalg.norm(x) for x in (xv, xu, xp)]
+        xv, xu, xp, q = [x.astype(np.float32).astype(np.float64) for x in (xv, xu, xp, q)]
+        ok, Ar, H, T, kind = O.test_edge(xv, xu, xp, q, L, m, A, B, metric, 0.1)
+        e = xu - xv
+        if metric == W.L2:
+            dist = lambda x: ((x - q) ** 2).sum()
+            num = 0.5 * (xu @ xu - xv @ xv) + 0.5 * (dist(xv) - dist(xp))
+            Aref = num / (np.linalg.norm(q) * np.linalg.norm(e))
+        else:
+            dist = lambda x: 1 - x @ q / np.linalg.norm(q)
+            Aref = (dist(xv) - dist(xp)) / np.linalg.norm(e)
+        assert Ar == pytest.approx(Aref, rel=1e-10, abs=1e-12)
+        cos = e @ q / (np.linalg.norm(e) * np.linalg.norm(q))
+        du, delta = dist(xu), dist(xp)
+        if abs(du - delta) > 1e-9 * abs(delta) and abs(cos - Ar) > 1e-9:
+            assert (du < delta) == (cos > Ar)
+            if Ar >= 1:
+                assert du >= delta and not ok and kind == 1
+            if Ar <= 0:
+                assert ok and kind == 2
+            n_checked += 1
+    assert n_checked > 1500
+
+
+def test_zero_length_edge_decided_by_sign():
+    L, m, d = 4, 16, 32
+    A, B = W.make_directions(L, m, d, 14)
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        xv, xp, q = rng.standard_normal((3, d)).astype(np.float32)
+        ok, Ar, H, T, kind = O.test_edge(xv, xv, xp, q, L, m, A, B, W.L2, 0.1)
+        dv = ((xv.astype(np.float64) - q) ** 2).sum()
+        dp = ((xp.astype(np.float64) - q) ** 2).sum()
+        assert kind == 0 and ok == (dv < dp)
+
+
+# ---------------------------------------------------------------------------
+# P1 / P2 / P3 / P4: search
+# ---------------------------------------------------------------------------
+def _tiny(n=300, d=16, R=8, seed=0, metric=W.L2):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    q = rng.standard_normal((20, d)).astype(np.float32)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    g, entry = W.build_graph(x, R, 2 * R)
+    return x, q, g, entry
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_brute_force_matches_cdist(metric):
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((500, 12))
+    q = rng.standard_normal((30, 12))
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)  # the angular metric takes unit base vectors
+    ids, dd = O.brute_force(x, q, 7, metric)
+    if metric == W.L2:
+        full = cdist(q, x, "sqeuclidean")
+    else:
+        full = cdist(q, x, "cosine")  # 1 - cos
+    for i in range(len(q)):
+        order = sorted(range(len(x)), key=lambda j: (full[i, j], j))[:7]
+        assert list(ids[i]) == order
+        np.testing.assert_allclose(dd[i], full[i, order], rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("mode", [O.MODE_EXHAUSTIVE, O.MODE_PEOS])
+def test_search_with_list_larger_than_n_is_exact_knn(metric, mode):
+    """With ef >= n the list never fills, no test runs, every reachable node
+    is visited: the search returns exact k-NN (the graph is connected)."""
+    x, q, g, entry = _tiny(metric=metric)
+    L, m = 4, 16
+    A, B = W.make_directions(L, m, x.shape[1], 15)
+    out = O.search(x, g, entry, q, 10, x.shape[0], L, m, A, B, metric, 0.1, mode=mode)
+    ids, dd = O.brute_force(x, q, 10, metric)
+    assert np.array_equal(out["ids"], ids)
+    np.testing.assert_allclose(out["dist"], dd, rtol=1e-12, atol=1e-12)
+    c = out["counters"]
+    assert np.all(c[:, O.COUNTERS.index("ndist")] == x.shape[0])
+    assert np.all(c[:, O.COUNTERS.index("expansions")] == x.shape[0])
+    assert np.all(c[:, O.COUNTERS.index("edges")] == (g >= 0).sum())
+    assert np.all(c[:, O.COUNTERS.index("tests")] == 0)
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_vanishing_eps_reproduces_exhaustive_search(metric):
+    """eps -> 0+ leaves only the exact prune A_r >= 1 (which implies
+    dist(u) >= delta): same ids and distances as exhaustive search, fewer
+    distance computations."""
+    w = W.TINY.with_sizes(n=1000, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    else:
+        # put the origin next to the first query: the l2 form of A_r divides
+        # by |q|, so a short query makes the exact prune A_r >= 1 fire
+        o = q[0] - 0.01
+        x, q = (x - o).astype(np.float32), (q - o).astype(np.float32)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    ex = O.search(x, g, entry, q, 10, 16, w.L, w.m, A, B, metric, 0.1, mode=O.MODE_EXHAUSTIVE)
+    pe = O.search(x, g, entry, q, 10, 16, w.L, w.m, A, B, metric, 1e-300, mode=O.MODE_PEOS)
+    assert np.array_equal(ex["ids"], pe["ids"])
+    np.testing.assert_array_equal(ex["dist"], pe["dist"])
+    ci = O.COUNTERS.index
+    assert np.all(pe["counters"][:, ci("ndist")] <= ex["counters"][:, ci("ndist")])
+    assert pe["counters"][:, ci("test_ge1")].sum() > 0
+    # every H-vs-T test passes when the quantile goes to -infinity (no
+    # zero-length edges occur in this continuous data)
+    c = pe["counters"]
+    assert np.all(c[:, ci("test_zero")] == 0)
+    assert np.all(c[:, ci("passes")] == c[:, ci("test_h")] + c[:, ci("test_le0")])
+
+
+def _two_heap_search(x, g, entry, q, k, ef, L, m, A, B, metric, eps, mode):
+    """HNSW-style formulation: candidate min-heap C, result max-heap W; same
+    delta snapshot per expansion and the same insertion rule."""
+    x64 = x.astype(np.float64)
+    q64 = q.astype(np.float64)
+
+    def dist(i):
+        if metric == W.L2:
+            return float(((x64[i] - q64) ** 2).sum())
+        return float(1 - x64[i] @ q64 / np.linalg.norm(q64))
+
+    ef = max(ef, k)
+    d0 = dist(entry)
+    C = [(d0, entry)]
+    Wh = [(-d0, -entry)]  # max-heap on (dist, id)
+    visited = {entry}
+    expansions, ndist = 0, 1
+    while C:
+        c = heapq.heappop(C)
+        worst = (-Wh[0][0], -Wh[0][1])
+        if len(Wh) >= ef and c > worst:
+            break
+        expansions += 1
+        full = len(Wh) == ef
+        delta = worst[0] if full else math.inf
+        p = worst[1]
+        S = []
+        for u in g[c[1]]:
+            if u < 0 or u in visited:
+                continue
+            ok = True
+            if full and mode == O.MODE_PEOS:
+                ok = O.test_edge(x[c[1]], x[u], x[p], q, L, m, A, B, metric, eps)[0]
+            if not ok:
+                continue
+            visited.add(u)
+            ndist += 1
+            du = dist(u)
+            if not full or du < delta:
+                S.append((du, int(u)))
+        for s in S:
+            heapq.heappush(C, s)
+            heapq.heappush(Wh, (-s[0], -s[1]))
+            if len(Wh) > ef:
+                heapq.heappop(Wh)
+    res = sorted((-a, -b) for a, b in Wh)[:k]
+    return [r[1] for r in res], [r[0] for r in res], expansions, ndist
+
+
+@pytest.mark.parametrize("mode", [O.MODE_EXHAUSTIVE, O.MODE_PEOS])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_single_list_with_pool_ef_equals_two_heap(mode, seed):
+    x, q, g, entry = _tiny(n=250, d=8, R=6, seed=seed)
+    L, m = 2, 8
+    A, B = W.make_directions(L, m, 8, 16 + seed)
+    ef = [6, 10, 20][seed]
+    out = O.search(x, g, entry, q, 5, ef, L, m, A, B, W.L2, 0.2, mode=mode, pool=ef)
+    for i in range(len(q)):
+        ids, dd, nexp, nd = _two_heap_search(x, g, entry, q[i], 5, ef, L, m, A, B, W.L2, 0.2, mode)
+        assert list(out["ids"][i][:len(ids)]) == ids
+        np.testing.assert_allclose(out["dist"][i][:len(ids)], dd, rtol=1e-12)
+        assert out["counters"][i, O.COUNTERS.index("expansions")] == nexp
+        assert out["counters"][i, O.COUNTERS.index("ndist")] == nd
+
+
+def test_padding_and_k_above_ef():
+    """k > ef uses ef := k; fewer reachable nodes than k pads with (-1, inf)."""
+    x = np.random.default_rng(0).standard_normal((6, 8)).astype(np.float32)
+    g = np.full((6, 4), -1, np.int32)
+    g[0, :2] = [1, 2]
+    g[1, 0] = 0
+    q = np.ones((1, 8), np.float32)
+    out = O.search(x, g, 0, q, 5, 2, 2, 8, np.zeros((2, 8, 4), np.float32),
+                   np.zeros((8, 8), np.float32), W.L2, 0.1, mode=O.MODE_EXHAUSTIVE)
+    assert sorted(out["ids"][0][:3]) == [0, 1, 2]
+    assert list(out["ids"][0][3:]) == [-1, -1] and np.all(np.isinf(out["dist"][0][3:]))
+
+
+def test_zero_query_status():
+    x = np.random.default_rng(0).standard_normal((10, 8)).astype(np.float32)
+    g = np.zeros((10, 2), np.int32) - 1
+    out = O.search(x, g, 0, np.zeros((1, 8), np.float32), 1, 4, 2, 8, None, None, W.L2, 0.1)
+    assert out["status"][0] == -1 and out["ids"][0, 0] == -1
+
+
+def _literal_alg1(x, g, entry, q, k, ef, L, m, A, B, metric, eps, mode, pool=None):
+    """Alg. 1 as printed: result list R (best ef so far) and priority queue P
+    holding every pushed node until it is popped; the loop runs until P is
+    empty.  With `pool`, P keeps at most pool - |R| entries that are not in R
+    (the worst are dropped).  Same delta snapshot per expansion."""
+    x64, q64 = x.astype(np.float64), q.astype(np.float64)
+
+    def dist(i):
+        if metric == W.L2:
+            return float(((x64[i] - q64) ** 2).sum())
+        return float(1 - x64[i] @ q64 / np.linalg.norm(q64))
+
+    ef = max(ef, k)
+    Rl = [(dist(entry), entry)]
+    P = [(dist(entry), entry)]
+    visited = {entry}
+    expansions, ndist = 0, 1
+    while P:
+        c = heapq.heappop(P)
+        expansions += 1
+        full = len(Rl) == ef
+        delta, p = (Rl[-1] if full else (math.inf, -1))
+        S = []
+        for u in g[c[1]]:
+            if u < 0 or u in visited:
+                continue
+            ok = True
+            if full and mode == O.MODE_PEOS:
+                ok = O.test_edge(x[c[1]], x[u], x[p], q, L, m, A, B, metric, eps)[0]
+            if not ok:
+                continue
+            visited.add(u)
+            ndist += 1
+            du = dist(u)
+            if not full or du < delta:
+                S.append((du, int(u)))
+        for s_ in S:
+            heapq.heappush(P, s_)
+        Rl = sorted(Rl + S)[:ef]
+        if pool is not None:
+            rs = set(Rl)
+            outside = sorted(e for e in P if e not in rs)
+            keep_out = max(0, pool - len(Rl))
+            P = [e for e in P if e in rs] + outside[:keep_out]
+            heapq.heapify(P)
+    return [r[1] for r in Rl[:k]], [r[0] for r in Rl[:k]], expansions, ndist
+
+
+@pytest.mark.parametrize("mode", [O.MODE_EXHAUSTIVE, O.MODE_PEOS])
+@pytest.mark.parametrize("pool_mul", [0, 2, 3])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_single_list_equals_literal_alg1(mode, pool_mul, seed):
+    """The one-list form with an unbounded pool is Alg. 1 as printed (R plus
+    a priority queue emptied to the end); a bounded pool matches Alg. 1 whose
+    queue keeps only the best pool - |R| nodes outside R."""
+    x, q, g, entry = _tiny(n=250, d=8, R=6, seed=10 + seed)
+    L, m = 2, 8
+    A, B = W.make_directions(L, m, 8, 40 + seed)
+    ef = [6, 12][seed]
+    pool = pool_mul * ef
+    out = O.search(x, g, entry, q, 5, ef, L, m, A, B, W.L2, 0.2, mode=mode, pool=pool)
+    for i in range(len(q)):
+        ids, dd, nexp, nd = _literal_alg1(x, g, entry, q[i], 5, ef, L, m, A, B, W.L2, 0.2, mode,
+                                          pool=pool if pool else None)
+        assert list(out["ids"][i][:len(ids)]) == ids
+        np.testing.assert_allclose(out["dist"][i][:len(ids)], dd, rtol=1e-12)
+        assert out["counters"][i, O.COUNTERS.index("expansions")] == nexp
+        assert out["counters"][i, O.COUNTERS.index("ndist")] == nd
+
+
+@pytest.mark.parametrize("mode", [O.MODE_EXHAUSTIVE, O.MODE_PEOS])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_integer_data_ties_follow_strict_insertion(mode, pool_mul):
+    """Small-integer data makes equal distances common: ties are broken by
+    id, and a neighbour at exactly delta is not inserted (strict <)."""
+    rng = np.random.default_rng(77)
+    x = rng.integers(0, 4, size=(300, 8)).astype(np.float32)
+    q = rng.integers(0, 4, size=(25, 8)).astype(np.float32)
+    g, entry = W.build_graph(x, 6, 12)
+    L, m = 2, 8
+    A, B = W.make_directions(L, m, 8, 99)
+    ef = 8
+    out = O.search(x, g, entry, q, 5, ef, L, m, A, B, W.L2, 0.2, mode=mode, pool=pool_mul * ef)
+    ties = 0
+    for i in range(len(q)):
+        ids, dd, nexp, nd = _literal_alg1(x, g, entry, q[i], 5, ef, L, m, A, B, W.L2, 0.2, mode,
+                                          pool=pool_mul * ef if pool_mul else None)
+        assert list(out["ids"][i][:len(ids)]) == ids
+        assert out["counters"][i, O.COUNTERS.index("expansions")] == nexp
+        assert out["counters"][i, O.COUNTERS.index("ndist")] == nd
+        ties += len(dd) - len(set(dd))
+    assert ties > 0
