@@ -1,0 +1,230 @@
+/*
+ * peos.h -- C ABI of the PEOs-routed graph search library for MI355X (gfx950).
+ *
+ * The library implements the search of Lu, Xiao and Ishikawa, "Probabilistic
+ * Routing for Graph-Based Approximate Nearest Neighbor Search" (ICML 2024):
+ * best-first search over a fixed proximity graph (Alg. 1) in which every
+ * unvisited neighbour of the expanded node is first screened by the PEOs
+ * routing test (Sec. 4.2, steps (1)-(6); Alg. 2), and only neighbours that
+ * pass get an exact distance.
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE pointers (hipMalloc'ed or torch CUDA
+ *     tensors) unless marked "host".  The caller owns all memory; the library
+ *     never allocates device memory and keeps no pointer after a call returns,
+ *     except that a peos_index records the base, graph and index_mem pointers
+ *     given to peos_build_tables, which must stay valid until peos_free.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Work is enqueued asynchronously on it unless stated otherwise.
+ *   - Return value: PEOS_OK (0) or a negative PEOS_E* code.  No exception
+ *     crosses the ABI.  peos_last_error() returns a thread-local message for
+ *     the last failing call on this thread.
+ *   - Row-major layouts throughout.
+ */
+#ifndef PEOS_H
+#define PEOS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define PEOS_OK 0
+#define PEOS_EINVAL (-1)   /* an argument is out of range or inconsistent      */
+#define PEOS_ENOSPACE (-2) /* a caller buffer is smaller than required          */
+#define PEOS_EHIP (-3)     /* a HIP runtime call failed                         */
+#define PEOS_EGRAPH (-4)   /* graph row with an out-of-range id, self loop or
+                              repeated neighbour                               */
+#define PEOS_EDEVICE (-5)  /* no gfx950 device is current                       */
+
+/* metrics.  L2: squared Euclidean distance |x - q|^2.  ANGULAR: 1 - x.q/|q|,
+ * the cosine distance when base vectors have unit norm (Sec. 3 of the paper
+ * reduces both to inner products; the test uses the MIPS numerator of the
+ * "Extension to MIPS" appendix, which is exact for this distance). */
+#define PEOS_METRIC_L2 0
+#define PEOS_METRIC_ANGULAR 1
+
+/* search modes.  PEOS: neighbours are screened by the routing test.
+ * EXHAUSTIVE: the test is off (every unvisited neighbour gets a distance),
+ * i.e. Alg. 1 with RoutingTest returning true. */
+#define PEOS_MODE_PEOS 0
+#define PEOS_MODE_EXHAUSTIVE 1
+
+/* per-query status bits written to stats[.. + PEOS_STAT_STATUS] */
+#define PEOS_STATUS_ZERO_QUERY 1    /* |q| = 0 or not finite: outputs padded  */
+#define PEOS_STATUS_POOL_FULL 2     /* the candidate list reached the kernel's
+                                       capacity with pool = 0 (see peos_search) */
+#define PEOS_STATUS_VISITED_SPILL 4 /* visited set moved from LDS to HBM       */
+
+/* per-query statistics: PEOS_NSTATS int32 per query, in this order */
+#define PEOS_STAT_EXPANSIONS 0   /* nodes popped and expanded                 */
+#define PEOS_STAT_EDGES 1        /* valid neighbour ids enumerated            */
+#define PEOS_STAT_VISITED_SKIPS 2/* neighbours skipped as already visited     */
+#define PEOS_STAT_TESTS 3        /* routing tests run                          */
+#define PEOS_STAT_TEST_GE1 4     /* tests decided by A_r >= 1 (fail)           */
+#define PEOS_STAT_TEST_LE0 5     /* tests decided by A_r <= 0 (pass)           */
+#define PEOS_STAT_TEST_H 6       /* tests decided by H >= T_r                  */
+#define PEOS_STAT_TEST_ZERO 7    /* tests on zero-length edges                 */
+#define PEOS_STAT_PASSES 8       /* tests passed                               */
+#define PEOS_STAT_NDIST 9        /* exact distances computed (entry included)  */
+#define PEOS_STAT_INSERTED 10    /* distances that entered the candidate list  */
+#define PEOS_STAT_STATUS 11      /* PEOS_STATUS_* bits                         */
+#define PEOS_NSTATS 12
+
+typedef struct peos_index peos_index;
+
+/* Byte layout of the per-node edge records inside index_mem (for tests and
+ * tools; the search needs nothing but the handle).  Record of node v starts at
+ * v * node_stride.  Codes: (L+1) rows of R bytes, row i at codes_offset +
+ * i*R (row 0 = residual code e[0], rows 1..L = subspace codes e[i]), byte j =
+ * edge to graph[v*R + j].  A code byte c encodes the index j* = c mod m of
+ * the extreme projection vector and its sign (negative iff c >= m).
+ * Scalars: 4 rows of R floats at scalars_offset + s*R*4, s = 0: g_e =
+ * (|u|^2 - |v|^2)/2 (zero for ANGULAR), 1: |e|, 2: w_reg, 3: sqrt(L)*w_res. */
+typedef struct {
+    int64_t n;
+    int32_t d, R, L, m, metric, flags, entry;
+    int64_t node_stride;    /* bytes */
+    int64_t codes_offset;   /* bytes, within a record */
+    int64_t scalars_offset; /* bytes, within a record */
+} peos_layout;
+
+/*
+ * peos_index_bytes -- size the caller-owned index memory.
+ * Implements: storage of PEOS steps (1)-(3) results per edge (Sec. 4.3,
+ * "Implementation of PEOs": codes and scalars are precomputed at build time).
+ * n, d, R, L, m: base size, dimension, max out-degree, subspaces, projection
+ * vectors per subspace.  flags: 0 (reserved for storage variants).
+ * Outputs (host pointers): index_bytes = bytes of index_mem;
+ * build_ws_bytes = bytes of the build workspace.  Pure, no device work.
+ * Errors: PEOS_EINVAL if n < 1, d < 1, R < 1, L < 1, d % L != 0, d/L % 4 != 0,
+ * m < 16, m % 16 != 0, 2*m > 256, or a null output pointer.
+ */
+int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int32_t flags,
+                     size_t* index_bytes, size_t* build_ws_bytes);
+
+/*
+ * peos_build_tables -- PEOs steps (1)-(3) for every edge of the graph
+ * (Sec. 4.2: orthogonal decomposition e = e_reg + e_res of e = u - v, the
+ * extreme-value codes e[0..L] against the projection vectors, and the weights
+ * w_reg, w_res), plus the per-edge scalars the test of step (6) needs.
+ *   base    n x d float, the vectors (ANGULAR expects unit-norm rows).
+ *   graph   n x R int32 neighbour ids, -1 = no edge; ids in [0, n), no self
+ *           loops and no repeated id within a row.
+ *   entry   entry node v0 of the search (Alg. 1), in [0, n).
+ *   dirs_a  L x m x (d/L) float: vectors a^i_j of subspace i (step (2)).
+ *   dirs_b  m x d float: full-space vectors b_j (step (2)).
+ *   metric  PEOS_METRIC_*.
+ *   index_mem / index_bytes  caller buffer sized by peos_index_bytes.
+ *   ws / ws_bytes            build workspace (peos_index_bytes).
+ *   out     (host) receives a handle; free it with peos_free.
+ * The handle records base, graph, dirs_a, dirs_b and index_mem (not copied).
+ * Synchronous: returns after the build finished on `stream` (it reads back a
+ * graph-validation flag).  Errors: PEOS_EINVAL, PEOS_ENOSPACE, PEOS_EGRAPH
+ * (the index is not created), PEOS_EHIP, PEOS_EDEVICE.
+ */
+int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* graph, int32_t R,
+                      int32_t entry, int32_t L, int32_t m, const float* dirs_a,
+                      const float* dirs_b, int32_t metric, int32_t flags, void* index_mem,
+                      size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
+                      peos_index** out);
+
+/* Fill *out (host) with the record layout of an index.  Errors: PEOS_EINVAL. */
+int peos_index_layout(const peos_index* index, peos_layout* out);
+
+/* Release a handle (host memory only; device buffers belong to the caller). */
+void peos_free(peos_index* index);
+
+/*
+ * peos_query_tables -- PEOs step (5): the per-query projection table, built
+ * once per query (Alg. 2, "only once and used throughout the search").
+ *   queries  nq x d float.
+ *   tables   out, nq x (L+1) x m float: row 0 = q'.b_j, row i = q'_i . a^i_j
+ *            with q' = q/|q| and q'_i its i-th block (not renormalized).
+ *   qnorms   out, nq float: |q| (0 for a zero query, whose table is 0).
+ * Runs the dense query-by-direction product on the matrix cores.
+ * Errors: PEOS_EINVAL (null pointer with nq > 0, nq < 0), PEOS_EHIP.
+ */
+int peos_query_tables(const peos_index* index, const float* queries, int64_t nq, float* tables,
+                      float* qnorms, void* stream);
+
+/*
+ * peos_search_ws_bytes -- workspace of peos_search / peos_search_tables for
+ * nq queries with list sizes up to efmax and candidate-pool capacity `pool`
+ * (as in peos_search).  Output *ws_bytes (host).  Errors: PEOS_EINVAL.
+ */
+int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int32_t pool,
+                         size_t* ws_bytes);
+
+/*
+ * peos_search_tables -- Alg. 1 with the PEOs test (steps (4) and (6), Alg. 2)
+ * for nq queries whose tables come from peos_query_tables.
+ *   queries, tables, qnorms  as produced/consumed by peos_query_tables.
+ *   k, ef    per-query int32 arrays (device), or NULL to use k_all / ef_all
+ *            for every query.  The effective list size is max(ef, k) (efs >= K
+ *            in Sec. 3).  1 <= k <= kstride, ef <= 4096.
+ *   kstride  row stride (entries) of ids/dists.
+ *   pool     capacity of the candidate list (R plus the queue P of Alg. 1,
+ *            held as one list sorted by (distance, id)).  pool = 0: the queue
+ *            is unbounded as printed in Alg. 1, up to the kernel's capacity
+ *            (a query that reaches it gets PEOS_STATUS_POOL_FULL and from then
+ *            on behaves as pool = that capacity); pool <= max(ef, k): the HNSW
+ *            stopping rule (stop when R holds no unexpanded node).
+ *   eps      error bound epsilon of probabilistic routing (Def. 3.2), in
+ *            (0, 0.5]; ignored by EXHAUSTIVE.
+ *   mode     PEOS_MODE_*.
+ *   ids      out, nq x kstride int64: first k results ordered by (distance,
+ *            id), then -1.
+ *   dists    out, nq x kstride float: their distances (squared l2, or
+ *            1 - x.q/|q|), then +inf.
+ *   stats    out, nq x PEOS_NSTATS int32, or NULL.
+ *   ws       workspace of peos_search_ws_bytes(index, nq, efmax, pool).
+ * Search semantics (where the paper leaves a choice): the entry node is
+ * distance-computed and visited first; delta is read once per expansion;
+ * a neighbour is visited only once its distance is computed; a survivor
+ * enters the list if R was not full or its distance is < delta.
+ * Errors: PEOS_EINVAL, PEOS_ENOSPACE, PEOS_EHIP.
+ */
+int peos_search_tables(const peos_index* index, const float* queries, const float* tables,
+                       const float* qnorms, int64_t nq, const int32_t* k, const int32_t* ef,
+                       int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool, float eps,
+                       int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/*
+ * peos_search -- peos_query_tables followed by peos_search_tables, with the
+ * tables and norms kept in the workspace.  Arguments as above; ws must hold
+ * peos_search_ws_bytes(index, nq, efmax, pool) bytes.
+ */
+int peos_search(const peos_index* index, const float* queries, int64_t nq, const int32_t* k,
+                const int32_t* ef, int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool,
+                float eps, int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
+                size_t ws_bytes, void* stream);
+
+/*
+ * peos_set_search_tuning -- override the search kernel's launch plan for all
+ * later calls in this process (0 keeps the automatic choice):
+ *   hash_log2  visited-hash capacity 2^hash_log2 entries in LDS, 6..14; a
+ *              query that visits more than 3/4 of it moves its visited set to
+ *              a bitmap in the workspace (PEOS_STATUS_VISITED_SPILL);
+ *   listcap    candidate-list capacity in LDS (rounded up to a multiple of 64
+ *              and to at least max(pool, ef)); with pool = 0 it is the
+ *              kernel capacity that PEOS_STATUS_POOL_FULL refers to;
+ *   slots      resident waves of the persistent grid, 1..4096.
+ * Results do not depend on the tuning except through the pool capacity.
+ * Errors: PEOS_EINVAL for values out of range.
+ */
+int peos_set_search_tuning(int32_t hash_log2, int32_t listcap, int32_t slots);
+
+/* Message for a return code, and the thread-local message of the last error. */
+const char* peos_strerror(int code);
+const char* peos_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PEOS_H */

@@ -1,0 +1,218 @@
+"""Python binding of libpeos (include/peos.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and takes
+torch CUDA tensors (device memory and streams come from PyTorch); all the work
+runs in the HIP kernels of libpeos.so.  There is no fallback: if the library
+is missing or the device is not gfx950 the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpeos.so")
+
+PEOS_OK = 0
+PEOS_METRIC_L2 = 0
+PEOS_METRIC_ANGULAR = 1
+PEOS_MODE_PEOS = 0
+PEOS_MODE_EXHAUSTIVE = 1
+PEOS_NSTATS = 12
+STATS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0", "test_h",
+         "test_zero", "passes", "ndist", "inserted", "status")
+PEOS_STATUS_ZERO_QUERY = 1
+PEOS_STATUS_POOL_FULL = 2
+PEOS_STATUS_VISITED_SPILL = 4
+
+
+class PeosError(RuntimeError):
+    def __init__(self, fn, code, msg):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+class peos_layout(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("d", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("L", ctypes.c_int32), ("m", ctypes.c_int32), ("metric", ctypes.c_int32),
+                ("flags", ctypes.c_int32), ("entry", ctypes.c_int32),
+                ("node_stride", ctypes.c_int64), ("codes_offset", ctypes.c_int64),
+                ("scalars_offset", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpeos.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "python -m paper_2402_11354_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P, i64, i32, sz, f32 = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_size_t,
+                                ctypes.c_float)
+        Psz = ctypes.POINTER(ctypes.c_size_t)
+        L.peos_index_bytes.argtypes = [i64, i32, i32, i32, i32, i32, Psz, Psz]
+        L.peos_build_tables.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, i32, P, sz,
+                                        P, sz, P, ctypes.POINTER(P)]
+        L.peos_index_layout.argtypes = [P, ctypes.POINTER(peos_layout)]
+        L.peos_free.argtypes = [P]
+        L.peos_free.restype = None
+        L.peos_query_tables.argtypes = [P, P, i64, P, P, P]
+        L.peos_search_ws_bytes.argtypes = [P, i64, i32, i32, Psz]
+        L.peos_search_tables.argtypes = [P, P, P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P,
+                                         P, P, sz, P]
+        L.peos_search.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P, sz, P]
+        L.peos_set_search_tuning.argtypes = [i32, i32, i32]
+        L.peos_strerror.argtypes = [i32]
+        L.peos_strerror.restype = ctypes.c_char_p
+        L.peos_last_error.restype = ctypes.c_char_p
+        for name in ("peos_index_bytes", "peos_build_tables", "peos_index_layout",
+                     "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
+                     "peos_search", "peos_set_search_tuning"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(fn, rc):
+    if rc != PEOS_OK:
+        raise PeosError(fn, rc, lib().peos_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def peos_index_bytes(n, d, R, L, m, flags=0):
+    """(index_bytes, build_ws_bytes)."""
+    ib, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check("peos_index_bytes", lib().peos_index_bytes(n, d, R, L, m, flags, ctypes.byref(ib),
+                                                      ctypes.byref(wb)))
+    return ib.value, wb.value
+
+
+class PeosIndex:
+    """A built index: the C handle plus the device tensors it points into
+    (kept alive here)."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def layout(self):
+        return peos_index_layout(self)
+
+    def close(self):
+        if self.handle:
+            lib().peos_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def peos_build_tables(base, graph, entry, L, m, dirs_a, dirs_b, metric, flags=0, stream=None):
+    """Build the edge records.  base (n, d) float32, graph (n, R) int32,
+    dirs_a (L, m, d/L) float32, dirs_b (m, d) float32, all on the device."""
+    n, d = base.shape
+    R = graph.shape[1]
+    ib, wb = peos_index_bytes(n, d, R, L, m, flags)
+    mem = torch.empty(ib, dtype=torch.uint8, device=base.device)
+    ws = torch.empty(wb, dtype=torch.uint8, device=base.device)
+    h = ctypes.c_void_p()
+    _check("peos_build_tables",
+           lib().peos_build_tables(_ptr(base), n, d, _ptr(graph), R, int(entry), L, m,
+                                   _ptr(dirs_a), _ptr(dirs_b), metric, flags, _ptr(mem), ib,
+                                   _ptr(ws), wb, _stream(stream), ctypes.byref(h)))
+    return PeosIndex(h, (base, graph, dirs_a, dirs_b, mem))
+
+
+def peos_index_layout(index):
+    out = peos_layout()
+    _check("peos_index_layout", lib().peos_index_layout(index.handle, ctypes.byref(out)))
+    return out
+
+
+def peos_query_tables(index, queries, tables, qnorms, stream=None):
+    _check("peos_query_tables",
+           lib().peos_query_tables(index.handle, _ptr(queries), queries.shape[0], _ptr(tables),
+                                   _ptr(qnorms), _stream(stream)))
+
+
+def peos_search_ws_bytes(index, nq, efmax, pool=0):
+    out = ctypes.c_size_t()
+    _check("peos_search_ws_bytes",
+           lib().peos_search_ws_bytes(index.handle, nq, efmax, pool, ctypes.byref(out)))
+    return out.value
+
+
+def peos_search_tables(index, queries, tables, qnorms, k, ef, kstride, pool, eps, mode, ids,
+                       dists, stats, ws, k_all=None, ef_all=None, stream=None):
+    """k, ef: int or per-query int32 device tensors (then k_all / ef_all are
+    their upper bounds)."""
+    kt = k if torch.is_tensor(k) else None
+    et = ef if torch.is_tensor(ef) else None
+    ka = int(k_all if k_all is not None else (k if kt is None else int(kt.max())))
+    ea = int(ef_all if ef_all is not None else (ef if et is None else int(et.max())))
+    _check("peos_search_tables",
+           lib().peos_search_tables(index.handle, _ptr(queries), _ptr(tables), _ptr(qnorms),
+                                    queries.shape[0], _ptr(kt), _ptr(et), ka, ea, kstride, pool,
+                                    float(eps), mode, _ptr(ids), _ptr(dists), _ptr(stats),
+                                    _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def peos_search(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, stats, ws,
+                k_all=None, ef_all=None, stream=None):
+    kt = k if torch.is_tensor(k) else None
+    et = ef if torch.is_tensor(ef) else None
+    ka = int(k_all if k_all is not None else (k if kt is None else int(kt.max())))
+    ea = int(ef_all if ef_all is not None else (ef if et is None else int(et.max())))
+    _check("peos_search",
+           lib().peos_search(index.handle, _ptr(queries), queries.shape[0], _ptr(kt), _ptr(et),
+                             ka, ea, kstride, pool, float(eps), mode, _ptr(ids), _ptr(dists),
+                             _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def peos_set_search_tuning(hash_log2=0, listcap=0, slots=0):
+    """Override the search launch plan (0 = automatic); see include/peos.h."""
+    _check("peos_set_search_tuning", lib().peos_set_search_tuning(hash_log2, listcap, slots))
+
+
+def search(index, queries, k, ef, eps=0.1, mode=PEOS_MODE_PEOS, pool=0, kstride=None,
+           ws=None, stream=None):
+    """Allocate outputs (and workspace if not given) and run peos_search.
+    Returns (ids int64 (nq, kstride), dists float32, stats int32 (nq, 12))."""
+    nq = queries.shape[0]
+    kmax = int(k if not torch.is_tensor(k) else k.max())
+    efmax = max(int(ef if not torch.is_tensor(ef) else ef.max()), kmax)
+    ks = kstride or kmax
+    dev = queries.device
+    ids = torch.empty((nq, ks), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, ks), dtype=torch.float32, device=dev)
+    stats = torch.empty((nq, PEOS_NSTATS), dtype=torch.int32, device=dev)
+    if ws is None:
+        ws = torch.empty(peos_search_ws_bytes(index, nq, efmax, pool), dtype=torch.uint8,
+                         device=dev)
+    if nq:
+        peos_search(index, queries, k, ef, ks, pool, eps, mode, ids, dists, stats, ws,
+                    k_all=kmax, ef_all=efmax, stream=stream)
+    return ids, dists, stats

@@ -1,0 +1,202 @@
+// PEOs steps (1)-(3) for every edge: one workgroup (one wave) per node v,
+// four edges of v at a time, sixteen lanes per edge.
+//
+// For edge e = x_u - x_v (Sec. 4.2 of the paper):
+//   (1) e = e_reg + e_res with e_reg the orthogonal projection of e on the
+//       direction [e_i / (sqrt(L) |e_i|)]_i (a zero block contributes zero);
+//       w_reg = |e_reg| / |e|, w_res = |e_res| / |e|;
+//   (2) the projection vectors a^i_j, b_j are inputs;
+//   (3) code e[i] = sign * argmax_j |e_i . a^i_j| per subspace, and e[0] the
+//       same over e_res and b_j.
+// The codes are integers decided by floating point, so they are computed in
+// single precision with one fixed operation order, element for element:
+//   e_k = x_u[k] - x_v[k]; s_i = sqrt(fma chain of e_k^2 over block i);
+//   p_ij = fma chain over the block of e_k * a^i_j[k] (ascending, from 0);
+//   j* = first j with the largest |p_ij|, negative sign iff p_ij* < 0;
+//   c = (s_1 + ... + s_L) / L' (L' = nonzero blocks, sequential adds);
+//   e_res_k = fma(-(c / s_i), e_k, e_k); p_0j = fma chain over all k.
+// A code byte is j* + m * [sign < 0].
+#pragma once
+
+#include "peos_device.hpp"
+
+namespace peos {
+
+struct EdgeBuildArgs {
+    const float* base;
+    const int32_t* graph;
+    const float* dirs_a;  // L x m x dp
+    const float* dirs_b;  // m x d
+    uint8_t* rec;         // n x node_stride bytes
+    int32_t* err;         // graph-validation flag (0 = ok)
+    int64_t n;
+    int64_t node_stride, codes_off, scal_off;
+    int d, R, L, m, metric;
+};
+
+// LDS: xv[d] | e[4][d] | s[4][L] | row[R]
+__global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
+{
+#pragma clang fp contract(off)
+    extern __shared__ float smem[];
+    const int64_t v = blockIdx.x;
+    if (v >= a.n) return;
+    const int d = a.d, R = a.R, L = a.L, m = a.m;
+    const int dp = d / L;
+    float* xv = smem;
+    float* ebuf = xv + d;
+    float* sblk = ebuf + 4 * d;
+    int32_t* row = reinterpret_cast<int32_t*>(sblk + 4 * L);
+    const int lane = lane_id();
+    const int g = lane >> 4;   // edge slot within the wave
+    const int s = lane & 15;   // lane within the edge's group
+
+    const float* xvg = a.base + v * (int64_t)d;
+    float nv2 = 0.f;
+    for (int k = lane; k < d; k += kWave) {
+        float x = xvg[k];
+        xv[k] = x;
+        nv2 = fmaf(x, x, nv2);
+    }
+    nv2 = wave_sum(nv2);
+    for (int j = lane; j < R; j += kWave) row[j] = a.graph[v * R + j];
+    __syncthreads();
+
+    // graph validation: id range, self loop, repeated id in the row
+    for (int j = lane; j < R; j += kWave) {
+        int32_t u = row[j];
+        bool bad = (u < -1) || (u >= a.n) || (u == v);
+        if (u >= 0)
+            for (int jj = 0; jj < j; ++jj) bad |= (row[jj] == u);
+        if (bad) atomicOr(a.err, 1);
+    }
+
+    uint8_t* rv = a.rec + v * a.node_stride;
+    uint8_t* codes = rv + a.codes_off;
+    float* scal = reinterpret_cast<float*>(rv + a.scal_off);
+
+    for (int j0 = 0; j0 < R; j0 += 4) {
+        const int j = j0 + g;
+        // an out-of-range id is never dereferenced (it is reported through err)
+        int32_t u = (j < R) ? row[j] : -1;
+        if (u >= a.n) u = -1;
+        float* e = ebuf + g * d;
+        float* sb = sblk + g * L;
+        float nu2 = 0.f, ne2 = 0.f;
+        if (u >= 0) {
+            const float* xu = a.base + (int64_t)u * d;
+            for (int k = s; k < d; k += 16) {
+                float x = xu[k];
+                float t = x - xv[k];
+                e[k] = t;
+                nu2 = fmaf(x, x, nu2);
+                ne2 = fmaf(t, t, ne2);
+            }
+        }
+        nu2 = group_sum<16>(nu2);
+        ne2 = group_sum<16>(ne2);
+        __syncthreads();
+        // block norms, fixed order
+        if (u >= 0) {
+            for (int i = s; i < L; i += 16) {
+                float ss = 0.f;
+                for (int t = 0; t < dp; ++t) ss = fmaf(e[i * dp + t], e[i * dp + t], ss);
+                sb[i] = sqrtf(ss);
+            }
+        }
+        // subspace codes
+        for (int i = 0; i < L; ++i) {
+            float best = -1.f, bp = 0.f;
+            int bj = 0;
+            if (u >= 0) {
+                for (int jj = s; jj < m; jj += 16) {
+                    const float* av = a.dirs_a + ((int64_t)i * m + jj) * dp;
+                    float p = 0.f;
+                    for (int t = 0; t < dp; ++t) p = fmaf(e[i * dp + t], av[t], p);
+                    float ap = fabsf(p);
+                    if (ap > best) { best = ap; bj = jj; bp = p; }
+                }
+            }
+            // first maximum across the group: larger |p|, ties to smaller j
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) {
+                float ob = __shfl_xor(best, o, 16);
+                int oj = __shfl_xor(bj, o, 16);
+                float op = __shfl_xor(bp, o, 16);
+                if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; bp = op; }
+            }
+            if (s == 0 && j < R)
+                codes[(1 + i) * R + j] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+        }
+        __syncthreads();
+        // regular part: c = sum(s_i) / L', residual in place
+        float c = 0.f;
+        int nz = 0;
+        if (u >= 0) {
+            float sum = 0.f;
+            for (int i = 0; i < L; ++i) {
+                sum = sum + sb[i];
+                nz += sb[i] > 0.f;
+            }
+            c = nz > 0 ? sum / (float)nz : 0.f;
+        }
+        __syncthreads();
+        float nr2 = 0.f;
+        if (u >= 0) {
+            for (int k = s; k < d; k += 16) {
+                const float sk = sb[k / dp];
+                const float r = sk > 0.f ? c / sk : 0.f;
+                const float ek = e[k];
+                const float t = fmaf(-r, ek, ek);
+                e[k] = t;
+                nr2 = fmaf(t, t, nr2);
+            }
+        }
+        nr2 = group_sum<16>(nr2);
+        __syncthreads();
+        // residual code
+        {
+            float best = -1.f, bp = 0.f;
+            int bj = 0;
+            if (u >= 0) {
+                for (int jj = s; jj < m; jj += 16) {
+                    const float* bv = a.dirs_b + (int64_t)jj * d;
+                    float p = 0.f;
+                    for (int k = 0; k < d; ++k) p = fmaf(e[k], bv[k], p);
+                    float ap = fabsf(p);
+                    if (ap > best) { best = ap; bj = jj; bp = p; }
+                }
+            }
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) {
+                float ob = __shfl_xor(best, o, 16);
+                int oj = __shfl_xor(bj, o, 16);
+                float op = __shfl_xor(bp, o, 16);
+                if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; bp = op; }
+            }
+            if (s == 0 && j < R) codes[j] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+        }
+        // scalars: g_e, |e|, w_reg, sqrt(L) w_res
+        if (s == 0 && j < R) {
+            float ge = 0.f, ne = 0.f, wreg = 0.f, swres = 0.f;
+            if (u >= 0) {
+                ne = sqrtf(ne2);
+                if (ne > 0.f) {
+                    wreg = fminf(1.f, c * sqrtf((float)nz) / ne);
+                    swres = sqrtf((float)L) * fminf(1.f, sqrtf(nr2) / ne);
+                } else {
+                    wreg = 1.f;
+                    swres = 0.f;
+                }
+                if (a.metric == 0) ge = 0.5f * (nu2 - nv2);
+            }
+            scal[0 * R + j] = ge;
+            scal[1 * R + j] = ne;
+            scal[2 * R + j] = wreg;
+            scal[3 * R + j] = swres;
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace peos

@@ -1,0 +1,441 @@
+// Graph search with the PEOs routing test (Alg. 1 with Alg. 2 as RoutingTest).
+//
+// One wavefront per query; the grid is persistent and pulls query indices
+// from an atomic counter.  Per query, in LDS:
+//   qv    the query vector;
+//   tab   its projection table (step (5)), sign-duplicated: row i holds
+//         T_i[j] at j and -T_i[j] at m + j, so a code byte indexes it directly;
+//   list  the candidate list, sorted by (distance, id): its first ef entries
+//         are the result list R, entries beyond are nodes of the priority
+//         queue P that were pushed out of R before being expanded.  Ids carry
+//         an "expanded" bit.  Popping P = the first unexpanded entry;
+//   hash  the visited set (open addressing), moved to a per-slot bitmap in
+//         HBM if it fills up.
+// Per expansion of v (delta read once, before the neighbours are tested):
+//   lane j < R loads neighbour id j of v and, when R is full and the test is
+//   on, edge j's L+1 code bytes and four scalars (all three loads depend on v
+//   only, so they are issued together); visited filter; routing test of step
+//   (6); survivors are marked visited and their vectors gathered by groups of
+//   lanes (64/ns... lanes per vector, so every survivor's load is in flight at
+//   once); survivors closer than delta (or all, while R is not full) are
+//   merged into the list.
+#pragma once
+
+#include "peos_device.hpp"
+
+namespace peos {
+
+struct SearchArgs {
+    const float* base;
+    const int32_t* graph;
+    const uint8_t* rec;
+    int64_t node_stride, codes_off, scal_off;
+    const float* queries;
+    const float* tables;
+    const float* qnorms;
+    const int32_t* kq;
+    const int32_t* efq;
+    int64_t* ids;
+    float* dists;
+    int32_t* stats;
+    uint32_t* counter;  // work counter, zero before launch
+    uint32_t* spill;    // per-slot visited bitmaps
+    int64_t spill_words;
+    int64_t n, nq;
+    int k_all, ef_all, kstride;
+    int d, R, L, m, metric, mode, entry;
+    float eta, c_eps, kappa;
+    int listcap, pool, hcap_log2, visit_limit;
+};
+
+constexpr int kStatusZeroQuery = 1;
+constexpr int kStatusPoolFull = 2;
+constexpr int kStatusSpill = 4;
+
+__device__ __forceinline__ uint32_t hash_slot(uint32_t u, int log2) { return (u * 0x9E3779B1u) >> (32 - log2); }
+
+__device__ __forceinline__ bool hash_lookup(const uint32_t* h, int log2, uint32_t u)
+{
+    const uint32_t mask = (1u << log2) - 1u;
+    uint32_t s = hash_slot(u, log2);
+    for (;;) {
+        const uint32_t k = h[s];
+        if (k == u) return true;
+        if (k == kEmpty) return false;
+        s = (s + 1u) & mask;
+    }
+}
+
+__device__ __forceinline__ void hash_insert(uint32_t* h, int log2, uint32_t u)
+{
+    const uint32_t mask = (1u << log2) - 1u;
+    uint32_t s = hash_slot(u, log2);
+    for (;;) {
+        const uint32_t prev = atomicCAS(&h[s], kEmpty, u);
+        if (prev == kEmpty || prev == u) return;
+        s = (s + 1u) & mask;
+    }
+}
+
+__device__ __forceinline__ bool bitmap_test(const uint32_t* bm, uint32_t u)
+{
+    const uint32_t w = __hip_atomic_load(bm + (u >> 5), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (w >> (u & 31u)) & 1u;
+}
+
+// Exact distances of ns vectors (ids in Su) to the query, G lanes per vector.
+template <int G>
+__device__ __forceinline__ void gather_distances(const float* base, int d, const uint32_t* Su, int ns,
+                                                 const float* qv, int metric, float inv_qn,
+                                                 float* Sdist)
+{
+    const int lane = lane_id();
+    const int t = lane / G;
+    const int s = lane % G;
+    const int nch = d >> 2;
+    const float4* q4 = reinterpret_cast<const float4*>(qv);
+    for (int b0 = 0; b0 < ns; b0 += kWave / G) {
+        const int idx = b0 + t;
+        const bool act = idx < ns;
+        float acc = 0.f;
+        if (act) {
+            const float4* x4 = reinterpret_cast<const float4*>(base + (int64_t)Su[idx] * d);
+            if (metric == 0) {
+#pragma unroll 4
+                for (int c = s; c < nch; c += G) {
+                    const float4 x = x4[c];
+                    const float4 q = q4[c];
+                    const float t0 = x.x - q.x, t1 = x.y - q.y, t2 = x.z - q.z, t3 = x.w - q.w;
+                    acc = fmaf(t0, t0, acc);
+                    acc = fmaf(t1, t1, acc);
+                    acc = fmaf(t2, t2, acc);
+                    acc = fmaf(t3, t3, acc);
+                }
+            } else {
+#pragma unroll 4
+                for (int c = s; c < nch; c += G) {
+                    const float4 x = x4[c];
+                    const float4 q = q4[c];
+                    acc = fmaf(x.x, q.x, acc);
+                    acc = fmaf(x.y, q.y, acc);
+                    acc = fmaf(x.z, q.z, acc);
+                    acc = fmaf(x.w, q.w, acc);
+                }
+            }
+        }
+        acc = group_sum<G>(acc);
+        if (act && s == 0) Sdist[idx] = (metric == 0) ? acc : 1.f - acc * inv_qn;
+    }
+}
+
+__device__ __forceinline__ void distances(const float* base, int d, const uint32_t* Su, int ns,
+                                          const float* qv, int metric, float inv_qn, float* Sdist)
+{
+    if (ns <= 4) gather_distances<16>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 8) gather_distances<8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 16) gather_distances<4>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 32) gather_distances<2>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else gather_distances<1>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+}
+
+template <int MAXL>
+__global__ __launch_bounds__(64) void k_search(SearchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char sm[];
+    const int lane = lane_id();
+    const int d = a.d, R = a.R, L = a.L, m = a.m;
+    const int tabw = 2 * m;
+    const int hcap = 1 << a.hcap_log2;
+    float* qv = reinterpret_cast<float*>(sm);
+    float* tab = qv + d;
+    float* Ld = tab + (L + 1) * tabw;
+    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + a.listcap);
+    // the merge buffer holds the list plus up to one wave of survivors
+    float* Md = reinterpret_cast<float*>(Li + a.listcap);
+    uint32_t* Mi = reinterpret_cast<uint32_t*>(Md + a.listcap + kWave);
+    uint32_t* hash = Mi + a.listcap + kWave;
+    float* Sd = reinterpret_cast<float*>(hash + hcap);
+    uint32_t* Si = reinterpret_cast<uint32_t*>(Sd + kWave);
+    uint32_t* Su = Si + kWave;
+    float* Sdist = reinterpret_cast<float*>(Su + kWave);
+    uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
+
+    for (;;) {
+        uint32_t qtaken = 0;
+        if (lane == 0) qtaken = atomicAdd(a.counter, 1u);
+        const int64_t qi = wave_uniform((int)__shfl(qtaken, 0, kWave));
+        if (qi >= a.nq) break;
+
+        // per-query k and ef are clamped to the launch bounds k_all, ef_all
+        int kq = a.kq ? a.kq[qi] : a.k_all;
+        kq = kq < 1 ? 1 : (kq > a.k_all ? a.k_all : kq);
+        int efq = a.efq ? a.efq[qi] : a.ef_all;
+        efq = efq > a.ef_all ? a.ef_all : efq;
+        efq = efq > kq ? efq : kq;
+        int cap = a.pool > 0 ? (a.pool > efq ? a.pool : efq) : a.listcap;
+        cap = cap < a.listcap ? cap : a.listcap;
+        const float qn = a.qnorms[qi];
+        int status = 0;
+        int st_exp = 0, st_edges = 0, st_skip = 0, st_tests = 0, st_ge1 = 0, st_le0 = 0, st_h = 0,
+            st_zero = 0, st_pass = 0, st_ndist = 0, st_ins = 0;
+        int size = 0;
+
+        if (qn > 0.f && qn < INFINITY) {
+            const float inv_qn = 1.f / qn;
+            const float* qg = a.queries + qi * d;
+            for (int t = lane; t < d; t += kWave) qv[t] = qg[t];
+            const float* tg = a.tables + qi * (int64_t)(L + 1) * m;
+            for (int t = lane; t < (L + 1) * m; t += kWave) {
+                const float x = tg[t];
+                const int i = t / m, j = t - i * m;
+                tab[i * tabw + j] = x;
+                tab[i * tabw + m + j] = -x;
+            }
+            for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
+            if (lane == 0) Su[0] = (uint32_t)a.entry;
+            __syncthreads();
+            distances(a.base, d, Su, 1, qv, a.metric, inv_qn, Sdist);
+            if (lane == 0) {
+                hash_insert(hash, a.hcap_log2, (uint32_t)a.entry);
+            }
+            __syncthreads();
+            if (lane == 0) {
+                Ld[0] = Sdist[0];
+                Li[0] = (uint32_t)a.entry;
+            }
+            size = 1;
+            int nvis = 1;
+            bool spilled = false;
+            st_ndist = 1;
+            int lb = 0;  // every entry before lb is expanded
+            __syncthreads();
+
+            for (;;) {
+                // pop: first unexpanded entry of the list
+                int pos = -1;
+                for (int c0 = lb; c0 < size; c0 += kWave) {
+                    const int p = c0 + lane;
+                    const bool un = p < size && !(Li[p] & kExpanded);
+                    const uint64_t mk = ballot(un);
+                    if (mk) {
+                        pos = c0 + __ffsll((unsigned long long)mk) - 1;
+                        break;
+                    }
+                }
+                if (pos < 0) break;
+                lb = pos + 1;
+                const uint32_t vid = Li[pos] & kIdMask;
+                const float dv = Ld[pos];
+                const bool full = size >= efq;
+                const float delta = full ? Ld[efq - 1] : INFINITY;
+                __syncthreads();
+                if (lane == 0) Li[pos] = vid | kExpanded;
+                ++st_exp;
+                const bool testing = (a.mode == 0) && full;
+
+                // loads that depend on v only
+                int32_t u = -1;
+                float sg = 0.f, se = 0.f, sw = 0.f, sr = 0.f;
+                uint8_t cd[MAXL + 1];
+                if (lane < R) {
+                    u = a.graph[(int64_t)vid * R + lane];
+                    if (testing) {
+                        const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
+                        const float* sc = reinterpret_cast<const float*>(rv + a.scal_off);
+                        sg = sc[lane];
+                        se = sc[R + lane];
+                        sw = sc[2 * R + lane];
+                        sr = sc[3 * R + lane];
+                        const uint8_t* cb = rv + a.codes_off + lane;
+#pragma unroll
+                        for (int i = 0; i <= MAXL; ++i)
+                            if (i <= L) cd[i] = cb[i * R];
+                    }
+                }
+                const bool valid = u >= 0;
+                st_edges += popc(ballot(valid));
+                bool vis = false;
+                if (valid)
+                    vis = spilled ? bitmap_test(bitmap, (uint32_t)u)
+                                  : hash_lookup(hash, a.hcap_log2, (uint32_t)u);
+                st_skip += popc(ballot(vis));
+                const bool cand = valid && !vis;
+                bool pass = cand;
+                if (testing) {
+                    int kind = -1;
+                    if (cand) {
+                        const float num = (a.metric == 0) ? sg + 0.5f * (dv - delta) : (dv - delta);
+                        if (se == 0.f) {
+                            kind = 0;
+                            pass = num < 0.f;
+                        } else {
+                            const float A = num / ((a.metric == 0 ? qn : 1.f) * se);
+                            if (A >= 1.f) {
+                                kind = 1;
+                                pass = false;
+                            } else if (A <= 0.f) {
+                                kind = 2;
+                                pass = true;
+                            } else {
+                                kind = 3;
+                                float h1 = 0.f;
+#pragma unroll
+                                for (int i = 1; i <= MAXL; ++i)
+                                    if (i <= L) h1 += tab[i * tabw + cd[i]];
+                                const float h2 = tab[cd[0]];
+                                const float H = sw * h1 + sr * h2;
+                                const float var = sw * sw + sr * sr - a.kappa * A * A;
+                                const float T = A * a.eta + a.c_eps * sqrtf(var);
+                                pass = H >= T;
+                            }
+                        }
+                    }
+                    st_tests += popc(ballot(cand));
+                    st_zero += popc(ballot(kind == 0));
+                    st_ge1 += popc(ballot(kind == 1));
+                    st_le0 += popc(ballot(kind == 2));
+                    st_h += popc(ballot(kind == 3));
+                    st_pass += popc(ballot(cand && pass));
+                }
+                const uint64_t smask = ballot(pass);
+                const int ns = popc(smask);
+                if (ns == 0) continue;
+
+                // visited := visited + survivors
+                if (!spilled && nvis + ns > a.visit_limit) {
+                    for (int64_t w = lane; w < a.spill_words; w += kWave) bitmap[w] = 0u;
+                    __threadfence();
+                    __syncthreads();
+                    for (int t = lane; t < hcap; t += kWave) {
+                        const uint32_t k = hash[t];
+                        if (k != kEmpty) atomicOr(bitmap + (k >> 5), 1u << (k & 31u));
+                    }
+                    __threadfence();
+                    __syncthreads();
+                    spilled = true;
+                    status |= kStatusSpill;
+                }
+                if (pass) {
+                    if (spilled) atomicOr(bitmap + ((uint32_t)u >> 5), 1u << ((uint32_t)u & 31u));
+                    else hash_insert(hash, a.hcap_log2, (uint32_t)u);
+                    Su[popc(smask & lanemask_lt())] = (uint32_t)u;
+                }
+                nvis += ns;
+                __syncthreads();
+                distances(a.base, d, Su, ns, qv, a.metric, inv_qn, Sdist);
+                st_ndist += ns;
+                __syncthreads();
+
+                // survivors that enter the list
+                bool keep = false;
+                float dt = 0.f;
+                uint32_t ut = 0;
+                if (lane < ns) {
+                    dt = Sdist[lane];
+                    ut = Su[lane];
+                    keep = !full || dt < delta;
+                }
+                const uint64_t km = ballot(keep);
+                const int nS = popc(km);
+                if (keep) {
+                    const int ix = popc(km & lanemask_lt());
+                    Sd[ix] = dt;
+                    Si[ix] = ut;
+                }
+                st_ins += nS;
+                __syncthreads();
+                if (nS == 0) continue;
+
+                // merge: M := sort(list + S); list := compaction of M
+                int mpos = 0x7fffffff;
+                if (lane < nS) {
+                    const uint64_t sk = sort_key(Sd[lane], Si[lane]);
+                    int r = 0;
+                    for (int t = 0; t < nS; ++t) r += sort_key(Sd[t], Si[t]) < sk;
+                    int lo = 0, hi = size;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (sort_key(Ld[mid], Li[mid]) < sk) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    mpos = r + lo;
+                    Md[mpos] = Sd[lane];
+                    Mi[mpos] = Si[lane];
+                }
+                for (int p = lane; p < size; p += kWave) {
+                    const float dd = Ld[p];
+                    const uint32_t id = Li[p];
+                    const uint64_t k = sort_key(dd, id);
+                    int sh = 0;
+                    for (int t = 0; t < nS; ++t) sh += sort_key(Sd[t], Si[t]) < k;
+                    Md[p + sh] = dd;
+                    Mi[p + sh] = id;
+                }
+                int minpos = mpos;
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    const int other = __shfl_xor(minpos, o, kWave);
+                    minpos = other < minpos ? other : minpos;
+                }
+                __syncthreads();
+                const int total = size + nS;
+                int w = 0;
+                for (int c0 = 0; c0 < total; c0 += kWave) {
+                    const int p = c0 + lane;
+                    const bool vld = p < total;
+                    const uint32_t id = vld ? Mi[p] : 0u;
+                    const float dd = vld ? Md[p] : 0.f;
+                    const bool kp = vld && (p < efq || !(id & kExpanded));
+                    const uint64_t kmask = ballot(kp);
+                    const int ix = w + popc(kmask & lanemask_lt());
+                    if (kp && ix < cap) {
+                        Ld[ix] = dd;
+                        Li[ix] = id;
+                    }
+                    w += popc(kmask);
+                }
+                if (w > cap && a.pool <= 0) status |= kStatusPoolFull;
+                size = w < cap ? w : cap;
+                minpos = wave_uniform(minpos);
+                lb = lb < efq ? lb : efq;
+                lb = lb < minpos ? lb : minpos;
+                __syncthreads();
+            }
+        } else {
+            status |= kStatusZeroQuery;
+        }
+
+        // results: first k entries of the list, padded with (-1, +inf)
+        for (int t = lane; t < a.kstride; t += kWave) {
+            const bool ok = t < kq && t < size;
+            a.ids[qi * a.kstride + t] = ok ? (int64_t)(Li[t] & kIdMask) : (int64_t)-1;
+            a.dists[qi * a.kstride + t] = ok ? Ld[t] : INFINITY;
+        }
+        if (a.stats && lane == 0) {
+            int32_t* o = a.stats + qi * 12;
+            o[0] = st_exp;
+            o[1] = st_edges;
+            o[2] = st_skip;
+            o[3] = st_tests;
+            o[4] = st_ge1;
+            o[5] = st_le0;
+            o[6] = st_h;
+            o[7] = st_zero;
+            o[8] = st_pass;
+            o[9] = st_ndist;
+            o[10] = st_ins;
+            o[11] = status;
+        }
+        __syncthreads();
+    }
+}
+
+// zero the work counter (a kernel rather than a memset, so the sequence can
+// be captured in a graph)
+__global__ void k_zero_u32(uint32_t* p, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+}  // namespace peos

@@ -1,0 +1,470 @@
+// C ABI of the PEOs search library (declarations and contracts: include/peos.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+
+#include "../../include/peos.h"
+#include "k_edge_build.hpp"
+#include "k_query_table.hpp"
+#include "k_search.hpp"
+
+struct peos_index {
+    const float* base;
+    const int32_t* graph;
+    const float* dirs_a;
+    const float* dirs_b;
+    uint8_t* rec;
+    int64_t n;
+    int32_t d, R, L, m, metric, flags, entry;
+    int64_t node_stride, codes_off, scal_off;
+    int device;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess) return fail(PEOS_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kMaxSlots = 4096;      // resident search waves at most
+constexpr int kMaxEf = 4096;
+constexpr int64_t kLdsPerCu = 160 * 1024;
+constexpr int kNumCu = 256;
+
+int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    int64_t stride, codes_off, scal_off;
+};
+
+Layout layout_of(int R, int L)
+{
+    Layout l;
+    l.codes_off = 0;
+    l.scal_off = round_up((int64_t)(L + 1) * R, 16);
+    l.stride = round_up(l.scal_off + 16LL * R, 128);
+    return l;
+}
+
+int check_shape(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m)
+{
+    if (n < 1 || n > 0x7fffffffLL) return fail(PEOS_EINVAL, "n=%lld out of range [1, 2^31)", (long long)n);
+    if (d < 4 || d % 4) return fail(PEOS_EINVAL, "d=%d must be a positive multiple of 4", d);
+    if (R < 1 || R > 64) return fail(PEOS_EINVAL, "R=%d must be in [1, 64]", R);
+    if (L < 1 || L > 32 || d % L) return fail(PEOS_EINVAL, "L=%d must divide d=%d and be <= 32", L, d);
+    if ((d / L) % 4) return fail(PEOS_EINVAL, "d/L=%d must be a multiple of 4", d / L);
+    if (m < 16 || m % 16 || 2 * m > 256) return fail(PEOS_EINVAL, "m=%d must be 16, 32, .. 128", m);
+    return PEOS_OK;
+}
+
+int check_device(int* dev)
+{
+    HIP_TRY(hipGetDevice(dev));
+    static std::mutex mu;
+    static int checked[64] = {0};
+    std::lock_guard<std::mutex> g(mu);
+    if (*dev < 0 || *dev >= 64) return fail(PEOS_EDEVICE, "device index %d", *dev);
+    if (checked[*dev] == 0) {
+        hipDeviceProp_t p;
+        HIP_TRY(hipGetDeviceProperties(&p, *dev));
+        checked[*dev] = (std::strncmp(p.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+    }
+    if (checked[*dev] < 0) return fail(PEOS_EDEVICE, "device %d is not gfx950", *dev);
+    return PEOS_OK;
+}
+
+// Standard normal quantile: Acklam's rational approximation (2003) refined
+// by one Halley step on the erfc form of the CDF (full double precision).
+double norm_ppf(double p)
+{
+    static const double a[] = {-3.969683028665376e+01, 2.209460984245205e+02, -2.759285104469687e+02,
+                               1.383577518672690e+02, -3.066479806614716e+01, 2.506628277459239e+00};
+    static const double b[] = {-5.447609879822406e+01, 1.615858368580409e+02, -1.556989798598866e+02,
+                               6.680131188771972e+01, -1.328068155288572e+01};
+    static const double c[] = {-7.784894002430293e-03, -3.223964580411365e-01, -2.400758277161838e+00,
+                               -2.549732539343734e+00, 4.374664141464968e+00, 2.938163982698783e+00};
+    static const double dd[] = {7.784695709041462e-03, 3.224671290700398e-01, 2.445134137142996e+00,
+                                3.754408661907416e+00};
+    const double plow = 0.02425, phigh = 1 - plow;
+    double x;
+    if (p < plow) {
+        double q = std::sqrt(-2 * std::log(p));
+        x = (((((c[0] * q + c[1]) * q + c[2]) * q + c[3]) * q + c[4]) * q + c[5]) /
+            ((((dd[0] * q + dd[1]) * q + dd[2]) * q + dd[3]) * q + 1);
+    } else if (p <= phigh) {
+        double q = p - 0.5, r = q * q;
+        x = (((((a[0] * r + a[1]) * r + a[2]) * r + a[3]) * r + a[4]) * r + a[5]) * q /
+            (((((b[0] * r + b[1]) * r + b[2]) * r + b[3]) * r + b[4]) * r + 1);
+    } else {
+        double q = std::sqrt(-2 * std::log(1 - p));
+        x = -(((((c[0] * q + c[1]) * q + c[2]) * q + c[3]) * q + c[4]) * q + c[5]) /
+            ((((dd[0] * q + dd[1]) * q + dd[2]) * q + dd[3]) * q + 1);
+    }
+    const double e = 0.5 * std::erfc(-x / std::sqrt(2.0)) - p;
+    const double u = e * std::sqrt(2 * M_PI) * std::exp(x * x / 2);
+    return x - u / (1 + x * u / 2);
+}
+
+struct Tuning {
+    int hash_log2 = 0, listcap = 0, slots = 0;
+};
+std::mutex g_tune_mu;
+Tuning g_tune;
+
+struct SearchPlan {
+    int listcap, hcap_log2, visit_limit, slots;
+    int64_t lds;
+    int64_t spill_words;
+};
+
+SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool)
+{
+    SearchPlan p;
+    Tuning t;
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        t = g_tune;
+    }
+    const int lmin = pool > efmax ? pool : efmax;
+    int lc = pool > 0 ? lmin : (6 * efmax > 256 ? 6 * efmax : 256);
+    if (t.listcap > 0) lc = t.listcap > lmin ? t.listcap : lmin;
+    lc = (int)round_up(lc, 64);
+    if (lc > kMaxEf * 2) lc = kMaxEf * 2;
+    p.listcap = lc;
+    int hl = 11;
+    while ((1 << hl) < 32 * efmax && hl < 13) ++hl;
+    if (t.hash_log2 > 0) hl = t.hash_log2;
+    p.hcap_log2 = hl;
+    p.visit_limit = (3 << hl) / 4;
+    // qv | table | list (lc) | merge buffer (lc + 64) | hash | 4 staging arrays of 64
+    p.lds = 4LL * ix->d + 4LL * (ix->L + 1) * 2 * ix->m + 8LL * lc + 8LL * (lc + 64) + (4LL << hl) +
+            4LL * 4 * 64;
+    int64_t per_cu = kLdsPerCu / p.lds;
+    if (per_cu < 1) per_cu = 1;
+    if (per_cu > 16) per_cu = 16;
+    int64_t slots = per_cu * kNumCu;
+    if (slots > kMaxSlots) slots = kMaxSlots;
+    if (t.slots > 0) slots = t.slots;
+    if (slots > nq) slots = nq;
+    p.slots = (int)(slots > 0 ? slots : 1);
+    p.spill_words = (ix->n + 31) / 32;
+    return p;
+}
+
+struct WsLayout {
+    int64_t counter_off, spill_off, tables_off, qnorm_off, total;
+};
+
+WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
+{
+    WsLayout w;
+    int64_t slots = nq < kMaxSlots ? nq : kMaxSlots;
+    if (slots < 1) slots = 1;
+    w.counter_off = 0;
+    w.spill_off = 256;
+    w.tables_off = round_up(w.spill_off + slots * spill_words * 4, 256);
+    w.qnorm_off = round_up(w.tables_off + nq * (int64_t)(ix->L + 1) * ix->m * 4, 256);
+    w.total = round_up(w.qnorm_off + nq * 4, 256);
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* peos_last_error(void) { return g_err; }
+
+int peos_set_search_tuning(int32_t hash_log2, int32_t listcap, int32_t slots)
+{
+    if (hash_log2 != 0 && (hash_log2 < 6 || hash_log2 > 14))
+        return fail(PEOS_EINVAL, "hash_log2=%d not in [6, 14]", hash_log2);
+    if (listcap < 0 || listcap > 2 * kMaxEf) return fail(PEOS_EINVAL, "listcap=%d", listcap);
+    if (slots < 0 || slots > kMaxSlots) return fail(PEOS_EINVAL, "slots=%d", slots);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.hash_log2 = hash_log2;
+    g_tune.listcap = listcap;
+    g_tune.slots = slots;
+    return PEOS_OK;
+}
+
+const char* peos_strerror(int code)
+{
+    switch (code) {
+    case PEOS_OK: return "ok";
+    case PEOS_EINVAL: return "invalid argument";
+    case PEOS_ENOSPACE: return "buffer too small";
+    case PEOS_EHIP: return "HIP runtime error";
+    case PEOS_EGRAPH: return "invalid graph (id out of range, self loop or repeated neighbour)";
+    case PEOS_EDEVICE: return "no gfx950 device";
+    default: return "unknown error";
+    }
+}
+
+int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int32_t flags,
+                     size_t* index_bytes, size_t* build_ws_bytes)
+{
+    if (!index_bytes || !build_ws_bytes) return fail(PEOS_EINVAL, "null output pointer");
+    if (flags != 0) return fail(PEOS_EINVAL, "flags=%d not supported", flags);
+    int rc = check_shape(n, d, R, L, m);
+    if (rc) return rc;
+    Layout l = layout_of(R, L);
+    *index_bytes = (size_t)(n * l.stride);
+    *build_ws_bytes = 256;
+    return PEOS_OK;
+}
+
+int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* graph, int32_t R,
+                      int32_t entry, int32_t L, int32_t m, const float* dirs_a,
+                      const float* dirs_b, int32_t metric, int32_t flags, void* index_mem,
+                      size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
+                      peos_index** out)
+{
+    if (!out) return fail(PEOS_EINVAL, "null output handle");
+    *out = nullptr;
+    size_t need = 0, need_ws = 0;
+    int rc = peos_index_bytes(n, d, R, L, m, flags, &need, &need_ws);
+    if (rc) return rc;
+    if (!base || !graph || !dirs_a || !dirs_b || !index_mem || !ws)
+        return fail(PEOS_EINVAL, "null device pointer");
+    if (entry < 0 || entry >= n) return fail(PEOS_EINVAL, "entry=%d out of range", entry);
+    if (metric != PEOS_METRIC_L2 && metric != PEOS_METRIC_ANGULAR)
+        return fail(PEOS_EINVAL, "metric=%d", metric);
+    if (index_bytes < need) return fail(PEOS_ENOSPACE, "index_bytes %zu < %zu", index_bytes, need);
+    if (ws_bytes < need_ws) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %zu", ws_bytes, need_ws);
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Layout l = layout_of(R, L);
+    int32_t* err = (int32_t*)ws;
+    hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, (uint32_t*)err, 1);
+    peos::EdgeBuildArgs a;
+    a.base = base;
+    a.graph = graph;
+    a.dirs_a = dirs_a;
+    a.dirs_b = dirs_b;
+    a.rec = (uint8_t*)index_mem;
+    a.err = err;
+    a.n = n;
+    a.node_stride = l.stride;
+    a.codes_off = l.codes_off;
+    a.scal_off = l.scal_off;
+    a.d = d;
+    a.R = R;
+    a.L = L;
+    a.m = m;
+    a.metric = metric;
+    size_t lds = sizeof(float) * (size_t)(5 * d + 4 * L) + sizeof(int32_t) * (size_t)R;
+    hipLaunchKernelGGL(peos::k_edge_build, dim3((unsigned)n), dim3(64), lds, s, a);
+    HIP_TRY(hipGetLastError());
+    int32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(PEOS_EGRAPH, "graph has an id out of range, a self loop or a repeated neighbour");
+    peos_index* ix = new (std::nothrow) peos_index;
+    if (!ix) return fail(PEOS_EINVAL, "out of host memory");
+    ix->base = base;
+    ix->graph = graph;
+    ix->dirs_a = dirs_a;
+    ix->dirs_b = dirs_b;
+    ix->rec = (uint8_t*)index_mem;
+    ix->n = n;
+    ix->d = d;
+    ix->R = R;
+    ix->L = L;
+    ix->m = m;
+    ix->metric = metric;
+    ix->flags = flags;
+    ix->entry = entry;
+    ix->node_stride = l.stride;
+    ix->codes_off = l.codes_off;
+    ix->scal_off = l.scal_off;
+    ix->device = dev;
+    *out = ix;
+    return PEOS_OK;
+}
+
+int peos_index_layout(const peos_index* ix, peos_layout* out)
+{
+    if (!ix || !out) return fail(PEOS_EINVAL, "null pointer");
+    out->n = ix->n;
+    out->d = ix->d;
+    out->R = ix->R;
+    out->L = ix->L;
+    out->m = ix->m;
+    out->metric = ix->metric;
+    out->flags = ix->flags;
+    out->entry = ix->entry;
+    out->node_stride = ix->node_stride;
+    out->codes_offset = ix->codes_off;
+    out->scalars_offset = ix->scal_off;
+    return PEOS_OK;
+}
+
+void peos_free(peos_index* ix) { delete ix; }
+
+int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, float* tables,
+                      float* qnorms, void* stream)
+{
+    if (!ix) return fail(PEOS_EINVAL, "null index");
+    if (nq < 0) return fail(PEOS_EINVAL, "nq=%lld", (long long)nq);
+    if (nq == 0) return PEOS_OK;
+    if (!queries || !tables || !qnorms) return fail(PEOS_EINVAL, "null device pointer");
+    peos::QueryTableArgs a;
+    a.queries = queries;
+    a.dirs_a = ix->dirs_a;
+    a.dirs_b = ix->dirs_b;
+    a.tables = tables;
+    a.qnorms = qnorms;
+    a.nq = nq;
+    a.d = ix->d;
+    a.L = ix->L;
+    a.m = ix->m;
+    const int64_t blocks = (nq + 15) / 16;
+    hipLaunchKernelGGL(peos::k_query_table, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, a);
+    HIP_TRY(hipGetLastError());
+    return PEOS_OK;
+}
+
+int peos_search_ws_bytes(const peos_index* ix, int64_t nq, int32_t efmax, int32_t pool,
+                         size_t* ws_bytes)
+{
+    if (!ix || !ws_bytes) return fail(PEOS_EINVAL, "null pointer");
+    if (nq < 0 || efmax < 1 || efmax > kMaxEf || pool < 0 || pool > 2 * kMaxEf)
+        return fail(PEOS_EINVAL, "nq=%lld efmax=%d pool=%d", (long long)nq, efmax, pool);
+    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    *ws_bytes = (size_t)w.total;
+    return PEOS_OK;
+}
+
+static int search_impl(const peos_index* ix, const float* queries, const float* tables,
+                       const float* qnorms, int64_t nq, const int32_t* k, const int32_t* ef,
+                       int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool, float eps,
+                       int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
+                       size_t ws_bytes, hipStream_t s)
+{
+    const int efmax = ef_all > k_all ? ef_all : k_all;
+    SearchPlan plan = plan_search(ix, nq, efmax, pool);
+    WsLayout w = ws_layout(ix, nq, plan.spill_words);
+    if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
+    if (plan.lds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
+    peos::SearchArgs a;
+    a.base = ix->base;
+    a.graph = ix->graph;
+    a.rec = ix->rec;
+    a.node_stride = ix->node_stride;
+    a.codes_off = ix->codes_off;
+    a.scal_off = ix->scal_off;
+    a.queries = queries;
+    a.tables = tables;
+    a.qnorms = qnorms;
+    a.kq = k;
+    a.efq = ef;
+    a.ids = ids;
+    a.dists = dists;
+    a.stats = stats;
+    a.counter = (uint32_t*)((char*)ws + w.counter_off);
+    a.spill = (uint32_t*)((char*)ws + w.spill_off);
+    a.spill_words = plan.spill_words;
+    a.n = ix->n;
+    a.nq = nq;
+    a.k_all = k_all;
+    a.ef_all = ef_all;
+    a.kstride = kstride;
+    a.d = ix->d;
+    a.R = ix->R;
+    a.L = ix->L;
+    a.m = ix->m;
+    a.metric = ix->metric;
+    a.mode = mode;
+    a.entry = ix->entry;
+    const double eta = std::sqrt(2.0 * ix->L * std::log((double)ix->m));
+    a.eta = (float)eta;
+    a.c_eps = (float)norm_ppf((double)eps);
+    a.kappa = (float)((double)ix->L / (double)(ix->L + 1));
+    a.listcap = plan.listcap;
+    a.pool = pool;
+    a.hcap_log2 = plan.hcap_log2;
+    a.visit_limit = plan.visit_limit;
+    hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, a.counter, 1);
+    const dim3 grid((unsigned)plan.slots);
+    if (ix->L <= 8) {
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
+        hipLaunchKernelGGL(peos::k_search<8>, grid, dim3(64), (size_t)plan.lds, s, a);
+    } else if (ix->L <= 16) {
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
+        hipLaunchKernelGGL(peos::k_search<16>, grid, dim3(64), (size_t)plan.lds, s, a);
+    } else {
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
+        hipLaunchKernelGGL(peos::k_search<32>, grid, dim3(64), (size_t)plan.lds, s, a);
+    }
+    HIP_TRY(hipGetLastError());
+    return PEOS_OK;
+}
+
+static int check_search_args(const peos_index* ix, const float* queries, int64_t nq, int32_t k_all,
+                             int32_t ef_all, int32_t kstride, int32_t pool, float eps, int32_t mode,
+                             const int64_t* ids, const float* dists, const void* ws)
+{
+    if (!ix) return fail(PEOS_EINVAL, "null index");
+    if (nq < 0 || nq > 0x7fffffffLL) return fail(PEOS_EINVAL, "nq=%lld", (long long)nq);
+    if (k_all < 1 || kstride < k_all) return fail(PEOS_EINVAL, "k_all=%d kstride=%d", k_all, kstride);
+    if (ef_all < 1 || ef_all > kMaxEf || k_all > kMaxEf) return fail(PEOS_EINVAL, "ef_all=%d (max %d)", ef_all, kMaxEf);
+    if (pool < 0 || pool > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d", pool);
+    if (mode != PEOS_MODE_PEOS && mode != PEOS_MODE_EXHAUSTIVE) return fail(PEOS_EINVAL, "mode=%d", mode);
+    if (mode == PEOS_MODE_PEOS && !(eps > 0.f && eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g not in (0, 0.5]", (double)eps);
+    if (nq > 0 && (!queries || !ids || !dists || !ws)) return fail(PEOS_EINVAL, "null device pointer");
+    return PEOS_OK;
+}
+
+int peos_search_tables(const peos_index* ix, const float* queries, const float* tables,
+                       const float* qnorms, int64_t nq, const int32_t* k, const int32_t* ef,
+                       int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool, float eps,
+                       int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
+                       size_t ws_bytes, void* stream)
+{
+    int rc = check_search_args(ix, queries, nq, k_all, ef_all, kstride, pool, eps, mode, ids, dists, ws);
+    if (rc) return rc;
+    if (nq == 0) return PEOS_OK;
+    if (!tables || !qnorms) return fail(PEOS_EINVAL, "null table pointer");
+    return search_impl(ix, queries, tables, qnorms, nq, k, ef, k_all, ef_all, kstride, pool, eps,
+                       mode, ids, dists, stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+int peos_search(const peos_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                const int32_t* ef, int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool,
+                float eps, int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
+                size_t ws_bytes, void* stream)
+{
+    int rc = check_search_args(ix, queries, nq, k_all, ef_all, kstride, pool, eps, mode, ids, dists, ws);
+    if (rc) return rc;
+    if (nq == 0) return PEOS_OK;
+    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
+    float* tables = (float*)((char*)ws + w.tables_off);
+    float* qnorms = (float*)((char*)ws + w.qnorm_off);
+    rc = peos_query_tables(ix, queries, nq, tables, qnorms, stream);
+    if (rc) return rc;
+    return search_impl(ix, queries, tables, qnorms, nq, k, ef, k_all, ef_all, kstride, pool, eps,
+                       mode, ids, dists, stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

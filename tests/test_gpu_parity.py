@@ -1,0 +1,263 @@
+"""Parity of the HIP path (through the C ABI) with the oracle, on the GPU."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import compare
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2402_11354_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+
+
+class Case:
+    def __init__(self, w, graph_device="cpu"):
+        self.w = w
+        self.x = W.make_base(w)
+        self.q = W.make_queries(w)
+        self.g, self.entry = W.build_graph(self.x, w.R, w.cand, device=graph_device)
+        self.A, self.B = W.directions_for(w)
+        self.xt, self.gt, self.At, self.Bt = T(self.x), T(self.g), T(self.A), T(self.B)
+        self.qt = T(self.q)
+        self.index = P.peos_build_tables(self.xt, self.gt, self.entry, w.L, w.m, self.At, self.Bt,
+                                         w.metric)
+
+    def oracle(self, k, ef, eps, mode, pool=0, queries=None):
+        q = self.q if queries is None else queries
+        return O.search(self.x, self.g, self.entry, q, k, ef, self.w.L, self.w.m, self.A, self.B,
+                        self.w.metric, eps, mode=mode, pool=pool)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    print("[gpu] building tiny workload", flush=True)
+    return Case(W.TINY)
+
+
+ANG = W.Workload("ang_sphere_5k_d64", 5000, 100, 64, 16, 32, 4, 16, W.ANGULAR, "sphere500", 0.1,
+                 10, 32, 1005)
+
+
+@pytest.fixture(scope="module")
+def angular():
+    print("[gpu] building angular workload", flush=True)
+    return Case(ANG)
+
+
+# ---------------------------------------------------------------------------
+# steps (1)-(3): edge records
+# ---------------------------------------------------------------------------
+def read_records(case):
+    lay = case.index.layout()
+    mem = case.index._keep[-1].cpu().numpy()
+    n, R, L = lay.n, lay.R, lay.L
+    rec = mem.reshape(n, lay.node_stride)
+    codes = rec[:, lay.codes_offset:lay.codes_offset + (L + 1) * R].reshape(n, L + 1, R)
+    sc = rec[:, lay.scalars_offset:lay.scalars_offset + 16 * R].copy().view(np.float32)
+    return codes.transpose(0, 2, 1), sc.reshape(n, 4, R).transpose(0, 2, 1)
+
+
+@pytest.mark.parametrize("which", ["tiny", "angular"])
+def test_edge_records_match_oracle(which, request):
+    case = request.getfixturevalue(which)
+    w = case.w
+    codes, sc = read_records(case)
+    rc, rs, margin = O.build_tables(case.x, case.g, w.L, w.m, case.A, case.B)
+    valid = case.g >= 0
+    # codes: integer decisions, bit-exact
+    assert np.array_equal(codes[valid], rc[valid])
+    assert np.all(codes[~valid] == 0)
+    # scalars
+    ge, ne, wreg, swres = (sc[..., i][valid].astype(np.float64) for i in range(4))
+    r_ne, r_wreg, r_wres, r_ge = (rs[..., i][valid] for i in range(4))
+    np.testing.assert_allclose(ne, r_ne, rtol=2e-6)
+    np.testing.assert_allclose(wreg, r_wreg, rtol=0, atol=2e-6)
+    np.testing.assert_allclose(swres, np.sqrt(w.L) * r_wres, rtol=0, atol=2e-5)
+    if w.metric == W.L2:
+        nu2 = (case.x.astype(np.float64) ** 2).sum(1)
+        scale = nu2.max()
+        np.testing.assert_allclose(ge, r_ge, rtol=0, atol=2e-6 * scale)
+    else:
+        assert np.all(ge == 0)
+
+
+def test_build_rejects_bad_graph(tiny):
+    for bad in ("self", "dup", "range"):
+        g = tiny.g.copy()
+        if bad == "self":
+            g[5, 0] = 5
+        elif bad == "dup":
+            g[7, 1] = g[7, 0]
+        else:
+            g[9, 0] = tiny.x.shape[0]
+        with pytest.raises(P.PeosError) as e:
+            P.peos_build_tables(tiny.xt, T(g), tiny.entry, tiny.w.L, tiny.w.m, tiny.At, tiny.Bt,
+                                tiny.w.metric)
+        assert e.value.code == -4
+
+
+# ---------------------------------------------------------------------------
+# step (5): projection tables (matrix cores)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["tiny", "angular"])
+def test_query_tables_match_oracle(which, request):
+    case = request.getfixturevalue(which)
+    w = case.w
+    nq = case.q.shape[0]
+    tables = torch.empty((nq, w.L + 1, w.m), dtype=torch.float32, device=dev())
+    norms = torch.empty(nq, dtype=torch.float32, device=dev())
+    P.peos_query_tables(case.index, case.qt, tables, norms)
+    torch.cuda.synchronize()
+    tables = tables.cpu().numpy()
+    ref = np.stack([O.query_table(case.q[i], w.L, w.m, case.A, case.B) for i in range(nq)])
+    np.testing.assert_allclose(tables, ref, rtol=0, atol=2e-5)
+    np.testing.assert_allclose(norms.cpu().numpy(), np.linalg.norm(case.q.astype(np.float64), axis=1),
+                               rtol=2e-6)
+
+
+def test_query_tables_ragged_tail(tiny):
+    """nq not a multiple of the 16-query tile."""
+    w = tiny.w
+    for nq in (1, 17, 33):
+        q = tiny.q[:nq]
+        tables = torch.full((nq, w.L + 1, w.m), np.nan, dtype=torch.float32, device=dev())
+        norms = torch.empty(nq, dtype=torch.float32, device=dev())
+        P.peos_query_tables(tiny.index, T(q), tables, norms)
+        torch.cuda.synchronize()
+        ref = np.stack([O.query_table(q[i], w.L, w.m, tiny.A, tiny.B) for i in range(nq)])
+        np.testing.assert_allclose(tables.cpu().numpy(), ref, rtol=0, atol=2e-5)
+
+
+# ---------------------------------------------------------------------------
+# Alg. 1 + Alg. 2: search
+# ---------------------------------------------------------------------------
+def run(case, k, ef, eps, mode, pool=0, queries=None, kstride=None):
+    q = case.qt if queries is None else T(queries)
+    ids, d, st = P.search(case.index, q, k, ef, eps=eps, mode=mode, pool=pool, kstride=kstride)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+
+
+def recall(case, ids, k):
+    gt, _ = O.brute_force(case.x, case.q, k, case.w.metric)
+    return np.mean([len(set(ids[i][:k]) & set(gt[i])) / k for i in range(len(ids))])
+
+
+@pytest.mark.parametrize("which", ["tiny", "angular"])
+@pytest.mark.parametrize("mode", [P.PEOS_MODE_PEOS, P.PEOS_MODE_EXHAUSTIVE])
+@pytest.mark.parametrize("pool_mul", [0, 1, 2])
+def test_search_matches_oracle(which, mode, pool_mul, request):
+    case = request.getfixturevalue(which)
+    w = case.w
+    pool = pool_mul * w.ef
+    ids, d, st = run(case, w.k, w.ef, w.eps, mode, pool)
+    ref = case.oracle(w.k, w.ef, w.eps, mode, pool)
+    res = compare(ids, d, st, ref, w.k)
+    print(f"[gpu] {which} mode={mode} pool={pool}: checked={res['checked']} fragile={res['fragile']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+    assert np.all(st[:, 11] & ~P.PEOS_STATUS_VISITED_SPILL == 0)
+    assert abs(recall(case, ids, w.k) - recall(case, ref["ids"], w.k)) <= 0.003 + 1e-12
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.2, 0.5])
+def test_search_eps_values(tiny, eps):
+    w = tiny.w
+    ids, d, st = run(tiny, w.k, w.ef, eps, P.PEOS_MODE_PEOS)
+    res = compare(ids, d, st, tiny.oracle(w.k, w.ef, eps, P.PEOS_MODE_PEOS), w.k)
+    assert not res["bad"], res["bad"][:5]
+
+
+def test_per_query_k_ef_ragged_batch(tiny):
+    """37 queries with their own k and ef (k > ef included: ef := max(ef, k))."""
+    w = tiny.w
+    rng = np.random.default_rng(3)
+    nq = 37
+    q = tiny.q[:nq]
+    k = rng.choice([1, 5, 10, 40], size=nq).astype(np.int32)
+    ef = rng.choice([8, 16, 32, 64, 128], size=nq).astype(np.int32)
+    ids, d, st = P.search(tiny.index, T(q), T(k), T(ef), eps=w.eps, kstride=40)
+    torch.cuda.synchronize()
+    ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    ref = O.search(tiny.x, tiny.g, tiny.entry, q, k, ef, w.L, w.m, tiny.A, tiny.B, w.metric,
+                   w.eps, kstride=40)
+    res = compare(ids, d, st, ref, 40)
+    assert not res["bad"], res["bad"][:5]
+    for i in range(nq):
+        assert np.all(ids[i, k[i]:] == -1) and np.all(np.isinf(d[i, k[i]:]))
+
+
+def test_visited_spill_and_pool_capacity(tiny):
+    """A tiny LDS hash forces every query onto the HBM bitmap; a small kernel
+    list capacity with pool = 0 behaves as pool = that capacity."""
+    w = tiny.w
+    try:
+        P.peos_set_search_tuning(hash_log2=6, listcap=128, slots=7)
+        ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=0)
+        ids2, d2, st2 = run(tiny, w.k, 96, w.eps, P.PEOS_MODE_EXHAUSTIVE, pool=0)
+    finally:
+        P.peos_set_search_tuning(0, 0, 0)
+    assert np.all(st[:, 11] & P.PEOS_STATUS_VISITED_SPILL)
+    ref = tiny.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=128)
+    res = compare(ids, d, st, ref, w.k)
+    assert not res["bad"], res["bad"][:5]
+    full = (st2[:, 11] & P.PEOS_STATUS_POOL_FULL) != 0
+    ref2 = tiny.oracle(w.k, 96, w.eps, P.PEOS_MODE_EXHAUSTIVE, pool=128)
+    res2 = compare(ids2, d2, st2, ref2, w.k)
+    assert not res2["bad"], res2["bad"][:5]
+    print(f"[gpu] pool-full queries: {int(full.sum())}")
+
+
+def test_edge_cases(tiny):
+    w = tiny.w
+    # nq = 0: no work, no error
+    ids, d, st = P.search(tiny.index, tiny.qt[:0], w.k, w.ef)
+    assert ids.shape == (0, w.k)
+    # zero query: status bit and padded output
+    q = tiny.q[:3].copy()
+    q[1] = 0
+    ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, queries=q)
+    assert st[1, 11] & P.PEOS_STATUS_ZERO_QUERY and np.all(ids[1] == -1) and np.all(np.isinf(d[1]))
+    assert ids[0, 0] >= 0 and ids[2, 0] >= 0
+    # k larger than the reachable set: padding
+    x = tiny.x[:50]
+    g = np.full((50, w.R), -1, np.int32)
+    g[0, :3] = [1, 2, 3]
+    idx = P.peos_build_tables(T(x), T(g), 0, w.L, w.m, tiny.At, tiny.Bt, w.metric)
+    ids, d, st = P.search(idx, tiny.qt[:2], 10, 16)
+    torch.cuda.synchronize()
+    ids = ids.cpu().numpy()
+    assert sorted(ids[0, :4].tolist()) == [0, 1, 2, 3] and np.all(ids[:, 4:] == -1)
+    # invalid eps / k
+    with pytest.raises(P.PeosError):
+        P.search(tiny.index, tiny.qt, w.k, w.ef, eps=0.0)
+    with pytest.raises(P.PeosError):
+        P.search(tiny.index, tiny.qt, w.k, w.ef, eps=0.7)
+
+
+def test_large_list(tiny):
+    """ef = 256 (the largest in the sweeps) with the queue unbounded."""
+    w = tiny.w
+    ids, d, st = run(tiny, 100, 256, w.eps, P.PEOS_MODE_PEOS)
+    res = compare(ids, d, st, tiny.oracle(100, 256, w.eps, P.PEOS_MODE_PEOS), 100)
+    assert not res["bad"], res["bad"][:5]
+
+
+def test_repeatable(tiny):
+    """Same inputs, same outputs, whatever the batch composition."""
+    w = tiny.w
+    a = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS)
+    perm = np.random.default_rng(0).permutation(len(tiny.q))
+    b = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, queries=tiny.q[perm])
+    assert np.array_equal(a[0][perm], b[0]) and np.array_equal(a[1][perm], b[1])
+    assert np.array_equal(a[2][perm], b[2])
