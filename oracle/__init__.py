@@ -72,7 +72,7 @@ def _load():
         lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, P]
         lib.oracle_test_edge.restype = i32
         lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
-                                      i32, i32, f64, i32, f64, i32, P, P, P, P, P]
+                                      i32, i32, f64, i32, f64, i32, i32, P, P, P, P, P, P]
         lib.oracle_search.restype = i32
         _lib = lib
     return _lib
@@ -164,12 +164,16 @@ def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps):
 # Alg. 1
 # ---------------------------------------------------------------------------
 def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MODE_PEOS,
-           tau=1e-5, nthreads=None, kstride=None, pool=0):
+           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64):
     """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
     pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
-    pool <= ef = the HNSW stopping rule.
-    Returns dict(ids (nq, kstride) int64, dist float64, counters (nq, 11) int64,
-    fragile (nq,) int32 flag words, status (nq,) int32)."""
+    pool <= ef = the HNSW stopping rule.  precision: 64 = distances in float64;
+    32 = the distance decisions taken on the canonical single-precision
+    distances (the GPU kernel's precision; see dist32 in peos_oracle.c).
+    Returns dict(ids (nq, kstride) int64, dist (as decided), dist64 float64,
+    counters (nq, 11) int64, fragile (nq,) int32 flag words, status (nq,) int32)."""
+    if precision not in (32, 64):
+        raise ValueError("precision must be 32 or 64")
     base, queries = _f32(base), _f32(queries)
     A = _f32(A) if A is not None else np.zeros(1, np.float32)
     B = _f32(B) if B is not None else np.zeros(1, np.float32)
@@ -181,17 +185,18 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     ks = int(kstride or (karr.max() if nq else 1))
     ids = np.zeros((nq, ks), np.int64)
     dist = np.zeros((nq, ks), np.float64)
+    dist64 = np.zeros((nq, ks), np.float64)
     cnt = np.zeros((nq, len(COUNTERS)), np.int64)
     frag = np.zeros(nq, np.int32)
     status = np.zeros(nq, np.int32)
     nt = nthreads or min(16, os.cpu_count() or 1)
     rc = _load().oracle_search(_p(base), n, d, _p(graph), graph.shape[1], int(entry), L, m, _p(A),
                                _p(B), metric, _p(queries), nq, _p(karr), _p(efarr), ks,
-                               int(pool), float(eps), mode, float(tau), nt, _p(ids), _p(dist), _p(cnt),
-                               _p(frag), _p(status))
+                               int(pool), float(eps), mode, float(tau), 1 if precision == 32 else 0,
+                               nt, _p(ids), _p(dist), _p(dist64), _p(cnt), _p(frag), _p(status))
     if rc:
         raise ValueError("bad search arguments")
-    return dict(ids=ids, dist=dist, counters=cnt, fragile=frag, status=status)
+    return dict(ids=ids, dist=dist, dist64=dist64, counters=cnt, fragile=frag, status=status)
 
 
 # ---------------------------------------------------------------------------

@@ -390,7 +390,7 @@ double oracle_threshold(double A, double w_reg, double w_res, int L, double eta,
  */
 static int routing_test(const test_params* tp, const edge_rec* er, const double* table,
                         double num, double qnorm, double* outA, double* outH, double* outT,
-                        int* kind, int* flags)
+                        int* kind, int* flags, int v_is_p)
 {
     const double tau = tp->tau;
     *outA = NAN;
@@ -398,13 +398,14 @@ static int routing_test(const test_params* tp, const edge_rec* er, const double*
     *outT = NAN;
     if (er->norm_e == 0.0) {
         *kind = 0;
-        if (fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
+        if (!v_is_p && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
         return num < 0.0;
     }
     double A = num / (qnorm * er->norm_e);
     *outA = A;
     if (fabs(A - 1.0) < tau) *flags |= F_A1;
-    if (fabs(A) < tau) *flags |= F_A0;
+    /* A = 0 exactly when v is p itself, identically in any precision */
+    if (!v_is_p && fabs(A) < tau) *flags |= F_A0;
     if (A >= 1.0) { *kind = 1; return 0; }
     if (A <= 0.0) { *kind = 2; return 1; }
     *kind = 3;
@@ -457,14 +458,61 @@ static double dist64(const float* x, const float* q, double qnorm, int d, int me
     return 1.0 - dot64(x, q, d) / qnorm;
 }
 
+/*
+ * Distances in single precision, in one fixed summation order (used for the
+ * search's ordering and comparison decisions when the oracle runs in the
+ * precision of the GPU kernel).  The d coordinates are read in chunks of four
+ * (chunk c = coordinates 4c..4c+3); chunk c belongs to segment c mod 16; each
+ * segment is an fmaf chain over its chunks in increasing c (coordinates in
+ * order), for l2 of t*t with t = x - q, for angular of x*q; the 16 segment
+ * sums are added as a fixed binary tree: (0+1), (2+3), ... then pairs of
+ * those, and so on.  Angular distance = fmaf(-s, 1/|q|, 1), with |q| =
+ * sqrtf((p0 + p1) + (p2 + p3)), p_j the fmaf chain of q_k^2 over k = j mod 4.
+ */
+static float qnorm32(const float* q, int d)
+{
+    float p[4];
+    for (int j = 0; j < 4; ++j) {
+        float acc = 0.0f;
+        for (int k = j; k < d; k += 4) acc = fmaf(q[k], q[k], acc);
+        p[j] = acc;
+    }
+    return sqrtf((p[0] + p[1]) + (p[2] + p[3]));
+}
+
+static float dist32(const float* x, const float* q, int d, int metric, float inv_qn)
+{
+    float seg[16];
+    const int nch = d / 4;
+    for (int s = 0; s < 16; ++s) {
+        float acc = 0.0f;
+        for (int c = s; c < nch; c += 16) {
+            for (int t = 0; t < 4; ++t) {
+                const float xv = x[4 * c + t], qv = q[4 * c + t];
+                if (metric == OR_L2) {
+                    const float df = xv - qv;
+                    acc = fmaf(df, df, acc);
+                } else {
+                    acc = fmaf(xv, qv, acc);
+                }
+            }
+        }
+        seg[s] = acc;
+    }
+    for (int w = 16; w > 1; w /= 2)
+        for (int i = 0; i < w / 2; ++i) seg[i] = seg[2 * i] + seg[2 * i + 1];
+    return metric == OR_L2 ? seg[0] : fmaf(-seg[0], inv_qn, 1.0f);
+}
+
 typedef struct {
     const float *base, *A, *B, *queries;
     const int32_t *graph, *k, *ef;
     int64_t n, q0, q1;
-    int d, R, L, m, metric, mode, entry, kstride, pool;
+    int d, R, L, m, metric, mode, entry, kstride, pool, fp32;
     double eps, tau;
     int64_t* out_ids;
     double* out_dist;
+    double* out_dist64;
     int64_t* counters;
     int32_t* fragile;
     int32_t* status;
@@ -503,11 +551,16 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
     int flags = 0;
     memset(cnt, 0, sizeof(int64_t) * C_NCOUNT);
     double qnorm = sqrt(dot64(q, q, d));
-    if (!(qnorm > 0.0) || !isfinite(qnorm)) {
+    const float qn32 = qnorm32(q, d);
+    const float inv_qn32 = 1.0f / qn32;
+#define DIST(xp) (j->fp32 ? (double)dist32((xp), q, d, j->metric, inv_qn32) \
+                          : dist64((xp), q, qnorm, d, j->metric))
+    if (!(qnorm > 0.0) || !isfinite(qnorm) || (j->fp32 && !(qn32 > 0.0f && isfinite(qn32)))) {
         j->status[qi] = -1;
         for (int t = 0; t < j->kstride; ++t) {
             j->out_ids[(size_t)qi * j->kstride + t] = -1;
             j->out_dist[(size_t)qi * j->kstride + t] = INFINITY;
+            if (j->out_dist64) j->out_dist64[(size_t)qi * j->kstride + t] = INFINITY;
         }
         return;
     }
@@ -516,7 +569,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
     memset(visited, 0, (size_t)j->n);
     int size = 0;
     const float* x0 = j->base + (size_t)j->entry * d;
-    R[0].dist = dist64(x0, q, qnorm, d, j->metric);
+    R[0].dist = DIST(x0);
     R[0].id = j->entry;
     R[0].expanded = 0;
     size = 1;
@@ -558,7 +611,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
                 else num = -r - vq;
                 double A, H, T;
                 int kind;
-                pass = routing_test(tp, &er, table, num, qnorm, &A, &H, &T, &kind, &flags);
+                pass = routing_test(tp, &er, table, num, qnorm, &A, &H, &T, &kind, &flags, v == p);
                 cnt[C_TESTS]++;
                 cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
                 if (pass) cnt[C_PASSES]++;
@@ -566,8 +619,8 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             if (!pass) continue;
             visited[u] = 1;
             cnt[C_NDIST]++;
-            double du = dist64(xu, q, qnorm, d, j->metric);
-            if (full && fabs(du - delta) < j->tau * fabs(delta)) flags |= F_DELTA;
+            double du = DIST(xu);
+            if (!j->fp32 && full && fabs(du - delta) < j->tau * fabs(delta)) flags |= F_DELTA;
             if (!full || du < delta) {
                 S[ns].dist = du;
                 S[ns].id = u;
@@ -588,7 +641,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             R[w++] = R[i];
         }
         size = w;
-        for (int i = 1; i < size; ++i) {
+        for (int i = 1; i < size && !j->fp32; ++i) {
             double a = R[i - 1].dist, b = R[i].dist;
             double sc = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
             if (a != b && fabs(a - b) < j->tau * sc) flags |= F_ORDER;
@@ -599,13 +652,17 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         if (t < kq && t < size) {
             j->out_ids[o] = R[t].id;
             j->out_dist[o] = R[t].dist;
+            if (j->out_dist64)
+                j->out_dist64[o] = dist64(j->base + (size_t)R[t].id * d, q, qnorm, d, j->metric);
         } else {
             j->out_ids[o] = -1;
             j->out_dist[o] = INFINITY;
+            if (j->out_dist64) j->out_dist64[o] = INFINITY;
         }
     }
     j->fragile[qi] = flags;
     j->status[qi] = 0;
+#undef DIST
 }
 
 static void* search_worker(void* arg)
@@ -649,6 +706,10 @@ static void* search_worker(void* arg)
  * Public: batched search.  k and ef are per-query arrays (ef := max(ef, k)).
  * pool: capacity of the candidate list (<= 0: unbounded, Alg. 1 as printed;
  * values below ef act as ef, the HNSW stopping rule).
+ * fp32: 0 = distances in double precision; 1 = the search's distance
+ * decisions (order, delta, insertion) taken on the single-precision
+ * distances of dist32(), the precision of the GPU kernel.  out_dist then
+ * holds those values and out_dist64 (optional) the double-precision ones.
  * out_ids / out_dist: nq x kstride, first k entries of R, padded (-1, +inf).
  * Distances: squared l2, or 1 - x.q/|q| for the angular metric.
  * counters: nq x C_NCOUNT int64; fragile: nq flag words; status: 0 ok, -1
@@ -657,8 +718,9 @@ static void* search_worker(void* arg)
 int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,
                   int L, int m, const float* A, const float* B, int metric, const float* queries,
                   int64_t nq, const int32_t* k, const int32_t* ef, int kstride, int pool,
-                  double eps, int mode, double tau, int nthreads, int64_t* out_ids,
-                  double* out_dist, int64_t* counters, int32_t* fragile, int32_t* status)
+                  double eps, int mode, double tau, int fp32, int nthreads, int64_t* out_ids,
+                  double* out_dist, double* out_dist64, int64_t* counters, int32_t* fragile,
+                  int32_t* status)
 {
     if (n <= 0 || d <= 0 || R <= 0 || entry < 0 || entry >= n) return -1;
     if (mode == OR_MODE_PEOS && (L <= 0 || d % L || L > 255 || m < 2 || 2 * m > 256)) return -1;
@@ -671,7 +733,8 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
                                nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
-                               pool, eps, tau, out_ids, out_dist, counters, fragile, status};
+                               pool, fp32, eps, tau, out_ids, out_dist, out_dist64, counters,
+                               fragile, status};
         pthread_create(&th[t], NULL, search_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
@@ -697,7 +760,7 @@ int oracle_test_edge(const float* xv, const float* xu, const float* xp, const fl
     double num = metric == OR_L2 ? 0.5 * er.nu2 - r - vq : -r - vq;
     double a, h, t;
     int kind, flags = 0;
-    int pass = routing_test(&tp, &er, table, num, qnorm, &a, &h, &t, &kind, &flags);
+    int pass = routing_test(&tp, &er, table, num, qnorm, &a, &h, &t, &kind, &flags, 0);
     out[0] = a;
     out[1] = h;
     out[2] = t;

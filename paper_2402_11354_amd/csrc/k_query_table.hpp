@@ -30,6 +30,7 @@ struct QueryTableArgs {
 
 __global__ __launch_bounds__(64) void k_query_table(QueryTableArgs a)
 {
+#pragma clang fp contract(off)
     __shared__ float inv_norm[16];
     const int lane = lane_id();
     const int row = lane & 15;
@@ -41,7 +42,8 @@ __global__ __launch_bounds__(64) void k_query_table(QueryTableArgs a)
     const int dp = d / L;
     const float* qv = a.queries + (valid ? qrow : 0) * (int64_t)d;
 
-    // |q|: four lanes per query, then combine across the lane groups
+    // |q| = sqrt((p0 + p1) + (p2 + p3)), p_j the fma chain of q_k^2 over
+    // k = j mod 4 (one lane each), combined by two xor shuffles
     float ss = 0.f;
     if (valid)
         for (int k = kq; k < d; k += 4) ss = fmaf(qv[k], qv[k], ss);

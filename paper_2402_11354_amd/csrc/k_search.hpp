@@ -83,12 +83,22 @@ __device__ __forceinline__ bool bitmap_test(const uint32_t* bm, uint32_t u)
     return (w >> (u & 31u)) & 1u;
 }
 
-// Exact distances of ns vectors (ids in Su) to the query, G lanes per vector.
+// Exact distances of ns vectors (ids in Su) to the query, G lanes per vector
+// (G = 1, 2, 4, 8 or 16).  Every G gives bit-identical results: the d
+// coordinates are read in float4 chunks, chunk c belongs to segment c mod 16,
+// each segment is an fma chain over its chunks in increasing c, and the 16
+// segment sums are added in one fixed binary tree ((0+1), (2+3), ...; then
+// pairs of those; ...).  Lane s of a group owns segments s, s+G, ...; the
+// tree levels that pair segments of different lanes are xor shuffles (an add
+// is commutative, so both partners get the same bits), the remaining levels
+// are local.  Angular distance = fma(-sum, 1/|q|, 1).
 template <int G>
 __device__ __forceinline__ void gather_distances(const float* base, int d, const uint32_t* Su, int ns,
                                                  const float* qv, int metric, float inv_qn,
                                                  float* Sdist)
 {
+#pragma clang fp contract(off)
+    constexpr int NP = 16 / G;  // segments per lane
     const int lane = lane_id();
     const int t = lane / G;
     const int s = lane % G;
@@ -97,34 +107,44 @@ __device__ __forceinline__ void gather_distances(const float* base, int d, const
     for (int b0 = 0; b0 < ns; b0 += kWave / G) {
         const int idx = b0 + t;
         const bool act = idx < ns;
-        float acc = 0.f;
+        float part[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) part[j] = 0.f;
         if (act) {
             const float4* x4 = reinterpret_cast<const float4*>(base + (int64_t)Su[idx] * d);
-            if (metric == 0) {
-#pragma unroll 4
-                for (int c = s; c < nch; c += G) {
+#pragma unroll
+            for (int j = 0; j < NP; ++j) {
+                float acc = 0.f;
+                for (int c = s + j * G; c < nch; c += 16) {
                     const float4 x = x4[c];
                     const float4 q = q4[c];
-                    const float t0 = x.x - q.x, t1 = x.y - q.y, t2 = x.z - q.z, t3 = x.w - q.w;
-                    acc = fmaf(t0, t0, acc);
-                    acc = fmaf(t1, t1, acc);
-                    acc = fmaf(t2, t2, acc);
-                    acc = fmaf(t3, t3, acc);
+                    if (metric == 0) {
+                        const float t0 = x.x - q.x, t1 = x.y - q.y, t2 = x.z - q.z, t3 = x.w - q.w;
+                        acc = fmaf(t0, t0, acc);
+                        acc = fmaf(t1, t1, acc);
+                        acc = fmaf(t2, t2, acc);
+                        acc = fmaf(t3, t3, acc);
+                    } else {
+                        acc = fmaf(x.x, q.x, acc);
+                        acc = fmaf(x.y, q.y, acc);
+                        acc = fmaf(x.z, q.z, acc);
+                        acc = fmaf(x.w, q.w, acc);
+                    }
                 }
-            } else {
-#pragma unroll 4
-                for (int c = s; c < nch; c += G) {
-                    const float4 x = x4[c];
-                    const float4 q = q4[c];
-                    acc = fmaf(x.x, q.x, acc);
-                    acc = fmaf(x.y, q.y, acc);
-                    acc = fmaf(x.z, q.z, acc);
-                    acc = fmaf(x.w, q.w, acc);
-                }
+                part[j] = acc;
             }
         }
-        acc = group_sum<G>(acc);
-        if (act && s == 0) Sdist[idx] = (metric == 0) ? acc : 1.f - acc * inv_qn;
+        // tree levels across lanes (segment index bits below log2 G)
+#pragma unroll
+        for (int o = 1; o < G; o <<= 1)
+#pragma unroll
+            for (int j = 0; j < NP; ++j) part[j] = part[j] + __shfl_xor(part[j], o, G);
+        // remaining levels inside the lane
+#pragma unroll
+        for (int h = 1; h < NP; h <<= 1)
+#pragma unroll
+            for (int j = 0; j < NP; j += 2 * h) part[j] = part[j] + part[j + h];
+        if (act && s == 0) Sdist[idx] = (metric == 0) ? part[0] : fmaf(-part[0], inv_qn, 1.f);
     }
 }
 

@@ -651,3 +651,47 @@ def test_integer_data_ties_follow_strict_insertion(mode, pool_mul):
         assert out["counters"][i, O.COUNTERS.index("ndist")] == nd
         ties += len(dd) - len(set(dd))
     assert ties > 0
+
+
+# ---------------------------------------------------------------------------
+# the single-precision distance decisions (the GPU kernel's precision)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_fp32_distances_within_rounding_bound(metric):
+    w = W.TINY.with_sizes(n=1500, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    out = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, precision=32)
+    d32, d64 = out["dist"], out["dist64"]
+    assert np.all(d32 == d32.astype(np.float32))   # values are single precision
+    u = 2.0 ** -24
+    if metric == W.L2:
+        assert np.all(np.abs(d32 - d64) <= (w.d + 2) * u * d64)
+    else:
+        assert np.all(np.abs(d32 - d64) <= (w.d + 4) * u)
+    # and far inside the 1e-5 relative tolerance of the GPU parity
+    assert np.all(np.abs(d32 - d64) <= 1e-5 * np.abs(d64) + 1e-6)
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_fp32_decisions_equal_fp64_away_from_near_ties(metric, pool_mul):
+    """Single-precision distance decisions change nothing unless two
+    distances (or a distance and delta) are within 1e-5 relative."""
+    w = W.TINY.with_sizes(n=2000, nq=100)
+    x, q = W.make_base(w), W.make_queries(w)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    kw = dict(pool=pool_mul * 32)
+    o64 = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, precision=64, **kw)
+    o32 = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, precision=32, **kw)
+    clean = (o64["fragile"] & (O.F_DELTA | O.F_ORDER)) == 0
+    assert clean.sum() >= 0.3 * len(q)
+    assert np.array_equal(o64["ids"][clean], o32["ids"][clean])
+    assert np.array_equal(o64["counters"][clean], o32["counters"][clean])
+    np.testing.assert_allclose(o32["dist64"][clean], o64["dist"][clean], rtol=0, atol=0)

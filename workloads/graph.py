@@ -49,7 +49,7 @@ def _sqnorm(x):
 
 
 def knn(base: torch.Tensor, queries: torch.Tensor, k: int, exclude_self: bool = False,
-        row_chunk: int = 2048, col_chunk: int = 1 << 20):
+        row_chunk: int = 2048, col_chunk: int = 1 << 20, log=None):
     """Exact k nearest base rows of every query row by squared l2, ordered by
     (distance, id).  With exclude_self, query i is base row i and is skipped."""
     nq, n = queries.shape[0], base.shape[0]
@@ -60,6 +60,8 @@ def knn(base: torch.Tensor, queries: torch.Tensor, k: int, exclude_self: bool = 
         return out_i, out_d
     bn = _sqnorm(base)
     for r0 in range(0, nq, row_chunk):
+        if log and r0 and (r0 // row_chunk) % 64 == 0:
+            log(f"knn rows {r0}/{nq}")
         q = queries[r0:r0 + row_chunk]
         qn = _sqnorm(q)
         best_d = None
@@ -246,14 +248,19 @@ def medoid(x: torch.Tensor, exact_limit: int = 20000) -> int:
     return int(torch.argmin(_sqnorm(x - mu)))
 
 
-def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool = True):
+def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool = True,
+                log=None):
     """Pruned exact-kNN graph (module docstring).  Returns (graph int32 n x R
-    padded with -1, entry id)."""
+    padded with -1, entry id).  `log` receives progress lines."""
     device, dt = _dev_dtype(device)
     x = torch.as_tensor(base).to(device=device, dtype=dt)
-    ci, cd = knn(x, x, cand, exclude_self=True)
+    ci, cd = knn(x, x, cand, exclude_self=True, log=log)
+    if log:
+        log("knn done, pruning")
     gi, gd = _prune(x, ci, cd, R)
     if reverse:
+        if log:
+            log("reverse edges")
         ci, cd = _reverse_merge(x, gi, gd, cand)
         small = (ci >= 0).sum(1) <= R
         pi, pd = _prune(x, ci, cd, R)
@@ -261,6 +268,8 @@ def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool
         gd = torch.where(small[:, None], cd[:, :R], pd)
     entry = medoid(x)
     kc, _ = knn(x, x, cand, exclude_self=True) if not reverse else (ci, cd)
+    if log:
+        log("connectivity")
     gi = _connect(x, gi, kc, entry)
     return gi.to(torch.int32).cpu().numpy(), entry
 
