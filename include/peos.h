@@ -78,18 +78,20 @@ typedef struct peos_index peos_index;
 
 /* Byte layout of the per-node edge records inside index_mem (for tests and
  * tools; the search needs nothing but the handle).  Record of node v starts at
- * v * node_stride.  Codes: (L+1) rows of R bytes, row i at codes_offset +
- * i*R (row 0 = residual code e[0], rows 1..L = subspace codes e[i]), byte j =
- * edge to graph[v*R + j].  A code byte c encodes the index j* = c mod m of
- * the extreme projection vector and its sign (negative iff c >= m).
- * Scalars: 4 rows of R floats at scalars_offset + s*R*4, s = 0: g_e =
- * (|u|^2 - |v|^2)/2 (zero for ANGULAR), 1: |e|, 2: w_reg, 3: sqrt(L)*w_res. */
+ * v * node_stride.  Codes: edge j (to graph[v*R + j]) owns code_bytes =
+ * round_up(L+1, 4) bytes at codes_offset + j*code_bytes: byte 0 = residual
+ * code e[0], bytes 1..L = subspace codes e[i], then zero padding.  A code
+ * byte c encodes the index j* = c mod m of the extreme projection vector and
+ * its sign (negative iff c >= m).  Scalars: edge j owns 4 floats at
+ * scalars_offset + 16*j: g_e = (|u|^2 - |v|^2)/2 (zero for ANGULAR), |e|,
+ * w_reg, sqrt(L)*w_res. */
 typedef struct {
     int64_t n;
     int32_t d, R, L, m, metric, flags, entry;
     int64_t node_stride;    /* bytes */
     int64_t codes_offset;   /* bytes, within a record */
     int64_t scalars_offset; /* bytes, within a record */
+    int64_t code_bytes;     /* bytes of codes per edge */
 } peos_layout;
 
 /*

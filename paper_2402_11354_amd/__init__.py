@@ -39,7 +39,7 @@ class peos_layout(ctypes.Structure):
                 ("L", ctypes.c_int32), ("m", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("entry", ctypes.c_int32),
                 ("node_stride", ctypes.c_int64), ("codes_offset", ctypes.c_int64),
-                ("scalars_offset", ctypes.c_int64)]
+                ("scalars_offset", ctypes.c_int64), ("code_bytes", ctypes.c_int64)]
 
 
 _lib = None

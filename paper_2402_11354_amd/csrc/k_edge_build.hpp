@@ -73,6 +73,7 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
 
     uint8_t* rv = a.rec + v * a.node_stride;
     uint8_t* codes = rv + a.codes_off;
+    const int cbytes = (L + 4) & ~3;  // round_up(L + 1, 4)
     float* scal = reinterpret_cast<float*>(rv + a.scal_off);
 
     for (int j0 = 0; j0 < R; j0 += 4) {
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; bp = op; }
             }
             if (s == 0 && j < R)
-                codes[(1 + i) * R + j] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+                codes[j * cbytes + 1 + i] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
         }
         __syncthreads();
         // regular part: c = sum(s_i) / L', residual in place
@@ -174,7 +175,10 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 float op = __shfl_xor(bp, o, 16);
                 if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; bp = op; }
             }
-            if (s == 0 && j < R) codes[j] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+            if (s == 0 && j < R) {
+                codes[j * cbytes] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+                for (int pz = L + 1; pz < cbytes; ++pz) codes[j * cbytes + pz] = 0;
+            }
         }
         // scalars: g_e, |e|, w_reg, sqrt(L) w_res
         if (s == 0 && j < R) {
@@ -190,10 +194,7 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 }
                 if (a.metric == 0) ge = 0.5f * (nu2 - nv2);
             }
-            scal[0 * R + j] = ge;
-            scal[1 * R + j] = ne;
-            scal[2 * R + j] = wreg;
-            scal[3 * R + j] = swres;
+            *reinterpret_cast<float4*>(scal + 4 * j) = make_float4(ge, ne, wreg, swres);
         }
         __syncthreads();
     }

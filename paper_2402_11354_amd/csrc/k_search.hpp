@@ -151,15 +151,18 @@ __device__ __forceinline__ void gather_distances(const float* base, int d, const
 __device__ __forceinline__ void distances(const float* base, int d, const uint32_t* Su, int ns,
                                           const float* qv, int metric, float inv_qn, float* Sdist)
 {
+    // at least 4 lanes per vector: more survivors than 16 take several rounds
     if (ns <= 4) gather_distances<16>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
     else if (ns <= 8) gather_distances<8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 16) gather_distances<4>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 32) gather_distances<2>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else gather_distances<1>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else gather_distances<4>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
 }
 
+#ifndef PEOS_SEARCH_WAVES_PER_EU
+#define PEOS_SEARCH_WAVES_PER_EU 5
+#endif
+
 template <int MAXL>
-__global__ __launch_bounds__(64) void k_search(SearchArgs a)
+__global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchArgs a)
 {
     extern __shared__ __align__(16) unsigned char sm[];
     const int lane = lane_id();
@@ -169,11 +172,10 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a)
     float* qv = reinterpret_cast<float*>(sm);
     float* tab = qv + d;
     float* Ld = tab + (L + 1) * tabw;
-    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + a.listcap);
-    // the merge buffer holds the list plus up to one wave of survivors
-    float* Md = reinterpret_cast<float*>(Li + a.listcap);
-    uint32_t* Mi = reinterpret_cast<uint32_t*>(Md + a.listcap + kWave);
-    uint32_t* hash = Mi + a.listcap + kWave;
+    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + a.listcap + kWave);
+    // the list has room for one wave of survivors beyond its capacity while
+    // a merge is in progress
+    uint32_t* hash = Li + a.listcap + kWave;
     float* Sd = reinterpret_cast<float*>(hash + hcap);
     uint32_t* Si = reinterpret_cast<uint32_t*>(Sd + kWave);
     uint32_t* Su = Si + kWave;
@@ -254,24 +256,23 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a)
                 const bool testing = (a.mode == 0) && full;
 
                 // loads that depend on v only
+                constexpr int NCW = (MAXL + 4) / 4;  // code dwords per edge (max)
+                const int ncw = (L + 4) >> 2;
                 int32_t u = -1;
-                float sg = 0.f, se = 0.f, sw = 0.f, sr = 0.f;
-                uint8_t cd[MAXL + 1];
+                float4 sc4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                uint32_t cw[NCW];
                 if (lane < R) {
                     u = a.graph[(int64_t)vid * R + lane];
                     if (testing) {
                         const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
-                        const float* sc = reinterpret_cast<const float*>(rv + a.scal_off);
-                        sg = sc[lane];
-                        se = sc[R + lane];
-                        sw = sc[2 * R + lane];
-                        sr = sc[3 * R + lane];
-                        const uint8_t* cb = rv + a.codes_off + lane;
+                        sc4 = reinterpret_cast<const float4*>(rv + a.scal_off)[lane];
+                        const uint32_t* cb = reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
 #pragma unroll
-                        for (int i = 0; i <= MAXL; ++i)
-                            if (i <= L) cd[i] = cb[i * R];
+                        for (int i = 0; i < NCW; ++i)
+                            if (i < ncw) cw[i] = cb[i];
                     }
                 }
+                const float sg = sc4.x, se = sc4.y, sw = sc4.z, sr = sc4.w;
                 const bool valid = u >= 0;
                 st_edges += popc(ballot(valid));
                 bool vis = false;
@@ -301,8 +302,8 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a)
                                 float h1 = 0.f;
 #pragma unroll
                                 for (int i = 1; i <= MAXL; ++i)
-                                    if (i <= L) h1 += tab[i * tabw + cd[i]];
-                                const float h2 = tab[cd[0]];
+                                    if (i <= L) h1 += tab[i * tabw + ((cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu)];
+                                const float h2 = tab[cw[0] & 0xFFu];
                                 const float H = sw * h1 + sr * h2;
                                 const float var = sw * sw + sr * sr - a.kappa * A * A;
                                 const float T = A * a.eta + a.c_eps * sqrtf(var);
@@ -366,10 +367,14 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a)
                 __syncthreads();
                 if (nS == 0) continue;
 
-                // merge: M := sort(list + S); list := compaction of M
+                // merge in place.  Every list entry moves right by the number
+                // of survivors with a smaller key; chunks are moved from the
+                // back so no entry is overwritten before it is read, then the
+                // survivors fill the gaps.
                 int mpos = 0x7fffffff;
+                uint64_t sk = 0;
                 if (lane < nS) {
-                    const uint64_t sk = sort_key(Sd[lane], Si[lane]);
+                    sk = sort_key(Sd[lane], Si[lane]);
                     int r = 0;
                     for (int t = 0; t < nS; ++t) r += sort_key(Sd[t], Si[t]) < sk;
                     int lo = 0, hi = size;
@@ -379,17 +384,28 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a)
                         else hi = mid;
                     }
                     mpos = r + lo;
-                    Md[mpos] = Sd[lane];
-                    Mi[mpos] = Si[lane];
                 }
-                for (int p = lane; p < size; p += kWave) {
-                    const float dd = Ld[p];
-                    const uint32_t id = Li[p];
-                    const uint64_t k = sort_key(dd, id);
+                for (int c0 = ((size - 1) / kWave) * kWave; c0 >= 0; c0 -= kWave) {
+                    const int p = c0 + lane;
+                    float dd = 0.f;
+                    uint32_t id = 0;
                     int sh = 0;
-                    for (int t = 0; t < nS; ++t) sh += sort_key(Sd[t], Si[t]) < k;
-                    Md[p + sh] = dd;
-                    Mi[p + sh] = id;
+                    if (p < size) {
+                        dd = Ld[p];
+                        id = Li[p];
+                        const uint64_t k = sort_key(dd, id);
+                        for (int t = 0; t < nS; ++t) sh += sort_key(Sd[t], Si[t]) < k;
+                    }
+                    __syncthreads();
+                    if (p < size && sh) {
+                        Ld[p + sh] = dd;
+                        Li[p + sh] = id;
+                    }
+                    __syncthreads();
+                }
+                if (lane < nS) {
+                    Ld[mpos] = Sd[lane];
+                    Li[mpos] = Si[lane];
                 }
                 int minpos = mpos;
 #pragma unroll
@@ -398,20 +414,24 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a)
                     minpos = other < minpos ? other : minpos;
                 }
                 __syncthreads();
+                // compaction, front to back: entries beyond ef leave once
+                // expanded, and at most cap entries stay
                 const int total = size + nS;
-                int w = 0;
-                for (int c0 = 0; c0 < total; c0 += kWave) {
+                int w = efq < total ? efq : total;
+                for (int c0 = w; c0 < total; c0 += kWave) {
                     const int p = c0 + lane;
                     const bool vld = p < total;
-                    const uint32_t id = vld ? Mi[p] : 0u;
-                    const float dd = vld ? Md[p] : 0.f;
-                    const bool kp = vld && (p < efq || !(id & kExpanded));
+                    const uint32_t id = vld ? Li[p] : 0u;
+                    const float dd = vld ? Ld[p] : 0.f;
+                    const bool kp = vld && !(id & kExpanded);
                     const uint64_t kmask = ballot(kp);
                     const int ix = w + popc(kmask & lanemask_lt());
-                    if (kp && ix < cap) {
+                    __syncthreads();
+                    if (kp && ix < cap + kWave) {
                         Ld[ix] = dd;
                         Li[ix] = id;
                     }
+                    __syncthreads();
                     w += popc(kmask);
                 }
                 if (w > cap && a.pool <= 0) status |= kStatusPoolFull;

@@ -55,11 +55,13 @@ struct Layout {
     int64_t stride, codes_off, scal_off;
 };
 
+// record of a node: codes [R][round_up(L+1, 4)] bytes | pad to 16 | scalars
+// [R][4] floats | pad to 128
 Layout layout_of(int R, int L)
 {
     Layout l;
     l.codes_off = 0;
-    l.scal_off = round_up((int64_t)(L + 1) * R, 16);
+    l.scal_off = round_up((int64_t)R * round_up(L + 1, 4), 16);
     l.stride = round_up(l.scal_off + 16LL * R, 128);
     return l;
 }
@@ -144,7 +146,10 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool)
         t = g_tune;
     }
     const int lmin = pool > efmax ? pool : efmax;
-    int lc = pool > 0 ? lmin : (6 * efmax > 256 ? 6 * efmax : 256);
+    // unbounded queue: room for 16 ef entries (the list of the printed Alg. 1
+    // stays well below that in practice), at most 2048
+    int lc = pool > 0 ? lmin : (16 * efmax > 256 ? 16 * efmax : 256);
+    if (pool <= 0 && lc > 2048) lc = lmin > 2048 ? lmin : 2048;
     if (t.listcap > 0) lc = t.listcap > lmin ? t.listcap : lmin;
     lc = (int)round_up(lc, 64);
     if (lc > kMaxEf * 2) lc = kMaxEf * 2;
@@ -154,8 +159,8 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool)
     if (t.hash_log2 > 0) hl = t.hash_log2;
     p.hcap_log2 = hl;
     p.visit_limit = (3 << hl) / 4;
-    // qv | table | list (lc) | merge buffer (lc + 64) | hash | 4 staging arrays of 64
-    p.lds = 4LL * ix->d + 4LL * (ix->L + 1) * 2 * ix->m + 8LL * lc + 8LL * (lc + 64) + (4LL << hl) +
+    // qv | table | list (lc + 64 during a merge) | hash | 4 staging arrays of 64
+    p.lds = 4LL * ix->d + 4LL * (ix->L + 1) * 2 * ix->m + 8LL * (lc + 64) + (4LL << hl) +
             4LL * 4 * 64;
     int64_t per_cu = kLdsPerCu / p.lds;
     if (per_cu < 1) per_cu = 1;
@@ -316,6 +321,7 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
     out->node_stride = ix->node_stride;
     out->codes_offset = ix->codes_off;
     out->scalars_offset = ix->scal_off;
+    out->code_bytes = round_up(ix->L + 1, 4);
     return PEOS_OK;
 }
 

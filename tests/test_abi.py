@@ -34,10 +34,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_index_bytes_layout():
     ib, wb = P.peos_index_bytes(1000, 128, 32, 8, 16)
-    # per node: (L+1)*R code bytes padded to 16, then 4 floats per edge, padded to 128
+    # per node: R * round_up(L+1, 4) code bytes padded to 16, then 4 floats per
+    # edge, padded to 128
     assert ib == 1000 * 896 and wb > 0
     ib, _ = P.peos_index_bytes(10, 32, 16, 4, 16)
     assert ib == 10 * 384
+    ib, _ = P.peos_index_bytes(10, 960, 32, 16, 16)
+    assert ib == 10 * 1152
 
 
 @pytest.mark.parametrize("args", [

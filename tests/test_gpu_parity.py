@@ -60,11 +60,12 @@ def angular():
 def read_records(case):
     lay = case.index.layout()
     mem = case.index._keep[-1].cpu().numpy()
-    n, R, L = lay.n, lay.R, lay.L
+    n, R, L, cb = lay.n, lay.R, lay.L, lay.code_bytes
     rec = mem.reshape(n, lay.node_stride)
-    codes = rec[:, lay.codes_offset:lay.codes_offset + (L + 1) * R].reshape(n, L + 1, R)
+    codes = rec[:, lay.codes_offset:lay.codes_offset + cb * R].reshape(n, R, cb)
+    assert np.all(codes[:, :, L + 1:] == 0)
     sc = rec[:, lay.scalars_offset:lay.scalars_offset + 16 * R].copy().view(np.float32)
-    return codes.transpose(0, 2, 1), sc.reshape(n, 4, R).transpose(0, 2, 1)
+    return codes[:, :, :L + 1], sc.reshape(n, R, 4)
 
 
 @pytest.mark.parametrize("which", ["tiny", "angular"])
