@@ -53,10 +53,22 @@ def main():
     ap.add_argument("--ef", type=int, default=64)
     ap.add_argument("--pool", default="ef")
     ap.add_argument("--eps", type=float, default=0.1)
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="with --profile-only: also run one device copy of this size (a "
-                         "known-traffic kernel for calibrating memory counters)")
+    ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
+                    help="only run one device copy of MIB MiB (a kernel of known traffic for "
+                         "calibrating memory counters) and exit")
     args = ap.parse_args()
+
+    if args.copy_calibrate:
+        # a plain device copy of known size, for scaling memory counters
+        import torch
+        dev = torch.device("cuda:0")
+        src = torch.ones(args.copy_calibrate << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copied {args.copy_calibrate} MiB")
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; sharding across GPUs is a "
@@ -139,13 +151,6 @@ def main():
         st = stats.cpu().numpy()
         log(f"per query: expansions {st[:, 0].mean():.1f} tests {st[:, 3].mean():.1f} "
             f"ndist {st[:, 9].mean():.1f}")
-        if args.copy_mib:
-            src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
-            dst = torch.empty_like(src)
-            torch.cuda.synchronize()
-            dst.copy_(src)
-            torch.cuda.synchronize()
-            log(f"copied {args.copy_mib} MiB")
         return
 
     def sweep(pool_spec, eps, mode):

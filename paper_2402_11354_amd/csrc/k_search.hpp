@@ -92,73 +92,102 @@ __device__ __forceinline__ bool bitmap_test(const uint32_t* bm, uint32_t u)
 // tree levels that pair segments of different lanes are xor shuffles (an add
 // is commutative, so both partners get the same bits), the remaining levels
 // are local.  Angular distance = fma(-sum, 1/|q|, 1).
-template <int G>
+template <int G, int PER, int K>
 __device__ __forceinline__ void gather_distances(const float* base, int d, const uint32_t* Su, int ns,
                                                  const float* qv, int metric, float inv_qn,
                                                  float* Sdist)
 {
 #pragma clang fp contract(off)
-    constexpr int NP = 16 / G;  // segments per lane
+    constexpr int NP = 16 / G;        // segments per lane
+    constexpr int SPR = kWave / G;    // vectors per pass of the wave, per slot
+    static_assert(K % NP == 0, "a load step must cover whole segment rounds");
     const int lane = lane_id();
     const int t = lane / G;
     const int s = lane % G;
     const int nch = d >> 2;
     const float4* q4 = reinterpret_cast<const float4*>(qv);
-    for (int b0 = 0; b0 < ns; b0 += kWave / G) {
-        const int idx = b0 + t;
-        const bool act = idx < ns;
-        float part[NP];
+    // lane s of a group reads chunks c = s + G*k, k = 0, 1, ...; chunk number
+    // k of the lane belongs to its segment k mod NP, so each segment still
+    // sums its chunks in increasing c.  K loads per vector are issued before
+    // any of them is used.
+    for (int b0 = 0; b0 < ns; b0 += SPR * PER) {
+        float part[PER][NP];
+        const float4* x4[PER];
+        bool act[PER];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) part[j] = 0.f;
-        if (act) {
-            const float4* x4 = reinterpret_cast<const float4*>(base + (int64_t)Su[idx] * d);
+        for (int pp = 0; pp < PER; ++pp) {
+            const int idx = b0 + t + pp * SPR;
+            act[pp] = idx < ns;
+            x4[pp] = reinterpret_cast<const float4*>(base + (int64_t)(act[pp] ? Su[idx] : 0u) * d);
 #pragma unroll
-            for (int j = 0; j < NP; ++j) {
-                float acc = 0.f;
-                for (int c = s + j * G; c < nch; c += 16) {
-                    const float4 x = x4[c];
-                    const float4 q = q4[c];
-                    if (metric == 0) {
-                        const float t0 = x.x - q.x, t1 = x.y - q.y, t2 = x.z - q.z, t3 = x.w - q.w;
-                        acc = fmaf(t0, t0, acc);
-                        acc = fmaf(t1, t1, acc);
-                        acc = fmaf(t2, t2, acc);
-                        acc = fmaf(t3, t3, acc);
-                    } else {
-                        acc = fmaf(x.x, q.x, acc);
-                        acc = fmaf(x.y, q.y, acc);
-                        acc = fmaf(x.z, q.z, acc);
-                        acc = fmaf(x.w, q.w, acc);
+            for (int j = 0; j < NP; ++j) part[pp][j] = 0.f;
+        }
+        for (int k0 = 0; s + G * k0 < nch; k0 += K) {
+            float4 xv[PER][K];
+#pragma unroll
+            for (int pp = 0; pp < PER; ++pp)
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    const int c = s + G * (k0 + kk);
+                    if (act[pp] && c < nch) xv[pp][kk] = x4[pp][c];
+                }
+#pragma unroll
+            for (int pp = 0; pp < PER; ++pp)
+#pragma unroll
+                for (int kk = 0; kk < K; ++kk) {
+                    const int c = s + G * (k0 + kk);
+                    if (act[pp] && c < nch) {
+                        const float4 x = xv[pp][kk];
+                        const float4 q = q4[c];
+                        float acc = part[pp][kk % NP];
+                        if (metric == 0) {
+                            const float t0 = x.x - q.x, t1 = x.y - q.y, t2 = x.z - q.z, t3 = x.w - q.w;
+                            acc = fmaf(t0, t0, acc);
+                            acc = fmaf(t1, t1, acc);
+                            acc = fmaf(t2, t2, acc);
+                            acc = fmaf(t3, t3, acc);
+                        } else {
+                            acc = fmaf(x.x, q.x, acc);
+                            acc = fmaf(x.y, q.y, acc);
+                            acc = fmaf(x.z, q.z, acc);
+                            acc = fmaf(x.w, q.w, acc);
+                        }
+                        part[pp][kk % NP] = acc;
                     }
                 }
-                part[j] = acc;
-            }
         }
-        // tree levels across lanes (segment index bits below log2 G)
 #pragma unroll
-        for (int o = 1; o < G; o <<= 1)
+        for (int pp = 0; pp < PER; ++pp) {
+            // tree levels across lanes (segment index bits below log2 G)
 #pragma unroll
-            for (int j = 0; j < NP; ++j) part[j] = part[j] + __shfl_xor(part[j], o, G);
-        // remaining levels inside the lane
+            for (int o = 1; o < G; o <<= 1)
 #pragma unroll
-        for (int h = 1; h < NP; h <<= 1)
+                for (int j = 0; j < NP; ++j) part[pp][j] = part[pp][j] + __shfl_xor(part[pp][j], o, G);
+            // remaining levels inside the lane
 #pragma unroll
-            for (int j = 0; j < NP; j += 2 * h) part[j] = part[j] + part[j + h];
-        if (act && s == 0) Sdist[idx] = (metric == 0) ? part[0] : fmaf(-part[0], inv_qn, 1.f);
+            for (int h = 1; h < NP; h <<= 1)
+#pragma unroll
+                for (int j = 0; j < NP; j += 2 * h) part[pp][j] = part[pp][j] + part[pp][j + h];
+            const int idx = b0 + t + pp * SPR;
+            if (act[pp] && s == 0)
+                Sdist[idx] = (metric == 0) ? part[pp][0] : fmaf(-part[pp][0], inv_qn, 1.f);
+        }
     }
 }
 
 __device__ __forceinline__ void distances(const float* base, int d, const uint32_t* Su, int ns,
                                           const float* qv, int metric, float inv_qn, float* Sdist)
 {
-    // at least 4 lanes per vector: more survivors than 16 take several rounds
-    if (ns <= 4) gather_distances<16>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 8) gather_distances<8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else gather_distances<4>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    // 4..16 lanes per vector; each lane keeps at most 8 float4 loads in
+    // flight (one round trip for up to 16 vectors of 128 floats)
+    if (ns <= 4) gather_distances<16, 1, 8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 8) gather_distances<8, 1, 8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 16) gather_distances<4, 1, 8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else gather_distances<4, 2, 4>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
 }
 
 #ifndef PEOS_SEARCH_WAVES_PER_EU
-#define PEOS_SEARCH_WAVES_PER_EU 5
+#define PEOS_SEARCH_WAVES_PER_EU 4
 #endif
 
 template <int MAXL>
@@ -215,12 +244,12 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             }
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
             if (lane == 0) Su[0] = (uint32_t)a.entry;
-            __syncthreads();
+            wave_sync();
             distances(a.base, d, Su, 1, qv, a.metric, inv_qn, Sdist);
             if (lane == 0) {
                 hash_insert(hash, a.hcap_log2, (uint32_t)a.entry);
             }
-            __syncthreads();
+            wave_sync();
             if (lane == 0) {
                 Ld[0] = Sdist[0];
                 Li[0] = (uint32_t)a.entry;
@@ -230,15 +259,16 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             bool spilled = false;
             st_ndist = 1;
             int lb = 0;  // every entry before lb is expanded
-            __syncthreads();
+            wave_sync();
 
+            constexpr int NCW = (MAXL + 4) / 4;  // code dwords per edge (max)
+            const int ncw = (L + 4) >> 2;
             for (;;) {
                 // pop: first unexpanded entry of the list
                 int pos = -1;
                 for (int c0 = lb; c0 < size; c0 += kWave) {
                     const int p = c0 + lane;
-                    const bool un = p < size && !(Li[p] & kExpanded);
-                    const uint64_t mk = ballot(un);
+                    const uint64_t mk = ballot(p < size && !(Li[p] & kExpanded));
                     if (mk) {
                         pos = c0 + __ffsll((unsigned long long)mk) - 1;
                         break;
@@ -246,27 +276,28 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 if (pos < 0) break;
                 lb = pos + 1;
-                const uint32_t vid = Li[pos] & kIdMask;
+                const uint32_t vid = wave_uniform(Li[pos] & kIdMask);
                 const float dv = Ld[pos];
                 const bool full = size >= efq;
                 const float delta = full ? Ld[efq - 1] : INFINITY;
-                __syncthreads();
+                wave_sync();
                 if (lane == 0) Li[pos] = vid | kExpanded;
                 ++st_exp;
                 const bool testing = (a.mode == 0) && full;
 
-                // loads that depend on v only
-                constexpr int NCW = (MAXL + 4) / 4;  // code dwords per edge (max)
-                const int ncw = (L + 4) >> 2;
+                // ids, codes and scalars depend on v only: one round trip
                 int32_t u = -1;
                 float4 sc4 = make_float4(0.f, 0.f, 0.f, 0.f);
                 uint32_t cw[NCW];
+#pragma unroll
+                for (int i = 0; i < NCW; ++i) cw[i] = 0u;
                 if (lane < R) {
                     u = a.graph[(int64_t)vid * R + lane];
                     if (testing) {
                         const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
                         sc4 = reinterpret_cast<const float4*>(rv + a.scal_off)[lane];
-                        const uint32_t* cb = reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
+                        const uint32_t* cb =
+                            reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
 #pragma unroll
                         for (int i = 0; i < NCW; ++i)
                             if (i < ncw) cw[i] = cb[i];
@@ -290,7 +321,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                             kind = 0;
                             pass = num < 0.f;
                         } else {
-                            const float A = num / ((a.metric == 0 ? qn : 1.f) * se);
+                            const float A = num * __builtin_amdgcn_rcpf((a.metric == 0 ? qn : 1.f) * se);
                             if (A >= 1.f) {
                                 kind = 1;
                                 pass = false;
@@ -306,7 +337,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                                 const float h2 = tab[cw[0] & 0xFFu];
                                 const float H = sw * h1 + sr * h2;
                                 const float var = sw * sw + sr * sr - a.kappa * A * A;
-                                const float T = A * a.eta + a.c_eps * sqrtf(var);
+                                const float T = A * a.eta + a.c_eps * __builtin_amdgcn_sqrtf(var);
                                 pass = H >= T;
                             }
                         }
@@ -326,13 +357,13 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 if (!spilled && nvis + ns > a.visit_limit) {
                     for (int64_t w = lane; w < a.spill_words; w += kWave) bitmap[w] = 0u;
                     __threadfence();
-                    __syncthreads();
+                    wave_sync();
                     for (int t = lane; t < hcap; t += kWave) {
                         const uint32_t k = hash[t];
                         if (k != kEmpty) atomicOr(bitmap + (k >> 5), 1u << (k & 31u));
                     }
                     __threadfence();
-                    __syncthreads();
+                    wave_sync();
                     spilled = true;
                     status |= kStatusSpill;
                 }
@@ -342,70 +373,66 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                     Su[popc(smask & lanemask_lt())] = (uint32_t)u;
                 }
                 nvis += ns;
-                __syncthreads();
+                wave_sync();
                 distances(a.base, d, Su, ns, qv, a.metric, inv_qn, Sdist);
                 st_ndist += ns;
-                __syncthreads();
+                wave_sync();
 
-                // survivors that enter the list
+                // survivors that enter the list stay in their own lanes
+                // (lane t = survivor t) with their sort keys in registers
                 bool keep = false;
                 float dt = 0.f;
                 uint32_t ut = 0;
+                uint64_t skey = ~0ull;
                 if (lane < ns) {
                     dt = Sdist[lane];
                     ut = Su[lane];
                     keep = !full || dt < delta;
+                    if (keep) skey = sort_key(dt, ut);
                 }
                 const uint64_t km = ballot(keep);
                 const int nS = popc(km);
-                if (keep) {
-                    const int ix = popc(km & lanemask_lt());
-                    Sd[ix] = dt;
-                    Si[ix] = ut;
-                }
                 st_ins += nS;
-                __syncthreads();
                 if (nS == 0) continue;
 
-                // merge in place.  Every list entry moves right by the number
-                // of survivors with a smaller key; chunks are moved from the
-                // back so no entry is overwritten before it is read, then the
-                // survivors fill the gaps.
-                int mpos = 0x7fffffff;
-                uint64_t sk = 0;
-                if (lane < nS) {
-                    sk = sort_key(Sd[lane], Si[lane]);
-                    int r = 0;
-                    for (int t = 0; t < nS; ++t) r += sort_key(Sd[t], Si[t]) < sk;
-                    int lo = 0, hi = size;
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (sort_key(Ld[mid], Li[mid]) < sk) lo = mid + 1;
-                        else hi = mid;
-                    }
-                    mpos = r + lo;
+                // merge in place: rank of each survivor among the survivors,
+                // number of list entries below it (lo), and for each list
+                // entry the number of survivors below it (its shift).  Keys
+                // are broadcast from the survivor lanes; chunks of the list
+                // move from the back so nothing is overwritten unread.
+                int rS = 0;
+                for (uint64_t mm = km; mm; mm &= mm - 1) {
+                    const int t = __ffsll((unsigned long long)mm) - 1;
+                    const uint64_t kt = readlane64(skey, t);
+                    rS += kt < skey;
                 }
+                int lo = 0;
                 for (int c0 = ((size - 1) / kWave) * kWave; c0 >= 0; c0 -= kWave) {
                     const int p = c0 + lane;
-                    float dd = 0.f;
-                    uint32_t id = 0;
+                    const bool in = p < size;
+                    const float dd = in ? Ld[p] : 0.f;
+                    const uint32_t id = in ? Li[p] : 0u;
+                    const uint64_t lk = in ? sort_key(dd, id) : ~0ull;
                     int sh = 0;
-                    if (p < size) {
-                        dd = Ld[p];
-                        id = Li[p];
-                        const uint64_t k = sort_key(dd, id);
-                        for (int t = 0; t < nS; ++t) sh += sort_key(Sd[t], Si[t]) < k;
+                    for (uint64_t mm = km; mm; mm &= mm - 1) {
+                        const int t = __ffsll((unsigned long long)mm) - 1;
+                        const uint64_t kt = readlane64(skey, t);
+                        const bool below = lk < kt;
+                        const int nb = popc(ballot(below));
+                        lo += (lane == t) ? nb : 0;
+                        sh += (in && !below) ? 1 : 0;
                     }
-                    __syncthreads();
-                    if (p < size && sh) {
+                    wave_sync();
+                    if (in && sh && p + sh < cap + kWave) {
                         Ld[p + sh] = dd;
                         Li[p + sh] = id;
                     }
-                    __syncthreads();
+                    wave_sync();
                 }
-                if (lane < nS) {
-                    Ld[mpos] = Sd[lane];
-                    Li[mpos] = Si[lane];
+                const int mpos = keep ? lo + rS : 0x7fffffff;
+                if (keep && mpos < cap + kWave) {
+                    Ld[mpos] = dt;
+                    Li[mpos] = ut;
                 }
                 int minpos = mpos;
 #pragma unroll
@@ -413,33 +440,38 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                     const int other = __shfl_xor(minpos, o, kWave);
                     minpos = other < minpos ? other : minpos;
                 }
-                __syncthreads();
+                wave_sync();
                 // compaction, front to back: entries beyond ef leave once
-                // expanded, and at most cap entries stay
+                // expanded, and at most cap entries stay (nothing to do when
+                // cap = ef: everything beyond is dropped)
                 const int total = size + nS;
                 int w = efq < total ? efq : total;
-                for (int c0 = w; c0 < total; c0 += kWave) {
-                    const int p = c0 + lane;
-                    const bool vld = p < total;
-                    const uint32_t id = vld ? Li[p] : 0u;
-                    const float dd = vld ? Ld[p] : 0.f;
-                    const bool kp = vld && !(id & kExpanded);
-                    const uint64_t kmask = ballot(kp);
-                    const int ix = w + popc(kmask & lanemask_lt());
-                    __syncthreads();
-                    if (kp && ix < cap + kWave) {
-                        Ld[ix] = dd;
-                        Li[ix] = id;
+                if (cap > efq) {
+                    for (int c0 = w; c0 < total; c0 += kWave) {
+                        const int p = c0 + lane;
+                        const bool vld = p < total;
+                        const uint32_t id = vld ? Li[p] : 0u;
+                        const float dd = vld ? Ld[p] : 0.f;
+                        const bool kp = vld && !(id & kExpanded);
+                        const uint64_t kmask = ballot(kp);
+                        const int ix = w + popc(kmask & lanemask_lt());
+                        wave_sync();
+                        if (kp && ix < cap + kWave) {
+                            Ld[ix] = dd;
+                            Li[ix] = id;
+                        }
+                        wave_sync();
+                        w += popc(kmask);
                     }
-                    __syncthreads();
-                    w += popc(kmask);
+                } else {
+                    w = total;
                 }
                 if (w > cap && a.pool <= 0) status |= kStatusPoolFull;
                 size = w < cap ? w : cap;
                 minpos = wave_uniform(minpos);
                 lb = lb < efq ? lb : efq;
                 lb = lb < minpos ? lb : minpos;
-                __syncthreads();
+                wave_sync();
             }
         } else {
             status |= kStatusZeroQuery;
@@ -466,7 +498,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             o[10] = st_ins;
             o[11] = status;
         }
-        __syncthreads();
+        wave_sync();
     }
 }
 

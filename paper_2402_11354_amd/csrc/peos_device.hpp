@@ -15,6 +15,16 @@ __device__ __forceinline__ int lane_id() { return __lane_id(); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
+// Ordering point for LDS traffic between the lanes of a one-wave workgroup.
+// A wave's LDS operations execute in order, so a compiler-level barrier
+// (a wavefront-scope fence) is enough; unlike __syncthreads it does not wait
+// for outstanding global loads, which lets prefetches stay in flight.
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // lanes below this one
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
@@ -28,6 +38,14 @@ template <typename T>
 __device__ __forceinline__ T wave_uniform(T v)
 {
     return __builtin_amdgcn_readfirstlane(v);
+}
+
+// value of v in lane t (t uniform across the wave), as a scalar
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int t)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, t);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), t);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
 __device__ __forceinline__ float wave_sum(float v)
