@@ -53,6 +53,7 @@ def main():
     ap.add_argument("--ef", type=int, default=64)
     ap.add_argument("--pool", default="ef")
     ap.add_argument("--eps", type=float, default=0.1)
+    ap.add_argument("--hash-cap", type=int, default=0, help="with --profile-only: visited-hash capacity")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (a kernel of known traffic for "
                          "calibrating memory counters) and exit")
@@ -144,6 +145,7 @@ def main():
         return wall, step_ms, table_ms, search_ms
 
     if args.profile_only:
+        P.peos_set_search_tuning(args.hash_cap, 0, 0)
         cfg = (args.ef, pool_of(args.pool, args.ef), args.eps, P.PEOS_MODE_PEOS)
         wall, sms, tms, srch = timed(cfg, args.steps, args.warmup)
         log(f"profile-only {cfg}: step {sms.mean():.3f} ms search {srch.mean():.3f} ms "
@@ -190,12 +192,23 @@ def main():
     pe, pe_ok = best(pe_sweeps.values())
     ex, ex_ok = best(ex_sweeps.values())
 
-    log(f"timed PEOS {pe['cfg']} ({args.steps} steps)")
+    from paper_2402_11354_amd import autotune
+
+    def tuned(cfg):
+        ef, pool, eps, mode = cfg
+        cap, _ = autotune.tune(index, qt, w.k, ef, pool=pool, eps=eps, mode=mode,
+                               use_cache=False, log=log)
+        return cap
+
+    pe_cap = tuned(pe["cfg"])
+    log(f"timed PEOS {pe['cfg']} hash_cap={pe_cap} ({args.steps} steps)")
     wall, step_ms, table_ms, search_ms = timed(pe["cfg"], args.steps, args.warmup)
     qps = nq * args.steps / wall
-    log(f"timed EXHAUSTIVE {ex['cfg']}")
+    ex_cap = tuned(ex["cfg"])
+    log(f"timed EXHAUSTIVE {ex['cfg']} hash_cap={ex_cap}")
     ex_wall, ex_step_ms, _, ex_search_ms = timed(ex["cfg"], args.steps, args.warmup)
     ex_qps = nq * args.steps / ex_wall
+    P.peos_set_search_tuning(0, 0, 0)
 
     # algorithmic bytes of one search launch, from the kernel's own counters
     code_bytes = 4 * ((w.L + 4) // 4)
@@ -239,7 +252,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L,
-                   "m": w.m, "eps": eps, "k": w.k, "ef": ef, "pool": pool,
+                   "m": w.m, "eps": eps, "k": w.k, "ef": ef, "pool": pool, "hash_cap": pe_cap,
                    "stop_rule": "hnsw (pool=ef)" if pool == ef else "unbounded queue (Alg. 1)",
                    "metric": "l2" if w.metric == 0 else "angular"},
         "recall": round(pe["recall"], 4),
@@ -247,6 +260,7 @@ def main():
         "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "exhaustive": {"value": round(ex_qps, 1), "ef": ex["cfg"][0], "pool": ex["cfg"][1],
+                       "hash_cap": ex_cap,
                        "recall": round(ex["recall"], 4), "recall_target_met": bool(ex_ok),
                        "p99_ms": round(float(np.percentile(ex_step_ms, 99)), 4),
                        "search_ms": round(float(ex_search_ms.mean()), 4),

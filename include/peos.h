@@ -209,9 +209,9 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
 /*
  * peos_set_search_tuning -- override the search kernel's launch plan for all
  * later calls in this process (0 keeps the automatic choice):
- *   hash_log2  visited-hash capacity 2^hash_log2 entries in LDS, 6..14; a
- *              query that visits more than 3/4 of it moves its visited set to
- *              a bitmap in the workspace (PEOS_STATUS_VISITED_SPILL);
+ *   hash_cap   visited-hash capacity in LDS, 64..16384 entries; a query that
+ *              visits more than 3/4 of it moves its visited set to a bitmap
+ *              in the workspace (PEOS_STATUS_VISITED_SPILL);
  *   listcap    candidate-list capacity in LDS (rounded up to a multiple of 64
  *              and to at least max(pool, ef)); with pool = 0 it is the
  *              kernel capacity that PEOS_STATUS_POOL_FULL refers to;
@@ -219,7 +219,7 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
  * Results do not depend on the tuning except through the pool capacity.
  * Errors: PEOS_EINVAL for values out of range.
  */
-int peos_set_search_tuning(int32_t hash_log2, int32_t listcap, int32_t slots);
+int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots);
 
 /* Message for a return code, and the thread-local message of the last error. */
 const char* peos_strerror(int code);

@@ -192,9 +192,9 @@ def peos_search(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, sta
                              _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)))
 
 
-def peos_set_search_tuning(hash_log2=0, listcap=0, slots=0):
+def peos_set_search_tuning(hash_cap=0, listcap=0, slots=0):
     """Override the search launch plan (0 = automatic); see include/peos.h."""
-    _check("peos_set_search_tuning", lib().peos_set_search_tuning(hash_log2, listcap, slots))
+    _check("peos_set_search_tuning", lib().peos_set_search_tuning(hash_cap, listcap, slots))
 
 
 def search(index, queries, k, ef, eps=0.1, mode=PEOS_MODE_PEOS, pool=0, kstride=None,

@@ -1,0 +1,86 @@
+"""Launch-plan autotuner for peos_search.
+
+The search kernel keeps each query's visited set in an LDS hash.  A larger hash
+avoids moving busy queries' visited sets to HBM but costs LDS, hence resident
+waves per CU; the best capacity depends on the graph, ef and the stopping rule.
+`tune` times peos_search with a few capacities on the caller's batch and sets
+the fastest with peos_set_search_tuning.  Results never depend on the choice
+(only speed does).  Choices are cached per device and problem shape in a JSON
+file (PEOS_TUNE_CACHE, default ~/.cache/peos_tune.json).
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import peos_search_ws_bytes, peos_set_search_tuning, search
+
+CACHE = os.environ.get("PEOS_TUNE_CACHE", os.path.expanduser("~/.cache/peos_tune.json"))
+HASH_CAPS = (1024, 1536, 1920, 2048, 3072, 4096, 8192)
+
+
+def _key(index, nq, k, ef, pool, mode):
+    lay = index.layout()
+    dev = torch.cuda.get_device_name(0)
+    return f"{dev}|n={lay.n}|d={lay.d}|R={lay.R}|L={lay.L}|m={lay.m}|nq={nq}|k={k}|ef={ef}|pool={pool}|mode={mode}"
+
+
+def _load():
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(cache):
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp%d" % os.getpid()
+        with open(tmp, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def tune(index, queries, k, ef, pool=0, eps=0.1, mode=0, caps=HASH_CAPS, reps=3, use_cache=True,
+         log=None):
+    """Pick and set the visited-hash capacity for this operating point.
+    Returns (hash_cap, {cap: ms})."""
+    nq = queries.shape[0]
+    key = _key(index, nq, k, ef, pool, mode)
+    cache = _load() if use_cache else {}
+    if key in cache:
+        cap = int(cache[key]["hash_cap"])
+        peos_set_search_tuning(cap, 0, 0)
+        return cap, cache[key].get("ms", {})
+    efmax = max(ef, k)
+    ws = torch.empty(peos_search_ws_bytes(index, nq, efmax, pool), dtype=torch.uint8,
+                     device=queries.device)
+    times = {}
+    for cap in caps:
+        peos_set_search_tuning(cap, 0, 0)
+        try:
+            search(index, queries, k, ef, eps=eps, mode=mode, pool=pool, ws=ws)  # warm-up
+        except RuntimeError:
+            continue  # LDS plan too large for this capacity
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            search(index, queries, k, ef, eps=eps, mode=mode, pool=pool, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        times[cap] = e0.elapsed_time(e1) / reps
+        if log:
+            log(f"autotune ef={ef} pool={pool} mode={mode} hash_cap={cap}: {times[cap]:.3f} ms")
+    best = min(times, key=times.get)
+    peos_set_search_tuning(best, 0, 0)
+    cache[key] = {"hash_cap": best, "ms": {str(c): round(t, 4) for c, t in times.items()}}
+    if use_cache:
+        _store(cache)
+    return best, times

@@ -45,35 +45,38 @@ struct SearchArgs {
     int k_all, ef_all, kstride;
     int d, R, L, m, metric, mode, entry;
     float eta, c_eps, kappa;
-    int listcap, pool, hcap_log2, visit_limit;
+    int listcap, listslack, pool, hcap, visit_limit;
 };
 
 constexpr int kStatusZeroQuery = 1;
 constexpr int kStatusPoolFull = 2;
 constexpr int kStatusSpill = 4;
 
-__device__ __forceinline__ uint32_t hash_slot(uint32_t u, int log2) { return (u * 0x9E3779B1u) >> (32 - log2); }
-
-__device__ __forceinline__ bool hash_lookup(const uint32_t* h, int log2, uint32_t u)
+// visited set: open addressing with linear probing over cap slots (any
+// capacity: the home slot is the multiplicative hash scaled to [0, cap))
+__device__ __forceinline__ uint32_t hash_slot(uint32_t u, uint32_t cap)
 {
-    const uint32_t mask = (1u << log2) - 1u;
-    uint32_t s = hash_slot(u, log2);
+    return (uint32_t)(((uint64_t)(u * 0x9E3779B1u) * cap) >> 32);
+}
+
+__device__ __forceinline__ bool hash_lookup(const uint32_t* h, uint32_t cap, uint32_t u)
+{
+    uint32_t s = hash_slot(u, cap);
     for (;;) {
         const uint32_t k = h[s];
         if (k == u) return true;
         if (k == kEmpty) return false;
-        s = (s + 1u) & mask;
+        s = (s + 1u == cap) ? 0u : s + 1u;
     }
 }
 
-__device__ __forceinline__ void hash_insert(uint32_t* h, int log2, uint32_t u)
+__device__ __forceinline__ void hash_insert(uint32_t* h, uint32_t cap, uint32_t u)
 {
-    const uint32_t mask = (1u << log2) - 1u;
-    uint32_t s = hash_slot(u, log2);
+    uint32_t s = hash_slot(u, cap);
     for (;;) {
         const uint32_t prev = atomicCAS(&h[s], kEmpty, u);
         if (prev == kEmpty || prev == u) return;
-        s = (s + 1u) & mask;
+        s = (s + 1u == cap) ? 0u : s + 1u;
     }
 }
 
@@ -196,18 +199,14 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
     extern __shared__ __align__(16) unsigned char sm[];
     const int lane = lane_id();
     const int d = a.d, R = a.R, L = a.L, m = a.m;
-    const int tabw = 2 * m;
-    const int hcap = 1 << a.hcap_log2;
+    const int hcap = a.hcap;
+    const int slack = a.listslack;  // room past the capacity during a merge
     float* qv = reinterpret_cast<float*>(sm);
     float* tab = qv + d;
-    float* Ld = tab + (L + 1) * tabw;
-    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + a.listcap + kWave);
-    // the list has room for one wave of survivors beyond its capacity while
-    // a merge is in progress
-    uint32_t* hash = Li + a.listcap + kWave;
-    float* Sd = reinterpret_cast<float*>(hash + hcap);
-    uint32_t* Si = reinterpret_cast<uint32_t*>(Sd + kWave);
-    uint32_t* Su = Si + kWave;
+    float* Ld = tab + (L + 1) * m;
+    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + a.listcap + slack);
+    uint32_t* hash = Li + a.listcap + slack;
+    uint32_t* Su = hash + hcap;
     float* Sdist = reinterpret_cast<float*>(Su + kWave);
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
 
@@ -236,18 +235,13 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             const float* qg = a.queries + qi * d;
             for (int t = lane; t < d; t += kWave) qv[t] = qg[t];
             const float* tg = a.tables + qi * (int64_t)(L + 1) * m;
-            for (int t = lane; t < (L + 1) * m; t += kWave) {
-                const float x = tg[t];
-                const int i = t / m, j = t - i * m;
-                tab[i * tabw + j] = x;
-                tab[i * tabw + m + j] = -x;
-            }
+            for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = tg[t];
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
             if (lane == 0) Su[0] = (uint32_t)a.entry;
             wave_sync();
             distances(a.base, d, Su, 1, qv, a.metric, inv_qn, Sdist);
             if (lane == 0) {
-                hash_insert(hash, a.hcap_log2, (uint32_t)a.entry);
+                hash_insert(hash, (uint32_t)hcap, (uint32_t)a.entry);
             }
             wave_sync();
             if (lane == 0) {
@@ -309,7 +303,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 bool vis = false;
                 if (valid)
                     vis = spilled ? bitmap_test(bitmap, (uint32_t)u)
-                                  : hash_lookup(hash, a.hcap_log2, (uint32_t)u);
+                                  : hash_lookup(hash, (uint32_t)hcap, (uint32_t)u);
                 st_skip += popc(ballot(vis));
                 const bool cand = valid && !vis;
                 bool pass = cand;
@@ -330,11 +324,17 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                                 pass = true;
                             } else {
                                 kind = 3;
+                                // code byte c: direction c mod m, negative iff c >= m
+                                auto signed_entry = [&](int i, uint32_t c) {
+                                    const bool neg = c >= (uint32_t)m;
+                                    const float v = tab[i * m + (int)(neg ? c - m : c)];
+                                    return neg ? -v : v;
+                                };
                                 float h1 = 0.f;
 #pragma unroll
                                 for (int i = 1; i <= MAXL; ++i)
-                                    if (i <= L) h1 += tab[i * tabw + ((cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu)];
-                                const float h2 = tab[cw[0] & 0xFFu];
+                                    if (i <= L) h1 += signed_entry(i, (cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu);
+                                const float h2 = signed_entry(0, cw[0] & 0xFFu);
                                 const float H = sw * h1 + sr * h2;
                                 const float var = sw * sw + sr * sr - a.kappa * A * A;
                                 const float T = A * a.eta + a.c_eps * __builtin_amdgcn_sqrtf(var);
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 if (pass) {
                     if (spilled) atomicOr(bitmap + ((uint32_t)u >> 5), 1u << ((uint32_t)u & 31u));
-                    else hash_insert(hash, a.hcap_log2, (uint32_t)u);
+                    else hash_insert(hash, (uint32_t)hcap, (uint32_t)u);
                     Su[popc(smask & lanemask_lt())] = (uint32_t)u;
                 }
                 nvis += ns;
@@ -423,14 +423,14 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                         sh += (in && !below) ? 1 : 0;
                     }
                     wave_sync();
-                    if (in && sh && p + sh < cap + kWave) {
+                    if (in && sh && p + sh < cap + slack) {
                         Ld[p + sh] = dd;
                         Li[p + sh] = id;
                     }
                     wave_sync();
                 }
                 const int mpos = keep ? lo + rS : 0x7fffffff;
-                if (keep && mpos < cap + kWave) {
+                if (keep && mpos < cap + slack) {
                     Ld[mpos] = dt;
                     Li[mpos] = ut;
                 }
@@ -456,7 +456,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                         const uint64_t kmask = ballot(kp);
                         const int ix = w + popc(kmask & lanemask_lt());
                         wave_sync();
-                        if (kp && ix < cap + kWave) {
+                        if (kp && ix < cap + slack) {
                             Ld[ix] = dd;
                             Li[ix] = id;
                         }

@@ -126,18 +126,19 @@ double norm_ppf(double p)
 }
 
 struct Tuning {
-    int hash_log2 = 0, listcap = 0, slots = 0;
+    int hash_cap = 0, listcap = 0, slots = 0;
 };
 std::mutex g_tune_mu;
 Tuning g_tune;
 
 struct SearchPlan {
-    int listcap, hcap_log2, visit_limit, slots;
+    int listcap, listslack, hcap, visit_limit, slots;
     int64_t lds;
     int64_t spill_words;
 };
 
-SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool)
+// per_query: k or ef given per query (then queries may have ef below efmax)
+SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bool per_query)
 {
     SearchPlan p;
     Tuning t;
@@ -154,14 +155,20 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool)
     lc = (int)round_up(lc, 64);
     if (lc > kMaxEf * 2) lc = kMaxEf * 2;
     p.listcap = lc;
-    int hl = 11;
-    while ((1 << hl) < 32 * efmax && hl < 13) ++hl;
-    if (t.hash_log2 > 0) hl = t.hash_log2;
-    p.hcap_log2 = hl;
-    p.visit_limit = (3 << hl) / 4;
-    // qv | table | list (lc + 64 during a merge) | hash | 4 staging arrays of 64
-    p.lds = 4LL * ix->d + 4LL * (ix->L + 1) * 2 * ix->m + 8LL * (lc + 64) + (4LL << hl) +
-            4LL * 4 * 64;
+    // visited hash: 32 slots per list entry, 2048 to 8192 (a query that visits
+    // more than 3/4 of it moves to the HBM bitmap)
+    int hc = 2048;
+    while (hc < 32 * efmax && hc < 8192) hc *= 2;
+    if (t.hash_cap > 0) hc = t.hash_cap;
+    p.hcap = hc;
+    p.visit_limit = (3 * hc) / 4;
+    // A merge writes up to one wave of survivors past the capacity; that room
+    // is needed only when entries past ef are kept (pool above ef, or the
+    // unbounded queue).  When the capacity is ef they are dropped instead.
+    p.listslack = (pool > 0 && pool <= efmax && !per_query) ? 0 : 64;
+    // qv | table | list (lc + slack) | hash | survivor ids and distances
+    p.lds = 4LL * ix->d + 4LL * (ix->L + 1) * ix->m + 8LL * (lc + p.listslack) + 4LL * hc +
+            4LL * 2 * 64;
     int64_t per_cu = kLdsPerCu / p.lds;
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 16) per_cu = 16;
@@ -197,14 +204,14 @@ extern "C" {
 
 const char* peos_last_error(void) { return g_err; }
 
-int peos_set_search_tuning(int32_t hash_log2, int32_t listcap, int32_t slots)
+int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots)
 {
-    if (hash_log2 != 0 && (hash_log2 < 6 || hash_log2 > 14))
-        return fail(PEOS_EINVAL, "hash_log2=%d not in [6, 14]", hash_log2);
+    if (hash_cap != 0 && (hash_cap < 64 || hash_cap > 16384))
+        return fail(PEOS_EINVAL, "hash_cap=%d not in [64, 16384]", hash_cap);
     if (listcap < 0 || listcap > 2 * kMaxEf) return fail(PEOS_EINVAL, "listcap=%d", listcap);
     if (slots < 0 || slots > kMaxSlots) return fail(PEOS_EINVAL, "slots=%d", slots);
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune.hash_log2 = hash_log2;
+    g_tune.hash_cap = hash_cap;
     g_tune.listcap = listcap;
     g_tune.slots = slots;
     return PEOS_OK;
@@ -368,7 +375,7 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
                        size_t ws_bytes, hipStream_t s)
 {
     const int efmax = ef_all > k_all ? ef_all : k_all;
-    SearchPlan plan = plan_search(ix, nq, efmax, pool);
+    SearchPlan plan = plan_search(ix, nq, efmax, pool, k != nullptr || ef != nullptr);
     WsLayout w = ws_layout(ix, nq, plan.spill_words);
     if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
     if (plan.lds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
@@ -407,8 +414,9 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.c_eps = (float)norm_ppf((double)eps);
     a.kappa = (float)((double)ix->L / (double)(ix->L + 1));
     a.listcap = plan.listcap;
+    a.listslack = plan.listslack;
     a.pool = pool;
-    a.hcap_log2 = plan.hcap_log2;
+    a.hcap = plan.hcap;
     a.visit_limit = plan.visit_limit;
     hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, a.counter, 1);
     const dim3 grid((unsigned)plan.slots);

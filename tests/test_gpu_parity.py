@@ -204,7 +204,7 @@ def test_visited_spill_and_pool_capacity(tiny):
     list capacity with pool = 0 behaves as pool = that capacity."""
     w = tiny.w
     try:
-        P.peos_set_search_tuning(hash_log2=6, listcap=128, slots=7)
+        P.peos_set_search_tuning(hash_cap=100, listcap=128, slots=7)
         ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=0)
         ids2, d2, st2 = run(tiny, w.k, 96, w.eps, P.PEOS_MODE_EXHAUSTIVE, pool=0)
     finally:
@@ -263,3 +263,34 @@ def test_repeatable(tiny):
     b = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, queries=tiny.q[perm])
     assert np.array_equal(a[0][perm], b[0]) and np.array_equal(a[1][perm], b[1])
     assert np.array_equal(a[2][perm], b[2])
+
+
+def test_results_do_not_depend_on_launch_plan(tiny):
+    """Visited-hash capacity, list capacity and grid size change speed only."""
+    w = tiny.w
+    base = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
+    try:
+        for tune in ((1024, 0, 0), (1536, 0, 0), (4096, 256, 0), (300, 0, 5)):
+            P.peos_set_search_tuning(*tune)
+            other = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
+            assert np.array_equal(base[0], other[0]) and np.array_equal(base[1], other[1])
+            st_a, st_b = base[2].copy(), other[2].copy()
+            st_a[:, 11] &= ~P.PEOS_STATUS_VISITED_SPILL
+            st_b[:, 11] &= ~P.PEOS_STATUS_VISITED_SPILL
+            assert np.array_equal(st_a, st_b)
+    finally:
+        P.peos_set_search_tuning(0, 0, 0)
+
+
+def test_autotune_sets_a_capacity(tiny):
+    from paper_2402_11354_amd import autotune
+    w = tiny.w
+    try:
+        cap, times = autotune.tune(tiny.index, tiny.qt, w.k, w.ef, pool=w.ef, eps=w.eps,
+                                   use_cache=False, reps=1)
+        assert cap in times and times[cap] == min(times.values())
+        ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
+        ref = tiny.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
+        assert not compare(ids, d, st, ref, w.k)["bad"]
+    finally:
+        P.peos_set_search_tuning(0, 0, 0)
