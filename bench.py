@@ -26,6 +26,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_2402_11354_amd/csrc/k_search.hpp",
+                  "paper_2402_11354_amd/csrc/peos_device.hpp",
+                  "paper_2402_11354_amd/csrc/peos_api.hip")
+
+
+def kernel_digest():
+    """Digest of the search kernel's sources: a memory-counter record applies
+    only to the kernel it was taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_record(key):
+    """HBM bytes per search launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summaries (a 'traffic-record:' JSON line in profiles/*.md), if
+    one was taken on this kernel at this operating point; else None."""
+    import glob
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(f) as fh:
+            for line in fh:
+                if not line.startswith("traffic-record:"):
+                    continue
+                try:
+                    rec = json.loads(line.split(":", 1)[1])
+                except ValueError:
+                    continue
+                if all(rec.get(k) == v for k, v in key.items()):
+                    return (rec["fetch_kib"] * rec["fetch_scale"]
+                            + rec["write_kib"] * rec["write_scale"]) * 1024.0
+    return None
 
 
 def log(*a):
@@ -153,6 +187,10 @@ def main():
         st = stats.cpu().numpy()
         log(f"per query: expansions {st[:, 0].mean():.1f} tests {st[:, 3].mean():.1f} "
             f"ndist {st[:, 9].mean():.1f}")
+        log("traffic key " + json.dumps(dict(kernel="k_search", source=kernel_digest(),
+                                             workload=w.name, n=w.n, nq=nq, ef=cfg[0],
+                                             pool=cfg[1], eps=cfg[2], mode=cfg[3],
+                                             hash_cap=args.hash_cap)))
         return
 
     def sweep(pool_spec, eps, mode):
@@ -223,12 +261,15 @@ def main():
 
     pe_bytes = alg_bytes(pe["stats"])
     achieved = pe_bytes / (float(search_ms.mean()) / 1e3) / 1e9
+    ef, pool, eps, mode = pe["cfg"]
+    traffic = traffic_record(dict(kernel="k_search", source=kernel_digest(), workload=w.name,
+                                  n=w.n, nq=nq, ef=ef, pool=pool, eps=eps, mode=mode,
+                                  hash_cap=pe_cap))
 
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x, g, entry, q, w, pe["cfg"], args.cpu_seconds)
 
-    ef, pool, eps, _ = pe["cfg"]
     st = pe["stats"]
 
     def pts_json(d):
@@ -274,7 +315,9 @@ def main():
         "kernel_ms": {"query_table": round(float(table_ms.mean()), 4),
                       "search": round(float(search_ms.mean()), 4)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic),
+                     "alg_bytes": round(pe_bytes)},
         "cpu_baseline": cpu,
         "sweep": {"peos": pts_json(pe_sweeps), "exhaustive": pts_json(ex_sweeps)},
     }
@@ -283,27 +326,33 @@ def main():
 
 def cpu_baseline(x, g, entry, q, w, cfg, budget_s):
     """The oracle, as it stands, on the host cores: a bounded sample of the
-    same queries at the same operating point."""
+    same queries at the same operating point, on all threads it is given and
+    on one thread."""
     import oracle
     import workloads as W
 
     ef, pool, eps, mode = cfg
     A, B = W.directions_for(w)
     threads = min(16, os.cpu_count() or 1)
+
+    def run(nq, nthreads):
+        t0 = time.perf_counter()
+        oracle.search(x, g, entry, q[:nq], w.k, ef, w.L, w.m, A, B, w.metric, eps, mode=mode,
+                      pool=pool, nthreads=nthreads)
+        return time.perf_counter() - t0
+
     n = 32
-    t0 = time.perf_counter()
-    oracle.search(x, g, entry, q[:n], w.k, ef, w.L, w.m, A, B, w.metric, eps, mode=mode,
-                  pool=pool, nthreads=threads)
-    dt = time.perf_counter() - t0
+    dt = run(n, threads)
     n2 = int(min(len(q), max(n, n * budget_s / max(dt, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.search(x, g, entry, q[:n2], w.k, ef, w.L, w.m, A, B, w.metric, eps, mode=mode,
-                  pool=pool, nthreads=threads)
-    dt = time.perf_counter() - t0
+    dt = run(n2, threads)
     log(f"cpu baseline: {n2} queries in {dt:.1f}s on {threads} threads")
+    n1 = int(min(len(q), max(8, n2 / max(1.0, dt) * 2.0 / threads)))
+    dt1 = run(n1, 1)
+    log(f"cpu baseline: {n1} queries in {dt1:.1f}s on 1 thread")
     return {"value": round(n2 / dt, 2), "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n2} of the {len(q)} queries at the same ef/pool/eps "
-                      f"(float64 oracle, {threads} threads)"}
+                      f"(float64 oracle, {threads} threads); single thread: first {n1}",
+            "value_1thread": round(n1 / dt1, 2)}
 
 
 if __name__ == "__main__":

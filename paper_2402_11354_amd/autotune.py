@@ -18,7 +18,8 @@ import torch
 from . import peos_search_ws_bytes, peos_set_search_tuning, search
 
 CACHE = os.environ.get("PEOS_TUNE_CACHE", os.path.expanduser("~/.cache/peos_tune.json"))
-HASH_CAPS = (1024, 1536, 1920, 2048, 3072, 4096, 8192)
+HASH_CAPS = (0, 1024, 1536, 1920, 3072, 4096, 8192)  # 0 = the library's default plan
+KEEP_DEFAULT = 0.03  # another plan must be this much faster to replace the default
 
 
 def _key(index, nq, k, ef, pool, mode):
@@ -49,6 +50,8 @@ def _store(cache):
 def tune(index, queries, k, ef, pool=0, eps=0.1, mode=0, caps=HASH_CAPS, reps=3, use_cache=True,
          log=None):
     """Pick and set the visited-hash capacity for this operating point.
+    The library's default plan (cap 0) is kept unless another capacity is at
+    least KEEP_DEFAULT faster, so that the choice is stable from run to run.
     Returns (hash_cap, {cap: ms})."""
     nq = queries.shape[0]
     key = _key(index, nq, k, ef, pool, mode)
@@ -79,6 +82,8 @@ def tune(index, queries, k, ef, pool=0, eps=0.1, mode=0, caps=HASH_CAPS, reps=3,
         if log:
             log(f"autotune ef={ef} pool={pool} mode={mode} hash_cap={cap}: {times[cap]:.3f} ms")
     best = min(times, key=times.get)
+    if 0 in times and times[best] > (1.0 - KEEP_DEFAULT) * times[0]:
+        best = 0
     peos_set_search_tuning(best, 0, 0)
     cache[key] = {"hash_cap": best, "ms": {str(c): round(t, 4) for c, t in times.items()}}
     if use_cache:

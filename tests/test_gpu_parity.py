@@ -288,7 +288,10 @@ def test_autotune_sets_a_capacity(tiny):
     try:
         cap, times = autotune.tune(tiny.index, tiny.qt, w.k, w.ef, pool=w.ef, eps=w.eps,
                                    use_cache=False, reps=1)
-        assert cap in times and times[cap] == min(times.values())
+        assert cap in times
+        # the default plan stays unless another is clearly faster
+        assert cap == 0 or times[cap] <= (1 - autotune.KEEP_DEFAULT) * times[0]
+        assert times[cap] == min(times.values()) or cap == 0
         ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
         ref = tiny.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
         assert not compare(ids, d, st, ref, w.k)["bad"]

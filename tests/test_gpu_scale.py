@@ -1,0 +1,138 @@
+"""Parity at the full size of the benchmark workload (1,000,000 x 128 SIFT-like
+base, 10,000 queries, degree 32, L = 8, m = 16), in the launch configuration
+the benchmark times: the whole query batch in one launch of the table and
+search kernels.  The oracle checks a seeded sample of queries one by one;
+properties that hold at any size are checked on every query.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import compare
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2402_11354_amd")
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow, pytest.mark.timeout(900)]
+
+NSAMPLE = 192
+
+
+def dev():
+    return torch.device("cuda:0")
+
+
+class Full:
+    def __init__(self, w):
+        self.w = w
+        print(f"[gpu] full-size workload {w.name}: data", flush=True)
+        self.x = W.make_base(w)
+        self.q = W.make_queries(w)
+        self.A, self.B = W.directions_for(w)
+        print("[gpu] full-size workload: graph", flush=True)
+        self.g, self.entry = W.build_graph(self.x, w.R, w.cand, device=dev())
+        T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev())
+        self.xt, self.gt, self.qt = T(self.x), T(self.g), T(self.q)
+        self.index = P.peos_build_tables(self.xt, self.gt, self.entry, w.L, w.m, T(self.A),
+                                         T(self.B), w.metric)
+        print("[gpu] full-size workload: ground truth", flush=True)
+        self.gt_ids, self.gt_d = W.ground_truth(self.x, self.q, w.k, w.metric, device=dev())
+        self.sample = np.sort(np.random.default_rng(77).choice(w.nq, NSAMPLE, replace=False))
+
+    def step(self, k, ef, pool, eps, mode):
+        """One pass of the benchmark's step: tables, then the search."""
+        w, nq = self.w, self.w.nq
+        tables = torch.empty((nq, w.L + 1, w.m), dtype=torch.float32, device=dev())
+        qn = torch.empty(nq, dtype=torch.float32, device=dev())
+        ids = torch.empty((nq, k), dtype=torch.int64, device=dev())
+        dists = torch.empty((nq, k), dtype=torch.float32, device=dev())
+        stats = torch.empty((nq, P.PEOS_NSTATS), dtype=torch.int32, device=dev())
+        ws = torch.empty(P.peos_search_ws_bytes(self.index, nq, max(k, ef), pool),
+                         dtype=torch.uint8, device=dev())
+        P.peos_query_tables(self.index, self.qt, tables, qn)
+        P.peos_search_tables(self.index, self.qt, tables, qn, k, ef, k, pool, eps, mode, ids,
+                             dists, stats, ws)
+        torch.cuda.synchronize()
+        return ids.cpu().numpy(), dists.cpu().numpy(), stats.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def full():
+    return Full(W.SIFT_LIKE)
+
+
+def test_fullsize_edge_records_sampled(full):
+    """Edge records of 400 sampled nodes against the oracle's build."""
+    w = full.w
+    rng = np.random.default_rng(5)
+    nodes = np.sort(rng.choice(w.n, 400, replace=False))
+    nb = full.g[nodes]
+    others = np.unique(nb[nb >= 0])
+    keep = np.concatenate([nodes, others])
+    remap = {int(v): i for i, v in enumerate(keep)}
+    gsub = np.full((len(keep), w.R), -1, np.int32)
+    for i, v in enumerate(nodes):
+        row = full.g[v]
+        gsub[i, :] = [remap[int(u)] if u >= 0 else -1 for u in row]
+    rc, rs, _ = O.build_tables(full.x[keep], gsub, w.L, w.m, full.A, full.B)
+    lay = full.index.layout()
+    mem = full.index._keep[-1].view(lay.n, lay.node_stride)[torch.from_numpy(nodes).to(dev())]
+    mem = mem.cpu().numpy()
+    cb = lay.code_bytes
+    codes = mem[:, lay.codes_offset:lay.codes_offset + cb * w.R].reshape(len(nodes), w.R, cb)
+    sc = mem[:, lay.scalars_offset:lay.scalars_offset + 16 * w.R].copy().view(np.float32)
+    sc = sc.reshape(len(nodes), w.R, 4).astype(np.float64)
+    valid = nb >= 0
+    assert np.array_equal(codes[:, :, :w.L + 1][valid], rc[:len(nodes)][valid])
+    r = rs[:len(nodes)]
+    np.testing.assert_allclose(sc[..., 1][valid], r[..., 0][valid], rtol=2e-6)
+    np.testing.assert_allclose(sc[..., 2][valid], r[..., 1][valid], rtol=0, atol=2e-6)
+    np.testing.assert_allclose(sc[..., 3][valid], np.sqrt(w.L) * r[..., 2][valid], rtol=0,
+                               atol=2e-5)
+    scale = float((full.x.astype(np.float64) ** 2).sum(1).max())
+    np.testing.assert_allclose(sc[..., 0][valid], r[..., 3][valid], rtol=0, atol=2e-6 * scale)
+
+
+# the operating points the benchmark sweeps: HNSW rule (pool = ef) with each
+# eps and with the test off, and the unbounded queue of the printed Alg. 1
+POINTS = [
+    ("peos_hnsw_eps0.2", 64, "ef", 0.2, 0),
+    ("peos_hnsw_eps0.1", 48, "ef", 0.1, 0),
+    ("exhaustive_hnsw", 64, "ef", 0.1, 1),
+    ("peos_alg1_eps0.1", 32, 0, 0.1, 0),
+]
+
+
+@pytest.mark.parametrize("name,ef,pool,eps,mode", POINTS, ids=[p[0] for p in POINTS])
+def test_fullsize_search(full, name, ef, pool, eps, mode):
+    w = full.w
+    pool = ef if pool == "ef" else pool
+    print(f"[gpu] full-size search {name}: ef={ef} pool={pool} eps={eps} mode={mode}", flush=True)
+    ids, d, st = full.step(w.k, ef, pool, eps, mode)
+    # properties on every query
+    assert np.all(ids >= 0) and np.all(ids < w.n)
+    assert np.all(np.diff(d, axis=1) >= 0)
+    srt = np.sort(ids, axis=1)
+    assert np.all(srt[:, 1:] != srt[:, :-1])
+    xs = torch.from_numpy(full.x).to(dev()).double()
+    qs = full.qt.double()
+    it = torch.from_numpy(ids).to(dev())
+    d64 = ((xs[it] - qs[:, None, :]) ** 2).sum(-1).cpu().numpy()
+    assert np.all(np.abs(d.astype(np.float64) - d64) <= 1e-5 * d64 + 1e-6)
+    assert np.all(st[:, 11] & P.PEOS_STATUS_ZERO_QUERY == 0)
+    # the sampled queries against the oracle, one by one
+    s = full.sample
+    ref = O.search(full.x, full.g, full.entry, full.q[s], w.k, ef, w.L, w.m, full.A, full.B,
+                   w.metric, eps, mode=mode, pool=pool, precision=32)
+    res = compare(ids[s], d[s], st[s], ref, w.k)
+    print(f"[gpu] {name}: checked={res['checked']}/{len(s)} fragile={res['fragile']} "
+          f"{res['flags']}", flush=True)
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.75 * len(s)
+    from workloads.graph import recall_at_k
+    r_gpu = recall_at_k(full.x, full.q[s], ids[s], full.gt_d[s], w.k, w.metric).mean()
+    r_orc = recall_at_k(full.x, full.q[s], ref["ids"], full.gt_d[s], w.k, w.metric).mean()
+    print(f"[gpu] {name}: recall@10 gpu={r_gpu:.4f} oracle={r_orc:.4f} "
+          f"(all queries {recall_at_k(full.x, full.q, ids, full.gt_d, w.k, w.metric).mean():.4f})")
+    assert abs(r_gpu - r_orc) <= 0.003 + 1e-12
