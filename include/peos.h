@@ -39,6 +39,7 @@ extern "C" {
 #define PEOS_EGRAPH (-4)   /* graph row with an out-of-range id, self loop or
                               repeated neighbour                               */
 #define PEOS_EDEVICE (-5)  /* no gfx950 device is current                       */
+#define PEOS_EBUSY (-6)    /* serving: the request queue is full; retry later    */
 
 /* metrics.  L2: squared Euclidean distance |x - q|^2.  ANGULAR: 1 - x.q/|q|,
  * the cosine distance when base vectors have unit norm (Sec. 3 of the paper
@@ -75,6 +76,7 @@ extern "C" {
 #define PEOS_NSTATS 12
 
 typedef struct peos_index peos_index;
+typedef struct peos_graph peos_graph;
 
 /* Byte layout of the per-node edge records inside index_mem (for tests and
  * tools; the search needs nothing but the handle).  Record of node v starts at
@@ -184,6 +186,11 @@ int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int
  *            1 - x.q/|q|), then +inf.
  *   stats    out, nq x PEOS_NSTATS int32, or NULL.
  *   ws       workspace of peos_search_ws_bytes(index, nq, efmax, pool).
+ * Launch: with per-query ef (ef != NULL) the batch is split on the device
+ * into classes of effective list size (<= 32, <= 64, ..., doubling, the last
+ * class up to max(ef_all, k_all)), and each class runs as its own persistent
+ * launch whose LDS plan fits its largest list, largest class first; results
+ * do not depend on the split.
  * Search semantics (where the paper leaves a choice): the entry node is
  * distance-computed and visited first; delta is read once per expansion;
  * a neighbour is visited only once its distance is computed; a survivor
@@ -221,6 +228,93 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
  */
 int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots);
 
+/*
+ * peos_set_class_tuning -- launch plan of one ef class of a split batch (see
+ * peos_search_tables; class c holds lists of size <= 32 << c, c in [0, 8)):
+ * visited-hash capacity and resident waves, 0 = automatic.  Overrides
+ * peos_set_search_tuning for that class.  Results do not depend on it.
+ * Errors: PEOS_EINVAL for values out of range.
+ */
+int peos_set_class_tuning(int32_t cls, int32_t hash_cap, int32_t slots);
+/*
+ * peos_graph_create -- capture one peos_search call (projection tables,
+ * class split and search launches; no memset nodes) into an executable HIP
+ * graph, so that a batch of the same shape is issued with one launch.
+ * Arguments as for peos_search; every pointer is baked into the graph, so the
+ * caller refills queries (and k, ef) in place between launches and reads
+ * ids/dists/stats after each.  Tuning in effect at capture time is frozen in
+ * the graph.  Output *out (host); release with peos_graph_destroy.
+ * Errors: as peos_search, PEOS_EINVAL for nq = 0, PEOS_EHIP if capture or
+ * instantiation fails.
+ */
+int peos_graph_create(const peos_index* index, const float* queries, int64_t nq, const int32_t* k,
+                      const int32_t* ef, int32_t k_all, int32_t ef_all, int32_t kstride,
+                      int32_t pool, float eps, int32_t mode, int64_t* ids, float* dists,
+                      int32_t* stats, void* ws, size_t ws_bytes, peos_graph** out);
+/* Launch a captured search on `stream` (asynchronous).  Errors: PEOS_EINVAL,
+ * PEOS_EHIP.  Launches of one graph must not overlap (they share the
+ * workspace). */
+int peos_graph_launch(peos_graph* graph, void* stream);
+/* Release a captured search. */
+void peos_graph_destroy(peos_graph* graph);
+/*
+ * Serving form: a request loop with continuous batching over one index.
+ * Unlike the calls above, a server allocates: device buffers for each launch
+ * slot (hipMalloc) and pinned host staging (hipHostMalloc), at open time.
+ *
+ * Requests of 1..max_batch queries, each request with its own k and ef, wait
+ * in a FIFO.  Whenever one of the server's launch slots is free, the longest
+ * prefix of the FIFO that fits max_batch queries becomes one batch (per-query
+ * k and ef) and is issued on that slot's stream: copy in, projection tables
+ * (peos_query_tables), ef-class split and search (peos_search_tables), copy
+ * out.  Batches on different slots overlap on the device, so requests that
+ * arrive while others are running start as soon as a slot and LDS free up.
+ * Admission: a batch is issued only while the LDS held by its resident waves
+ * plus that of the batches in flight fits lds_budget; the HBM budget caps the
+ * number of slots at open time; submit refuses work beyond max_pending
+ * queued queries (PEOS_EBUSY).  A query's result does not depend on the
+ * batch it ran in.  Single-threaded: one thread drives a server.
+ */
+typedef struct peos_server peos_server;
+typedef struct {
+    int32_t max_batch;    /* queries per launch, and per request             */
+    int32_t max_k;        /* largest k of a request                          */
+    int32_t max_ef;       /* largest ef of a request (ef := max(ef, k))      */
+    int32_t max_inflight; /* launch slots (streams), 1..16                    */
+    int32_t max_pending;  /* queued queries before submit returns PEOS_EBUSY  */
+    int32_t pool;         /* stopping rule for all requests, as peos_search  */
+    int32_t mode;         /* PEOS_MODE_*                                     */
+    int32_t launch_waves; /* resident waves one launch may hold, 0 = all     */
+    float eps;            /* in (0, 0.5] for PEOS_MODE_PEOS                  */
+    float reserved;
+    size_t hbm_budget;    /* device bytes for all slots, 0 = no limit        */
+    size_t lds_budget;    /* LDS bytes of all launches in flight, 0 = device */
+} peos_serve_config;
+/* Open a server on the current device (the index's).  *out (host).  Errors:
+ * PEOS_EINVAL (config out of range), PEOS_ENOSPACE (not one slot fits
+ * hbm_budget), PEOS_EHIP (allocation), PEOS_EDEVICE. */
+int peos_serve_open(const peos_index* index, const peos_serve_config* cfg, peos_server** out);
+/* Queue a request: queries (host, nq x d float), k, ef; the results are
+ * written to ids (host, nq x k int64) and dists (host, nq x k float) when the
+ * request completes (see peos_serve_poll); all three buffers must stay valid
+ * until then.  *ticket (host) identifies the request.  May issue batches.
+ * Errors: PEOS_EINVAL, PEOS_EBUSY (queue full, nothing queued), PEOS_EHIP. */
+int peos_serve_submit(peos_server* server, const float* queries, int32_t nq, int32_t k, int32_t ef,
+                      int64_t* ids, float* dists, uint64_t* ticket);
+/* Progress: collect finished batches (their requests' results are copied
+ * out), issue waiting requests on free slots, and return up to max_done
+ * tickets of completed requests in done (host), their count in *n_done.
+ * wait != 0: if nothing has completed, block until the oldest batch in flight
+ * does.  Errors: PEOS_EINVAL, PEOS_EHIP. */
+int peos_serve_poll(peos_server* server, int32_t wait, uint64_t* done, int32_t max_done,
+                    int32_t* n_done);
+/* Eight counters (host int64): launches, requests completed, queries
+ * completed, largest batch, batches in flight, queries waiting, launch slots,
+ * LDS bytes in flight.  Errors: PEOS_EINVAL. */
+int peos_serve_counters(const peos_server* server, int64_t* out);
+/* Wait for the work in flight and release the server (requests still queued
+ * are dropped). */
+void peos_serve_close(peos_server* server);
 /* Message for a return code, and the thread-local message of the last error. */
 const char* peos_strerror(int code);
 const char* peos_last_error(void);

@@ -68,12 +68,19 @@ def lib():
                                          P, P, sz, P]
         L.peos_search.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P, sz, P]
         L.peos_set_search_tuning.argtypes = [i32, i32, i32]
+        L.peos_set_class_tuning.argtypes = [i32, i32, i32]
+        L.peos_graph_create.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P,
+                                        sz, ctypes.POINTER(P)]
+        L.peos_graph_launch.argtypes = [P, P]
+        L.peos_graph_destroy.argtypes = [P]
+        L.peos_graph_destroy.restype = None
         L.peos_strerror.argtypes = [i32]
         L.peos_strerror.restype = ctypes.c_char_p
         L.peos_last_error.restype = ctypes.c_char_p
         for name in ("peos_index_bytes", "peos_build_tables", "peos_index_layout",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
-                     "peos_search", "peos_set_search_tuning"):
+                     "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
+                     "peos_graph_create", "peos_graph_launch"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -195,6 +202,49 @@ def peos_search(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, sta
 def peos_set_search_tuning(hash_cap=0, listcap=0, slots=0):
     """Override the search launch plan (0 = automatic); see include/peos.h."""
     _check("peos_set_search_tuning", lib().peos_set_search_tuning(hash_cap, listcap, slots))
+
+
+def peos_set_class_tuning(cls, hash_cap=0, slots=0):
+    """Launch plan of ef class cls (lists <= 32 << cls) of a split batch."""
+    _check("peos_set_class_tuning", lib().peos_set_class_tuning(cls, hash_cap, slots))
+
+
+class PeosGraph:
+    """A captured peos_search (HIP graph) and the tensors baked into it."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def launch(self, stream=None):
+        _check("peos_graph_launch", lib().peos_graph_launch(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().peos_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def peos_graph_create(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, stats, ws,
+                      k_all=None, ef_all=None):
+    """Capture peos_search over these buffers into a graph (see include/peos.h)."""
+    kt = k if torch.is_tensor(k) else None
+    et = ef if torch.is_tensor(ef) else None
+    ka = int(k_all if k_all is not None else (k if kt is None else int(kt.max())))
+    ea = int(ef_all if ef_all is not None else (ef if et is None else int(et.max())))
+    h = ctypes.c_void_p()
+    _check("peos_graph_create",
+           lib().peos_graph_create(index.handle, _ptr(queries), queries.shape[0], _ptr(kt),
+                                   _ptr(et), ka, ea, kstride, pool, float(eps), mode, _ptr(ids),
+                                   _ptr(dists), _ptr(stats), _ptr(ws), ws.numel(),
+                                   ctypes.byref(h)))
+    return PeosGraph(h, (index, queries, kt, et, ids, dists, stats, ws))
 
 
 def search(index, queries, k, ef, eps=0.1, mode=PEOS_MODE_PEOS, pool=0, kstride=None,

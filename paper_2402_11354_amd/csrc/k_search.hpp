@@ -35,6 +35,8 @@ struct SearchArgs {
     const float* qnorms;
     const int32_t* kq;
     const int32_t* efq;
+    const int32_t* qperm;   // optional: query order (a class of the batch)
+    const uint32_t* qrange; // with qperm: {begin, end} of this launch's part
     int64_t* ids;
     float* dists;
     int32_t* stats;
@@ -210,11 +212,17 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
     float* Sdist = reinterpret_cast<float*>(Su + kWave);
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
 
+    uint32_t qbegin = 0, qend = (uint32_t)a.nq;
+    if (a.qperm) {
+        qbegin = a.qrange[0];
+        qend = a.qrange[1];
+    }
     for (;;) {
         uint32_t qtaken = 0;
         if (lane == 0) qtaken = atomicAdd(a.counter, 1u);
-        const int64_t qi = wave_uniform((int)__shfl(qtaken, 0, kWave));
-        if (qi >= a.nq) break;
+        const uint32_t slot = wave_uniform((uint32_t)__shfl((int)qtaken, 0, kWave)) + qbegin;
+        if (slot >= qend) break;
+        const int64_t qi = a.qperm ? (int64_t)wave_uniform(a.qperm[slot]) : (int64_t)slot;
 
         // per-query k and ef are clamped to the launch bounds k_all, ef_all
         int kq = a.kq ? a.kq[qi] : a.k_all;
@@ -499,6 +507,75 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             o[11] = status;
         }
         wave_sync();
+    }
+}
+
+// Split a batch with per-query list sizes into classes by effective ef
+// (class c holds ef in (32 << (c-1), 32 << c], the last class the rest), as
+// a stable counting sort: qperm lists the queries of class 0, then class 1,
+// ..., each in query order; ranges[2c], ranges[2c+1] = begin, end of class c.
+// One workgroup of 1024 threads.
+constexpr int kMaxClasses = 8;
+
+__device__ __forceinline__ int ef_class(int efq, int nclass)
+{
+    int c = 0;
+    while (c < nclass - 1 && efq > (32 << c)) ++c;
+    return c;
+}
+
+__global__ __launch_bounds__(1024) void k_classify(const int32_t* kq, const int32_t* efq, int k_all,
+                                                   int ef_all, int64_t nq, int nclass,
+                                                   int32_t* qperm, uint32_t* ranges)
+{
+    __shared__ uint32_t cnt[kMaxClasses];
+    __shared__ uint32_t run[kMaxClasses];
+    __shared__ uint32_t wc[16][kMaxClasses];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto cls = [&](int64_t i) {
+        int k = kq ? kq[i] : k_all;
+        k = k < 1 ? 1 : (k > k_all ? k_all : k);
+        int e = efq ? efq[i] : ef_all;
+        e = e > ef_all ? ef_all : e;
+        e = e > k ? e : k;
+        return ef_class(e, nclass);
+    };
+    if (tid < kMaxClasses) cnt[tid] = 0u;
+    __syncthreads();
+    for (int64_t i = tid; i < nq; i += 1024) atomicAdd(&cnt[cls(i)], 1u);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t b = 0;
+        for (int c = 0; c < kMaxClasses; ++c) {
+            run[c] = b;
+            ranges[2 * c] = b;
+            b += c < nclass ? cnt[c] : 0u;
+            ranges[2 * c + 1] = b;
+        }
+    }
+    __syncthreads();
+    for (int64_t b0 = 0; b0 < nq; b0 += 1024) {
+        const int64_t i = b0 + tid;
+        const int c = i < nq ? cls(i) : -1;
+        int rank = 0;
+        for (int cc = 0; cc < nclass; ++cc) {
+            const uint64_t mk = ballot(c == cc);
+            if (c == cc) rank = popc(mk & lanemask_lt());
+            if (lane == 0) wc[wv][cc] = (uint32_t)popc(mk);
+        }
+        __syncthreads();
+        if (c >= 0) {
+            uint32_t off = run[c];
+            for (int w = 0; w < wv; ++w) off += wc[w][c];
+            qperm[off + rank] = (int32_t)i;
+        }
+        __syncthreads();
+        if (tid < nclass) {
+            uint32_t t = 0;
+            for (int w = 0; w < 16; ++w) t += wc[w][tid];
+            run[tid] += t;
+        }
+        __syncthreads();
     }
 }
 

@@ -13,6 +13,12 @@
 #include "k_query_table.hpp"
 #include "k_search.hpp"
 
+struct peos_graph {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    int device;
+};
+
 struct peos_index {
     const float* base;
     const int32_t* graph;
@@ -130,6 +136,24 @@ struct Tuning {
 };
 std::mutex g_tune_mu;
 Tuning g_tune;
+Tuning g_class_tune[peos::kMaxClasses];  // per ef class of a batch (hash_cap, slots)
+
+// The search kernels may use up to 64 KB of LDS; raise the limit once per
+// device (not a stream operation, so it also holds for captured launches).
+int ensure_kernel_attrs(int dev)
+{
+    static std::mutex mu;
+    static bool done[64] = {false};
+    std::lock_guard<std::mutex> g(mu);
+    if (dev < 0 || dev >= 64) return fail(PEOS_EDEVICE, "device index %d", dev);
+    if (!done[dev]) {
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<32>, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+        done[dev] = true;
+    }
+    return PEOS_OK;
+}
 
 struct SearchPlan {
     int listcap, listslack, hcap, visit_limit, slots;
@@ -138,13 +162,18 @@ struct SearchPlan {
 };
 
 // per_query: k or ef given per query (then queries may have ef below efmax)
-SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bool per_query)
+SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bool per_query,
+                       int cls = -1)
 {
     SearchPlan p;
     Tuning t;
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
         t = g_tune;
+        if (cls >= 0 && cls < peos::kMaxClasses) {
+            if (g_class_tune[cls].hash_cap > 0) t.hash_cap = g_class_tune[cls].hash_cap;
+            if (g_class_tune[cls].slots > 0) t.slots = g_class_tune[cls].slots;
+        }
     }
     const int lmin = pool > efmax ? pool : efmax;
     // unbounded queue: room for 16 ef entries (the list of the printed Alg. 1
@@ -181,8 +210,10 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     return p;
 }
 
+// workspace: work counters (one per ef class) and class ranges | per-slot
+// visited bitmaps | tables | norms | query order of the class split
 struct WsLayout {
-    int64_t counter_off, spill_off, tables_off, qnorm_off, total;
+    int64_t counter_off, ranges_off, spill_off, tables_off, qnorm_off, qperm_off, total;
 };
 
 WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
@@ -191,11 +222,21 @@ WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
     int64_t slots = nq < kMaxSlots ? nq : kMaxSlots;
     if (slots < 1) slots = 1;
     w.counter_off = 0;
+    w.ranges_off = 64;
     w.spill_off = 256;
     w.tables_off = round_up(w.spill_off + slots * spill_words * 4, 256);
     w.qnorm_off = round_up(w.tables_off + nq * (int64_t)(ix->L + 1) * ix->m * 4, 256);
-    w.total = round_up(w.qnorm_off + nq * 4, 256);
+    w.qperm_off = round_up(w.qnorm_off + nq * 4, 256);
+    w.total = round_up(w.qperm_off + nq * 4, 256);
     return w;
+}
+
+// number of ef classes a batch with list sizes up to efmax is split into
+int num_classes(int efmax)
+{
+    int c = 1;
+    while (c < peos::kMaxClasses && efmax > (32 << (c - 1))) ++c;
+    return c;
 }
 
 }  // namespace
@@ -217,6 +258,18 @@ int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots)
     return PEOS_OK;
 }
 
+int peos_set_class_tuning(int32_t cls, int32_t hash_cap, int32_t slots)
+{
+    if (cls < 0 || cls >= peos::kMaxClasses) return fail(PEOS_EINVAL, "class %d not in [0, %d)", cls, peos::kMaxClasses);
+    if (hash_cap != 0 && (hash_cap < 64 || hash_cap > 16384))
+        return fail(PEOS_EINVAL, "hash_cap=%d not in [64, 16384]", hash_cap);
+    if (slots < 0 || slots > kMaxSlots) return fail(PEOS_EINVAL, "slots=%d", slots);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_class_tune[cls].hash_cap = hash_cap;
+    g_class_tune[cls].slots = slots;
+    return PEOS_OK;
+}
+
 const char* peos_strerror(int code)
 {
     switch (code) {
@@ -226,6 +279,7 @@ const char* peos_strerror(int code)
     case PEOS_EHIP: return "HIP runtime error";
     case PEOS_EGRAPH: return "invalid graph (id out of range, self loop or repeated neighbour)";
     case PEOS_EDEVICE: return "no gfx950 device";
+    case PEOS_EBUSY: return "request queue full";
     default: return "unknown error";
     }
 }
@@ -368,17 +422,41 @@ int peos_search_ws_bytes(const peos_index* ix, int64_t nq, int32_t efmax, int32_
     return PEOS_OK;
 }
 
+// one launch of the search kernel for the queries of qrange (all queries
+// when qperm is null), planned for list sizes up to efmax
+static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args, int64_t nq,
+                         int efmax, int pool, bool per_query, int cls, const uint32_t* counter,
+                         int slots_cap, hipStream_t s)
+{
+    SearchPlan plan = plan_search(ix, nq, efmax, pool, per_query, cls);
+    if (slots_cap > 0 && plan.slots > slots_cap) plan.slots = slots_cap;
+    if (plan.lds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
+    peos::SearchArgs a = base_args;
+    a.counter = const_cast<uint32_t*>(counter);
+    a.spill_words = plan.spill_words;
+    a.listcap = plan.listcap;
+    a.listslack = plan.listslack;
+    a.hcap = plan.hcap;
+    a.visit_limit = plan.visit_limit;
+    const dim3 grid((unsigned)plan.slots);
+    if (ix->L <= 8) hipLaunchKernelGGL(peos::k_search<8>, grid, dim3(64), (size_t)plan.lds, s, a);
+    else if (ix->L <= 16) hipLaunchKernelGGL(peos::k_search<16>, grid, dim3(64), (size_t)plan.lds, s, a);
+    else hipLaunchKernelGGL(peos::k_search<32>, grid, dim3(64), (size_t)plan.lds, s, a);
+    HIP_TRY(hipGetLastError());
+    return PEOS_OK;
+}
+
 static int search_impl(const peos_index* ix, const float* queries, const float* tables,
                        const float* qnorms, int64_t nq, const int32_t* k, const int32_t* ef,
                        int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool, float eps,
                        int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
-                       size_t ws_bytes, hipStream_t s)
+                       size_t ws_bytes, hipStream_t s, int slots_cap = 0)
 {
     const int efmax = ef_all > k_all ? ef_all : k_all;
-    SearchPlan plan = plan_search(ix, nq, efmax, pool, k != nullptr || ef != nullptr);
-    WsLayout w = ws_layout(ix, nq, plan.spill_words);
+    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
     if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
-    if (plan.lds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
+    int rc = ensure_kernel_attrs(ix->device);
+    if (rc) return rc;
     peos::SearchArgs a;
     a.base = ix->base;
     a.graph = ix->graph;
@@ -391,12 +469,14 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.qnorms = qnorms;
     a.kq = k;
     a.efq = ef;
+    a.qperm = nullptr;
+    a.qrange = nullptr;
     a.ids = ids;
     a.dists = dists;
     a.stats = stats;
-    a.counter = (uint32_t*)((char*)ws + w.counter_off);
+    a.counter = nullptr;
     a.spill = (uint32_t*)((char*)ws + w.spill_off);
-    a.spill_words = plan.spill_words;
+    a.spill_words = 0;
     a.n = ix->n;
     a.nq = nq;
     a.k_all = k_all;
@@ -413,24 +493,27 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.eta = (float)eta;
     a.c_eps = (float)norm_ppf((double)eps);
     a.kappa = (float)((double)ix->L / (double)(ix->L + 1));
-    a.listcap = plan.listcap;
-    a.listslack = plan.listslack;
     a.pool = pool;
-    a.hcap = plan.hcap;
-    a.visit_limit = plan.visit_limit;
-    hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, a.counter, 1);
-    const dim3 grid((unsigned)plan.slots);
-    if (ix->L <= 8) {
-        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<8>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
-        hipLaunchKernelGGL(peos::k_search<8>, grid, dim3(64), (size_t)plan.lds, s, a);
-    } else if (ix->L <= 16) {
-        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<16>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
-        hipLaunchKernelGGL(peos::k_search<16>, grid, dim3(64), (size_t)plan.lds, s, a);
-    } else {
-        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<32>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)plan.lds));
-        hipLaunchKernelGGL(peos::k_search<32>, grid, dim3(64), (size_t)plan.lds, s, a);
-    }
+    uint32_t* counters = (uint32_t*)((char*)ws + w.counter_off);
+    const bool per_query = k != nullptr || ef != nullptr;
+    const int nclass = ef ? num_classes(efmax) : 1;
+    hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, counters, peos::kMaxClasses);
+    if (nclass == 1) return launch_search(ix, a, nq, efmax, pool, per_query, -1, counters, slots_cap, s);
+    // per-query list sizes: one launch per ef class, each with the LDS plan
+    // of its own largest list (small lists are not held to the largest one's
+    // visited-hash and list capacity), largest class first
+    uint32_t* ranges = (uint32_t*)((char*)ws + w.ranges_off);
+    int32_t* qperm = (int32_t*)((char*)ws + w.qperm_off);
+    hipLaunchKernelGGL(peos::k_classify, dim3(1), dim3(1024), 0, s, k, ef, k_all, ef_all, nq, nclass,
+                       qperm, ranges);
     HIP_TRY(hipGetLastError());
+    a.qperm = qperm;
+    for (int c = nclass - 1; c >= 0; --c) {
+        a.qrange = ranges + 2 * c;
+        const int ef_c = c == nclass - 1 ? efmax : (32 << c);
+        rc = launch_search(ix, a, nq, ef_c, pool, true, c, counters + c, slots_cap, s);
+        if (rc) return rc;
+    }
     return PEOS_OK;
 }
 
@@ -481,4 +564,69 @@ int peos_search(const peos_index* ix, const float* queries, int64_t nq, const in
                        mode, ids, dists, stats, ws, ws_bytes, (hipStream_t)stream);
 }
 
+int peos_graph_create(const peos_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                      const int32_t* ef, int32_t k_all, int32_t ef_all, int32_t kstride,
+                      int32_t pool, float eps, int32_t mode, int64_t* ids, float* dists,
+                      int32_t* stats, void* ws, size_t ws_bytes, peos_graph** out)
+{
+    if (!out) return fail(PEOS_EINVAL, "null output handle");
+    *out = nullptr;
+    int rc = check_search_args(ix, queries, nq, k_all, ef_all, kstride, pool, eps, mode, ids, dists, ws);
+    if (rc) return rc;
+    if (nq == 0) return fail(PEOS_EINVAL, "nq = 0: nothing to capture");
+    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
+    rc = ensure_kernel_attrs(ix->device);
+    if (rc) return rc;
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        rc = peos_search(ix, queries, nq, k, ef, k_all, ef_all, kstride, pool, eps, mode, ids, dists,
+                         stats, ws, ws_bytes, cs);
+        e = hipStreamEndCapture(cs, &g);
+    }
+    hipStreamDestroy(cs);
+    if (rc) {
+        if (g) hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) return fail(PEOS_EHIP, "stream capture: %s", hipGetErrorString(e));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(PEOS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    peos_graph* pg = new (std::nothrow) peos_graph;
+    if (!pg) {
+        hipGraphExecDestroy(x);
+        hipGraphDestroy(g);
+        return fail(PEOS_EINVAL, "out of host memory");
+    }
+    pg->graph = g;
+    pg->exec = x;
+    pg->device = ix->device;
+    *out = pg;
+    return PEOS_OK;
+}
+
+int peos_graph_launch(peos_graph* g, void* stream)
+{
+    if (!g) return fail(PEOS_EINVAL, "null graph");
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return PEOS_OK;
+}
+
+void peos_graph_destroy(peos_graph* g)
+{
+    if (!g) return;
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    delete g;
+}
+
 }  // extern "C"
+
+#include "peos_serve.hpp"

@@ -297,3 +297,92 @@ def test_autotune_sets_a_capacity(tiny):
         assert not compare(ids, d, st, ref, w.k)["bad"]
     finally:
         P.peos_set_search_tuning(0, 0, 0)
+
+
+# ---------------------------------------------------------------------------
+# batched form: per-query list sizes split into ef classes, captured graphs
+# ---------------------------------------------------------------------------
+def test_ef_classes_match_oracle_and_single_runs(angular):
+    """A batch with ef from {32, 64, 128, 256} and k from {1, 10, 100} (the
+    batched workload's mix) runs as one launch per ef class; every query's
+    result equals the oracle's and the same query searched on its own."""
+    case, w = angular, angular.w
+    k, ef = W.query_params(w, len(case.q), seed=1)
+    kt, eft = T(k), T(ef)
+    ids, d, st = P.search(case.index, case.qt, kt, eft, eps=w.eps, pool=1, kstride=100)
+    torch.cuda.synchronize()
+    ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    ref = O.search(case.x, case.g, case.entry, case.q, k, ef, w.L, w.m, case.A, case.B, w.metric,
+                   w.eps, kstride=100, pool=1, precision=32)
+    res = compare(ids, d, st, ref, 100)
+    print(f"[gpu] ef classes: checked={res['checked']} fragile={res['fragile']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+    for i in range(len(k)):
+        assert np.all(ids[i, k[i]:] == -1)
+    # each ef value alone, uniform launch (no class split)
+    for e in np.unique(ef):
+        sel = np.nonzero(ef == e)[0]
+        ii, dd, ss = P.search(case.index, T(case.q[sel]), T(k[sel]), int(e), eps=w.eps, pool=1,
+                              kstride=100)
+        torch.cuda.synchronize()
+        assert np.array_equal(ii.cpu().numpy(), ids[sel])
+        assert np.array_equal(dd.cpu().numpy(), d[sel])
+
+
+def test_ef_class_tuning_does_not_change_results(angular):
+    case, w = angular, angular.w
+    k, ef = W.query_params(w, len(case.q), seed=2)
+    base = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=1, kstride=100)
+    try:
+        for c, (hc, sl) in enumerate([(512, 3), (1024, 0), (3000, 17), (8192, 5)]):
+            P.peos_set_class_tuning(c, hc, sl)
+        other = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=1, kstride=100)
+    finally:
+        for c in range(8):
+            P.peos_set_class_tuning(c, 0, 0)
+    torch.cuda.synchronize()
+    assert torch.equal(base[0], other[0]) and torch.equal(base[1], other[1])
+
+
+@pytest.mark.parametrize("per_query", [False, True])
+def test_graph_capture_replays(tiny, per_query):
+    """Tables + class split + search captured once, replayed with the
+    program's own eager work and synchronisations in between; every replay
+    equals the eager result, also after the queries are refilled in place."""
+    w = tiny.w
+    nq = len(tiny.q)
+    rng = np.random.default_rng(11)
+    k = rng.choice([1, 10, 40], size=nq).astype(np.int32) if per_query else w.k
+    ef = rng.choice([16, 32, 64, 128], size=nq).astype(np.int32) if per_query else w.ef
+    kt = T(k) if per_query else k
+    eft = T(ef) if per_query else ef
+    kmax, efmax = (40, 128) if per_query else (w.k, w.ef)
+    q = tiny.qt.clone()
+    ids = torch.empty((nq, kmax), dtype=torch.int64, device=dev())
+    dists = torch.empty((nq, kmax), dtype=torch.float32, device=dev())
+    stats = torch.empty((nq, P.PEOS_NSTATS), dtype=torch.int32, device=dev())
+    ws = torch.empty(P.peos_search_ws_bytes(tiny.index, nq, efmax, 0), dtype=torch.uint8,
+                     device=dev())
+    g = P.peos_graph_create(tiny.index, q, kt, eft, kmax, 0, w.eps, P.PEOS_MODE_PEOS, ids, dists,
+                            stats, ws, k_all=kmax, ef_all=efmax)
+    try:
+        eager = P.search(tiny.index, q, kt, eft, eps=w.eps, kstride=kmax)
+        torch.cuda.synchronize()
+        for rep in range(3):
+            ids.fill_(-7)
+            g.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(ids, eager[0]) and torch.equal(dists, eager[1]), rep
+            assert torch.equal(stats, eager[2]), rep
+            # unrelated eager work between replays
+            P.search(tiny.index, q[:7], w.k, w.ef, eps=w.eps)
+            torch.cuda.synchronize()
+        perm = torch.from_numpy(rng.permutation(nq)).to(dev())
+        q.copy_(tiny.qt[perm])
+        g.launch()
+        eager2 = P.search(tiny.index, q, kt, eft, eps=w.eps, kstride=kmax)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, eager2[0]) and torch.equal(dists, eager2[1])
+    finally:
+        g.close()
