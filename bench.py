@@ -88,6 +88,13 @@ def main():
     ap.add_argument("--pool", default="ef")
     ap.add_argument("--eps", type=float, default=0.1)
     ap.add_argument("--hash-cap", type=int, default=0, help="with --profile-only: visited-hash capacity")
+    ap.add_argument("--mode", default="headline", choices=("headline", "batched", "serving"),
+                    help="headline: the QPS-at-recall comparison (default); batched: one "
+                         "captured launch over a batch of uneven k/ef; serving: the request "
+                         "loop under Poisson arrivals")
+    ap.add_argument("--rates", default="5000,20000,50000,100000,200000",
+                    help="serving: arrival rates (queries/s)")
+    ap.add_argument("--seconds", type=float, default=1.5, help="serving: duration per rate")
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (a kernel of known traffic for "
                          "calibrating memory counters) and exit")
@@ -111,6 +118,11 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.mode == "batched":
+        return batched(args)
+    if args.mode == "serving":
+        return serving(args)
 
     import paper_2402_11354_amd as P
     import workloads as W
@@ -322,6 +334,193 @@ def main():
         "sweep": {"peos": pts_json(pe_sweeps), "exhaustive": pts_json(ex_sweeps)},
     }
     print(json.dumps(out), flush=True)
+
+
+def _setup(name, n, nq, gt_k):
+    """Data, graph, edge records and exact top-gt_k of a named workload."""
+    import torch
+
+    import paper_2402_11354_amd as P
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[name].with_sizes(n=n, nq=nq)
+    t0 = time.time()
+    x, q = W.make_base(w), W.make_queries(w)
+    A, B = W.directions_for(w)
+    log(f"data {w.name} n={w.n} nq={w.nq} d={w.d} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    g, entry = W.build_graph(x, w.R, w.cand, device=dev, log=lambda m: log("graph:", m))
+    log(f"graph R={w.R} mean degree {(g >= 0).sum(1).mean():.2f} in {time.time() - t0:.1f}s")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    index = P.peos_build_tables(T(x), T(g), entry, w.L, w.m, T(A), T(B), w.metric)
+    t0 = time.time()
+    _, gt_d = W.ground_truth(x, q, gt_k, w.metric, device=dev)
+    log(f"ground truth in {time.time() - t0:.1f}s")
+    return w, x, q, g, entry, index, gt_d
+
+
+def _recall(x, q, ids, gt_d, k, metric):
+    from workloads.graph import recall_at_k
+    return recall_at_k(x, q, ids, gt_d, k, metric)
+
+
+def batched(args):
+    """One launch over a batch of queries with uneven k and ef (the batched
+    persistent form): ef classes tuned per class, tables + split + search
+    captured in a HIP graph and replayed."""
+    import torch
+
+    import paper_2402_11354_amd as P
+    import workloads as W
+    from paper_2402_11354_amd import autotune
+
+    name = args.workload if args.workload != "sift_like_1m_d128" else "deep_like_10m_d96"
+    w, x, q, g, entry, index, gt_d = _setup(name, args.n, args.nq, 100)
+    dev = torch.device("cuda:0")
+    nq = w.nq
+    k, ef = W.query_params(w, nq)
+    kt, eft = torch.from_numpy(k).to(dev), torch.from_numpy(ef).to(dev)
+    qt = torch.from_numpy(q).to(dev)
+    kmax, efmax = int(k.max()), int(ef.max())
+    ids = torch.empty((nq, kmax), dtype=torch.int64, device=dev)
+    dists = torch.empty((nq, kmax), dtype=torch.float32, device=dev)
+    stats = torch.empty((nq, P.PEOS_NSTATS), dtype=torch.int32, device=dev)
+    ws = torch.empty(P.peos_search_ws_bytes(index, nq, efmax, 1), dtype=torch.uint8, device=dev)
+    out = {}
+    for mode, label in ((P.PEOS_MODE_PEOS, "peos"), (P.PEOS_MODE_EXHAUSTIVE, "exhaustive")):
+        caps = autotune.tune_classes(index, qt, k, ef, pool=1, eps=w.eps, mode=mode, log=log)
+        gr = P.peos_graph_create(index, qt, kt, eft, kmax, 1, w.eps, mode, ids, dists, stats, ws,
+                                 k_all=kmax, ef_all=efmax)
+        for _ in range(args.warmup):
+            gr.launch()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for e0, e1 in evs:
+            e0.record()
+            gr.launch()
+            e1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gr.close()
+        for c in range(8):
+            P.peos_set_class_tuning(c, 0, 0)
+        ms = np.array([a.elapsed_time(b) for a, b in evs])
+        st = stats.cpu().numpy()
+        ii = ids.cpu().numpy()
+        rec = {}
+        for kc in (1, 10, 100):
+            sel = np.nonzero(k == kc)[0]
+            rec[f"k={kc}"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :kc], kc,
+                                                 w.metric).mean()), 4)
+        sel = np.nonzero(k >= 10)[0]
+        rec["recall@10 (k>=10)"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :10], 10,
+                                                       w.metric).mean()), 4)
+        code_bytes = 4 * ((w.L + 4) // 4)
+        alg = float((4.0 * w.R * st[:, 0] + (code_bytes + 16.0) * st[:, 3] + 4.0 * w.d * st[:, 9]
+                     + 4.0 * w.d + 4.0 * (w.L + 1) * w.m + 12.0 * k).sum())
+        out[label] = dict(qps=round(nq * args.steps / wall, 1), ms=round(float(ms.mean()), 4),
+                          p99_ms=round(float(np.percentile(ms, 99)), 4), recall=rec,
+                          ndist=round(float(st[:, 9].mean()), 1),
+                          gbs=round(alg / (ms.mean() / 1e3) / 1e9, 1), class_hash_caps=caps)
+        log(f"batched {label}: {out[label]}")
+    pe = out["peos"]
+    print(json.dumps({
+        "metric": "QPS of one launch over a batch of uneven k/ef (batched persistent form)",
+        "value": pe["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": pe["ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L, "m": w.m,
+                   "eps": w.eps, "k": "U{1,10,100}", "ef": "U{32,64,128,256}, max(ef,k)",
+                   "stop_rule": "hnsw (pool=ef)", "launch": "hip graph, ef classes"},
+        "peos": pe, "exhaustive": out["exhaustive"],
+        "speedup_vs_exhaustive": round(pe["qps"] / out["exhaustive"]["qps"], 3),
+        "roofline": {"bound": "hbm", "achieved": pe["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(pe["gbs"] / PEAK_HBM_GBS, 4), "traffic": None},
+    }), flush=True)
+
+
+def serving(args):
+    """The request loop under Poisson arrivals: requests of 1..64 queries,
+    k in {10, 100}, ef in {32, ..., 512}; p50/p99 latency from arrival to
+    completion, completed queries per second, recall@10 of what completed."""
+    import paper_2402_11354_amd as P
+
+    name = args.workload if args.workload != "sift_like_1m_d128" else "serving_1m_d256"
+    w, x, q, g, entry, index, gt_d = _setup(name, args.n, args.nq, 10)
+    rng = np.random.default_rng(w.seed + 11)
+    srv = P.Server(index, max_batch=2048, max_k=100, max_ef=512, max_inflight=4,
+                   max_pending=1 << 18, pool=1, eps=w.eps, hbm_budget=32 << 30)
+    per_rate = []
+    hits, total = 0.0, 0
+    try:
+        for _ in range(16):  # warm-up through every slot
+            srv.submit(q[:64], 100, 512)
+        while srv.live:
+            srv.poll(wait=True)
+        for rate in [float(r) for r in args.rates.split(",")]:
+            mean_req = 32.5  # queries per request, U{1..64}
+            n_req = max(8, int(rate / mean_req * args.seconds))
+            arrive = np.cumsum(rng.exponential(mean_req / rate, size=n_req))
+            sizes = rng.integers(1, 65, size=n_req)
+            ks = rng.choice([10, 100], size=n_req)
+            efs = np.maximum(rng.choice([32, 64, 128, 256, 512], size=n_req), ks)
+            starts = rng.integers(0, len(q) - 64, size=n_req)
+            c0 = srv.counters()
+            lat = np.full(n_req, np.nan)
+            tick = {}
+            rejected = 0
+            t0 = time.perf_counter()
+            i = 0
+            while i < n_req or srv.live:
+                now = time.perf_counter() - t0
+                while i < n_req and arrive[i] <= now:
+                    s = int(starts[i])
+                    try:
+                        tick[srv.submit(q[s:s + sizes[i]], int(ks[i]), int(efs[i]))] = i
+                    except P.PeosError as e:
+                        if e.code != P.PEOS_EBUSY:
+                            raise
+                        rejected += 1
+                    i += 1
+                for t, ids, _ in srv.poll(wait=False):
+                    j = tick.pop(t)
+                    lat[j] = time.perf_counter() - t0 - arrive[j]
+                    s = int(starts[j])
+                    sl = slice(s, s + sizes[j])
+                    rc = _recall(x, q[sl], ids[:, :10], gt_d[sl], 10, w.metric)
+                    hits += float(rc.sum())
+                    total += len(rc)
+            elapsed = time.perf_counter() - t0
+            c1 = srv.counters()
+            done = np.isfinite(lat)
+            batches = c1["launches"] - c0["launches"]
+            r = dict(rate=rate, requests=n_req, rejected=rejected,
+                     qps=round(float(sizes[done].sum()) / elapsed, 1),
+                     p50_ms=round(float(np.percentile(lat[done], 50) * 1e3), 3),
+                     p99_ms=round(float(np.percentile(lat[done], 99) * 1e3), 3),
+                     batches=int(batches),
+                     mean_batch=round((c1["queries"] - c0["queries"]) / max(1, batches), 1),
+                     seconds=round(elapsed, 3))
+            log(f"serving {r}")
+            per_rate.append(r)
+    finally:
+        srv.close()
+    top = max(per_rate, key=lambda r: r["qps"])
+    print(json.dumps({
+        "metric": "serving: completed queries/s under Poisson arrivals, p50/p99 latency",
+        "value": top["qps"], "unit": "queries/s", "n_gpus": 1, "steps": len(per_rate),
+        "warmup": 16, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "R": w.R, "L": w.L, "m": w.m,
+                   "eps": w.eps, "request_size": "U{1..64}", "k": "{10,100}",
+                   "ef": "{32,64,128,256,512}, max(ef,k)", "max_batch": 2048,
+                   "launch_slots": 4},
+        "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
+        "recall@10": round(hits / max(1, total), 4), "rates": per_rate,
+    }), flush=True)
 
 
 def cpu_baseline(x, g, entry, q, w, cfg, budget_s):

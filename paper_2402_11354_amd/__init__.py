@@ -10,12 +10,19 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpeos.so")
 
 PEOS_OK = 0
+PEOS_EINVAL = -1
+PEOS_ENOSPACE = -2
+PEOS_EHIP = -3
+PEOS_EGRAPH = -4
+PEOS_EDEVICE = -5
+PEOS_EBUSY = -6
 PEOS_METRIC_L2 = 0
 PEOS_METRIC_ANGULAR = 1
 PEOS_MODE_PEOS = 0
@@ -40,6 +47,15 @@ class peos_layout(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("entry", ctypes.c_int32),
                 ("node_stride", ctypes.c_int64), ("codes_offset", ctypes.c_int64),
                 ("scalars_offset", ctypes.c_int64), ("code_bytes", ctypes.c_int64)]
+
+
+class peos_serve_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("max_k", ctypes.c_int32),
+                ("max_ef", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("pool", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("launch_waves", ctypes.c_int32),
+                ("eps", ctypes.c_float), ("reserved", ctypes.c_float),
+                ("hbm_budget", ctypes.c_size_t), ("lds_budget", ctypes.c_size_t)]
 
 
 _lib = None
@@ -69,6 +85,12 @@ def lib():
         L.peos_search.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P, sz, P]
         L.peos_set_search_tuning.argtypes = [i32, i32, i32]
         L.peos_set_class_tuning.argtypes = [i32, i32, i32]
+        L.peos_serve_open.argtypes = [P, ctypes.POINTER(peos_serve_config), ctypes.POINTER(P)]
+        L.peos_serve_submit.argtypes = [P, P, i32, i32, i32, P, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.peos_serve_poll.argtypes = [P, i32, P, i32, ctypes.POINTER(i32)]
+        L.peos_serve_counters.argtypes = [P, P]
+        L.peos_serve_close.argtypes = [P]
+        L.peos_serve_close.restype = None
         L.peos_graph_create.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P,
                                         sz, ctypes.POINTER(P)]
         L.peos_graph_launch.argtypes = [P, P]
@@ -80,7 +102,8 @@ def lib():
         for name in ("peos_index_bytes", "peos_build_tables", "peos_index_layout",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
                      "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
-                     "peos_graph_create", "peos_graph_launch"):
+                     "peos_graph_create", "peos_graph_launch", "peos_serve_open",
+                     "peos_serve_submit", "peos_serve_poll", "peos_serve_counters"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -266,3 +289,72 @@ def search(index, queries, k, ef, eps=0.1, mode=PEOS_MODE_PEOS, pool=0, kstride=
         peos_search(index, queries, k, ef, ks, pool, eps, mode, ids, dists, stats, ws,
                     k_all=kmax, ef_all=efmax, stream=stream)
     return ids, dists, stats
+
+
+SERVE_COUNTERS = ("launches", "requests", "queries", "max_batch", "inflight", "pending", "slots",
+                  "lds_inflight")
+
+
+class Server:
+    """The serving loop (peos_serve_*): submit requests of host queries, poll
+    for completed ones.  Keeps each request's host buffers alive until it
+    completes."""
+
+    def __init__(self, index, max_batch=64, max_k=100, max_ef=512, max_inflight=4,
+                 max_pending=1 << 16, pool=1, mode=PEOS_MODE_PEOS, eps=0.1, launch_waves=0,
+                 hbm_budget=0, lds_budget=0):
+        cfg = peos_serve_config(max_batch, max_k, max_ef, max_inflight, max_pending, pool, mode,
+                                launch_waves, eps, 0.0, hbm_budget, lds_budget)
+        h = ctypes.c_void_p()
+        _check("peos_serve_open", lib().peos_serve_open(index.handle, ctypes.byref(cfg),
+                                                        ctypes.byref(h)))
+        self.handle = h
+        self.index = index
+        self.live = {}
+        self._done = np.zeros(4096, np.uint64)
+
+    def submit(self, queries, k, ef):
+        """queries: host (nq, d) float32.  Returns the ticket; raises
+        PeosError (code PEOS_EBUSY) when the queue is full."""
+        q = np.ascontiguousarray(queries, dtype=np.float32)
+        nq = q.shape[0]
+        ids = np.empty((nq, k), np.int64)
+        dists = np.empty((nq, k), np.float32)
+        t = ctypes.c_uint64()
+        _check("peos_serve_submit",
+               lib().peos_serve_submit(self.handle, q.ctypes.data, nq, int(k), int(ef),
+                                       ids.ctypes.data, dists.ctypes.data, ctypes.byref(t)))
+        self.live[t.value] = (q, ids, dists)
+        return t.value
+
+    def poll(self, wait=False):
+        """[(ticket, ids, dists)] of the requests completed since the last poll."""
+        out = []
+        n = ctypes.c_int32()
+        while True:
+            _check("peos_serve_poll", lib().peos_serve_poll(self.handle, 1 if wait else 0,
+                                                            self._done.ctypes.data,
+                                                            len(self._done), ctypes.byref(n)))
+            for t in self._done[:n.value].tolist():
+                _, ids, dists = self.live.pop(t)
+                out.append((t, ids, dists))
+            if n.value < len(self._done):
+                return out
+            wait = False
+
+    def counters(self):
+        c = np.zeros(8, np.int64)
+        _check("peos_serve_counters", lib().peos_serve_counters(self.handle, c.ctypes.data))
+        return dict(zip(SERVE_COUNTERS, c.tolist()))
+
+    def close(self):
+        if self.handle:
+            lib().peos_serve_close(self.handle)
+            self.handle = None
+            self.live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

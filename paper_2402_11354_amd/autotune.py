@@ -89,3 +89,65 @@ def tune(index, queries, k, ef, pool=0, eps=0.1, mode=0, caps=HASH_CAPS, reps=3,
     if use_cache:
         _store(cache)
     return best, times
+
+
+def ef_classes(k, ef):
+    """Host copy of the device's ef-class split: class c holds effective list
+    sizes max(min(ef, max ef), k) in (32 << (c-1), 32 << c]."""
+    import numpy as np
+    k = np.asarray(k)
+    ef = np.asarray(ef)
+    eff = np.maximum(np.minimum(ef, ef.max()), k)
+    efmax = int(max(ef.max(), k.max()))
+    nclass = 1
+    while nclass < 8 and efmax > (32 << (nclass - 1)):
+        nclass += 1
+    cls = np.zeros(len(eff), np.int64)
+    for c in range(nclass - 1):
+        cls += eff > (32 << c)
+    return cls
+
+
+def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS, reps=2,
+                 log=None):
+    """Pick the visited-hash capacity of every ef class of a batch with
+    per-query k and ef (host arrays), timing each class on its own queries,
+    and set it with peos_set_class_tuning.  Returns {class: hash_cap}."""
+    import numpy as np
+    from . import peos_set_class_tuning
+    cls = ef_classes(k, ef)
+    chosen = {}
+    dev = queries.device
+    for c in np.unique(cls).tolist():
+        sel = np.nonzero(cls == c)[0]
+        qs = queries[torch.from_numpy(sel).to(dev)]
+        kt = torch.from_numpy(np.ascontiguousarray(k[sel], dtype=np.int32)).to(dev)
+        et = torch.from_numpy(np.ascontiguousarray(ef[sel], dtype=np.int32)).to(dev)
+        efmax = int(max(ef[sel].max(), k[sel].max()))
+        ws = torch.empty(peos_search_ws_bytes(index, len(sel), efmax, pool), dtype=torch.uint8,
+                         device=dev)
+        times = {}
+        for cap in caps:
+            peos_set_class_tuning(c, cap, 0)
+            try:
+                search(index, qs, kt, et, eps=eps, mode=mode, pool=pool, ws=ws)
+            except RuntimeError:
+                continue
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                search(index, qs, kt, et, eps=eps, mode=mode, pool=pool, ws=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            times[cap] = e0.elapsed_time(e1) / reps
+        best = min(times, key=times.get)
+        if 0 in times and times[best] > (1.0 - KEEP_DEFAULT) * times[0]:
+            best = 0
+        peos_set_class_tuning(c, best, 0)
+        chosen[c] = best
+        if log:
+            log(f"autotune class {c} ({len(sel)} queries, ef <= {efmax}): "
+                + " ".join(f"{cp}:{t:.3f}ms" for cp, t in times.items()) + f" -> {best}")
+    return chosen

@@ -87,12 +87,18 @@ class _Model:
             self.scales = np.exp(rng.normal(math.log(0.3), 0.5, size=(256, w.d)))
             self.weights = np.full(256, 1.0 / 256)
         elif w.family in ("sphere1000", "sphere500"):
-            # vMF-like clusters on the sphere: normalize(mu + 0.25 N(0, I)).
+            # vMF-like clusters on the sphere: normalize(mu_c + 2.5 s * z),
+            # mu_c uniform on the sphere, z ~ N(0, I), and a decaying
+            # per-dimension spectrum s_j ~ (j+1)^-1/2 with |s| = 1, the shape of
+            # PCA-compressed descriptors (the noise norm of 2.5 makes
+            # neighbouring clusters overlap, as real descriptor clusters do).
             self.kind = "sphere"
             ncl = 1000 if w.family == "sphere1000" else 500
             mu = rng.normal(size=(ncl, w.d))
             self.centers = mu / np.linalg.norm(mu, axis=1, keepdims=True)
             self.weights = np.full(ncl, 1.0 / ncl)
+            spec = (np.arange(w.d) + 1.0) ** -0.5
+            self.spectrum = 2.5 * spec / np.linalg.norm(spec)
         else:
             raise ValueError(f"unknown family {w.family}")
 
@@ -106,7 +112,7 @@ class _Model:
             elif self.kind == "expint":
                 x = np.minimum(255.0, np.floor(rng.exponential(1.0, size=(c, self.w.d)) * self.means[z]))
             else:
-                x = self.centers[z] + 0.25 * rng.standard_normal((c, self.w.d))
+                x = self.centers[z] + self.spectrum * rng.standard_normal((c, self.w.d))
                 x /= np.linalg.norm(x, axis=1, keepdims=True)
             out[s:s + c] = x
         return out

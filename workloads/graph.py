@@ -98,6 +98,76 @@ def knn(base: torch.Tensor, queries: torch.Tensor, k: int, exclude_self: bool = 
     return out_i, out_d
 
 
+def knn_ivf(x: torch.Tensor, k: int, nlist: int = 2048, nprobe: int = 12, iters: int = 8,
+            seed: int = 0, log=None):
+    """Approximate k nearest neighbours of every row of x among the rows of x
+    (self excluded), for bases too large for the exact product: k-means
+    centroids from a sample; every row scans the primary lists of its
+    `nprobe` nearest centroids, one probe rank at a time, merging into a
+    running top-k ordered by (distance, id).  Returns (ids, dists) like knn."""
+    n, d = x.shape
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    sample = x[torch.randperm(n, generator=g)[:min(n, 64 * nlist)].to(x.device)]
+    cent = sample[:nlist].clone()
+    for _ in range(iters):
+        a, _ = knn(cent, sample, 1)
+        a = a[:, 0]
+        sums = torch.zeros_like(cent).index_add_(0, a, sample)
+        cnt = torch.bincount(a, minlength=nlist).to(x.dtype)
+        ok = cnt > 0
+        cent[ok] = sums[ok] / cnt[ok, None]
+    probes, _ = knn(cent, x, nprobe, row_chunk=16384)        # n x nprobe, nearest first
+    primary = probes[:, 0]
+    order = torch.argsort(primary, stable=True)
+    counts = torch.bincount(primary, minlength=nlist)
+    starts = (torch.cumsum(counts, 0) - counts).tolist()
+    counts = counts.tolist()
+    kk = k + 1
+    best_i = torch.full((n, kk), -1, dtype=torch.int64, device=x.device)
+    best_d = torch.full((n, kk), math.inf, dtype=x.dtype, device=x.device)
+    for j in range(nprobe):
+        if log:
+            log(f"ivf probe {j + 1}/{nprobe}")
+        pj = probes[:, j]
+        qord = torch.argsort(pj, stable=True)
+        qcnt = torch.bincount(pj, minlength=nlist)
+        qst = (torch.cumsum(qcnt, 0) - qcnt).tolist()
+        qcnt = qcnt.tolist()
+        cur_i = torch.full((n, kk), -1, dtype=torch.int64, device=x.device)
+        cur_d = torch.full((n, kk), math.inf, dtype=x.dtype, device=x.device)
+        for c in range(nlist):
+            if qcnt[c] == 0 or counts[c] == 0:
+                continue
+            members = order[starts[c]:starts[c] + counts[c]]
+            b = x[members]
+            bn = _sqnorm(b)
+            qs = qord[qst[c]:qst[c] + qcnt[c]]
+            for q0 in range(0, qs.shape[0], 8192):
+                qi = qs[q0:q0 + 8192]
+                q = x[qi]
+                dd = _sqnorm(q)[:, None] + bn[None, :] - 2.0 * (q @ b.T.contiguous())
+                dd.clamp_(min=0)
+                dd[members[None, :] == qi[:, None]] = math.inf
+                t = min(kk, members.shape[0])
+                vd, vi = torch.topk(dd, t, dim=1, largest=False, sorted=False)
+                cur_i[qi, :t] = members[vi]
+                cur_d[qi, :t] = vd
+        # merge (the lists of different probes are disjoint)
+        ci = torch.cat([best_i, cur_i], 1)
+        cd = torch.cat([best_d, cur_d], 1)
+        cd = torch.where(ci >= 0, cd, torch.full_like(cd, math.inf))
+        big = torch.iinfo(torch.int64).max
+        key = torch.where(ci >= 0, ci, torch.full_like(ci, big))
+        o = torch.argsort(key, dim=1, stable=True)
+        ci, cd = torch.gather(ci, 1, o), torch.gather(cd, 1, o)
+        o = torch.argsort(cd, dim=1, stable=True)
+        best_i, best_d = torch.gather(ci, 1, o)[:, :kk], torch.gather(cd, 1, o)[:, :kk]
+        del ci, cd, cur_i, cur_d, key, o
+    best_i, best_d = best_i[:, :k], best_d[:, :k]
+    best_i = torch.where(torch.isfinite(best_d), best_i, torch.full_like(best_i, -1))
+    return best_i, best_d
+
+
 def _prune(x: torch.Tensor, cand_i: torch.Tensor, cand_d: torch.Tensor, R: int,
            chunk: int = 16384):
     """Relative-neighbourhood pruning of ordered candidate lists (see module
@@ -248,13 +318,22 @@ def medoid(x: torch.Tensor, exact_limit: int = 20000) -> int:
     return int(torch.argmin(_sqnorm(x - mu)))
 
 
+EXACT_KNN_LIMIT = 2_000_000
+
+
 def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool = True,
                 log=None):
     """Pruned exact-kNN graph (module docstring).  Returns (graph int32 n x R
-    padded with -1, entry id).  `log` receives progress lines."""
+    padded with -1, entry id).  `log` receives progress lines.  Above
+    EXACT_KNN_LIMIT rows the candidates come from knn_ivf (approximate)."""
     device, dt = _dev_dtype(device)
     x = torch.as_tensor(base).to(device=device, dtype=dt)
-    ci, cd = knn(x, x, cand, exclude_self=True, log=log)
+    if x.shape[0] > EXACT_KNN_LIMIT:
+        ci, cd = knn_ivf(x, cand, log=log)
+        if log:
+            log("ivf knn done")
+    else:
+        ci, cd = knn(x, x, cand, exclude_self=True, log=log)
     if log:
         log("knn done, pruning")
     gi, gd = _prune(x, ci, cd, R)
@@ -291,9 +370,9 @@ def ground_truth(base: np.ndarray, queries: np.ndarray, k: int, metric: int, dev
         kk = min(k + 8, x.shape[0])
         v, i = torch.topk(sim, kk, dim=1)
         dd = 1.0 - v
-        o = torch.argsort(i, 1, stable=True)
+        o = torch.argsort(i, dim=1, stable=True)
         i, dd = torch.gather(i, 1, o), torch.gather(dd, 1, o)
-        o = torch.argsort(dd, 1, stable=True)
+        o = torch.argsort(dd, dim=1, stable=True)
         ids_all.append(torch.gather(i, 1, o)[:, :k])
         d_all.append(torch.gather(dd, 1, o)[:, :k])
     return torch.cat(ids_all).cpu().numpy(), torch.cat(d_all).cpu().numpy()
