@@ -33,6 +33,7 @@ MODE_EXHAUSTIVE = 1
 COUNTERS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0",
             "test_h", "test_zero", "passes", "ndist", "inserted")
 F_HT, F_A1, F_A0, F_DELTA, F_ORDER = 1, 2, 4, 8, 16
+LP_BF16_BASE, LP_FP16 = 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "peos_oracle.c")
@@ -69,11 +70,15 @@ def _load():
         lib.oracle_build_tables.restype = i32
         lib.oracle_query_table.argtypes = [P, i32, i32, i32, P, P, P]
         lib.oracle_query_table.restype = None
-        lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, P]
+        lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, i32, P]
         lib.oracle_test_edge.restype = i32
         lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
-                                      i32, i32, f64, i32, f64, i32, i32, P, P, P, P, P, P]
+                                      i32, i32, f64, i32, f64, i32, i32, i32, P, P, P, P, P, P]
         lib.oracle_search.restype = i32
+        lib.oracle_round_half.argtypes = [f64]
+        lib.oracle_round_half.restype = f64
+        lib.oracle_round_bf16.argtypes = [ctypes.c_float]
+        lib.oracle_round_bf16.restype = ctypes.c_float
         _lib = lib
     return _lib
 
@@ -89,6 +94,16 @@ def _f32(a):
 # ---------------------------------------------------------------------------
 # constants
 # ---------------------------------------------------------------------------
+def round_half(x: float) -> float:
+    """Nearest binary16 value (ties to even), as a float."""
+    return _load().oracle_round_half(float(x))
+
+
+def round_bf16(x: float) -> float:
+    """Nearest bfloat16 value of a float32 (ties to even)."""
+    return _load().oracle_round_bf16(float(x))
+
+
 def norm_ppf(p: float) -> float:
     """Standard normal quantile (bisection on the erfc form of the CDF)."""
     return _load().oracle_norm_ppf(float(p))
@@ -150,13 +165,14 @@ def query_table(q, L, m, A, B):
     return out
 
 
-def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps):
+def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps, lowp=0):
     """One routing test of edge (v, u) against furthest result p.
-    Returns (pass, A_r, H, T, kind) with kind 0 zero edge / 1 A>=1 / 2 A<=0 / 3 H-vs-T."""
+    Returns (pass, A_r, H, T, kind) with kind 0 zero edge / 1 A>=1 / 2 A<=0 / 3 H-vs-T.
+    lowp = LP_FP16: the precision-form test (half-rounded scalars and table)."""
     xv, xu, xp, q, A, B = map(_f32, (xv, xu, xp, q, A, B))
     out = np.zeros(4, np.float64)
     ok = _load().oracle_test_edge(_p(xv), _p(xu), _p(xp), _p(q), q.shape[0], L, m, _p(A), _p(B),
-                                  metric, float(eps), _p(out))
+                                  metric, float(eps), int(lowp), _p(out))
     return bool(ok), out[0], out[1], out[2], int(out[3])
 
 
@@ -164,12 +180,16 @@ def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps):
 # Alg. 1
 # ---------------------------------------------------------------------------
 def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MODE_PEOS,
-           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64):
+           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0):
     """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
     pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
     pool <= ef = the HNSW stopping rule.  precision: 64 = distances in float64;
     32 = the distance decisions taken on the canonical single-precision
     distances (the GPU kernel's precision; see dist32 in peos_oracle.c).
+    lowp: precision form (implies precision 32): LP_FP16 = routing test on
+    half-rounded edge scalars and tables; LP_BF16_BASE = traversal on the
+    bfloat16-rounded base, result list re-ranked in single precision on the
+    full base (see routing_test_lowp and oracle_search in peos_oracle.c).
     Returns dict(ids (nq, kstride) int64, dist (as decided), dist64 float64,
     counters (nq, 11) int64, fragile (nq,) int32 flag words, status (nq,) int32)."""
     if precision not in (32, 64):
@@ -193,7 +213,8 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     rc = _load().oracle_search(_p(base), n, d, _p(graph), graph.shape[1], int(entry), L, m, _p(A),
                                _p(B), metric, _p(queries), nq, _p(karr), _p(efarr), ks,
                                int(pool), float(eps), mode, float(tau), 1 if precision == 32 else 0,
-                               nt, _p(ids), _p(dist), _p(dist64), _p(cnt), _p(frag), _p(status))
+                               int(lowp), nt, _p(ids), _p(dist), _p(dist64), _p(cnt), _p(frag),
+                               _p(status))
     if rc:
         raise ValueError("bad search arguments")
     return dict(ids=ids, dist=dist, dist64=dist64, counters=cnt, fragile=frag, status=status)

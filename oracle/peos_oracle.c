@@ -94,6 +94,46 @@ double oracle_norm_ppf(double p)
  * margin[i] returns the relative gap between the two largest |p| (a near-tie
  * diagnostic only).
  */
+/* ------------------------------------------------------------------ */
+/* Storage roundings of the precision form                              */
+/* ------------------------------------------------------------------ */
+/*
+ * Nearest IEEE binary16 value of x (ties to even), as a double: 11
+ * significant bits for |x| >= 2^-14, a fixed step of 2^-24 below (subnormal
+ * numbers), and infinity from 65520 on (the first value that rounds past the
+ * largest finite half, 65504).  rint() rounds to nearest even.
+ */
+double oracle_round_half(double x)
+{
+    if (!isfinite(x) || x == 0.0) return x;
+    const double ax = fabs(x);
+    double r;
+    if (ax < ldexp(1.0, -14)) {
+        r = rint(ax * ldexp(1.0, 24)) * ldexp(1.0, -24);
+    } else {
+        int e;
+        frexp(ax, &e);                  /* ax = f * 2^e, f in [0.5, 1) */
+        const double ulp = ldexp(1.0, e - 11);
+        r = rint(ax / ulp) * ulp;
+        if (r > 65504.0) r = INFINITY;
+    }
+    return x < 0 ? -r : r;
+}
+
+/* Nearest bfloat16 value of a float (ties to even): the float's upper 16
+ * bits after rounding its lower 16 bits away. */
+float oracle_round_bf16(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return x; /* inf, nan */
+    u += 0x7fffu + ((u >> 16) & 1u);
+    u &= 0xffff0000u;
+    float r;
+    memcpy(&r, &u, 4);
+    return r;
+}
+
 static void edge_codes_fp32(const float* xv, const float* xu, int d, int L, int m,
                             const float* A, const float* B, float* ework, float* eres,
                             uint8_t* codes, double* margin)
@@ -367,6 +407,10 @@ typedef struct {
     int L, m, metric;
 } test_params;
 
+/* precision-form flags (the library's index flags of the same values) */
+#define LP_BF16_BASE 1  /* traversal distances on the bfloat16-rounded base  */
+#define LP_FP16 2       /* edge scalars and projection tables stored as half */
+
 /*
  * Threshold of step (4)/(6): the eps-quantile of
  * N(x sqrt(2 L ln m), w_reg^2 + L w_res^2 - L x^2/(L+1)), written in closed
@@ -396,16 +440,18 @@ static int routing_test(const test_params* tp, const edge_rec* er, const double*
     *outA = NAN;
     *outH = NAN;
     *outT = NAN;
+    /* the numerator is exactly 0 in any precision only for the angular
+       metric with v = p; for l2 it is then g_e */
+    const int exact0 = v_is_p && tp->metric == OR_ANGULAR;
     if (er->norm_e == 0.0) {
         *kind = 0;
-        if (!v_is_p && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
+        if (!exact0 && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
         return num < 0.0;
     }
     double A = num / (qnorm * er->norm_e);
     *outA = A;
     if (fabs(A - 1.0) < tau) *flags |= F_A1;
-    /* A = 0 exactly when v is p itself, identically in any precision */
-    if (!v_is_p && fabs(A) < tau) *flags |= F_A0;
+    if (!exact0 && fabs(A) < tau) *flags |= F_A0;
     if (A >= 1.0) { *kind = 1; return 0; }
     if (A <= 0.0) { *kind = 2; return 1; }
     *kind = 3;
@@ -414,6 +460,58 @@ static int routing_test(const test_params* tp, const edge_rec* er, const double*
     double H2 = lookup(table, tp->m, 0, er->codes[0]);
     double H = er->w_reg * H1 + sqrt((double)tp->L) * er->w_res * H2;
     double T = oracle_threshold(A, er->w_reg, er->w_res, tp->L, tp->eta, tp->c_eps);
+    *outH = H;
+    *outT = T;
+    if (fabs(H - T) < tau * (fabs(H) + fabs(T) + 1e-30)) *flags |= F_HT;
+    return H >= T;
+}
+
+/*
+ * Step (6) in the precision form.  The edge's scalars are stored as halves:
+ * gp = g_e / |e| with g_e = (|u|^2 - |v|^2)/2 (0 for angular), ie = 1/|e|,
+ * wr = w_reg, sr = sqrt(L) w_res, each the nearest half of its exact value;
+ * the table entries are the nearest halves of the exact table.  The
+ * numerator of A_r is taken from the search's own distances, which is the
+ * same quantity: |u|^2/2 - r - v.q = g_e + (dist_v - delta)/2 for squared
+ * l2 (and dist_v - delta for angular), so A_r = (gp + (dist_v - delta)/2 *
+ * ie) / |q|, or (dist_v - delta) * ie.  An edge whose 1/|e| is not finite
+ * as a half (|e| = 0, or below the half range) is decided by the sign of the
+ * numerator, as a zero-length edge.
+ */
+static int routing_test_lowp(const test_params* tp, const edge_rec* er, const double* table16,
+                             double dv, double delta, double qnorm, double* outA, double* outH,
+                             double* outT, int* kind, int* flags, int v_is_p)
+{
+    const double tau = tp->tau;
+    const int L = tp->L;
+    *outA = NAN;
+    *outH = NAN;
+    *outT = NAN;
+    const double diff = tp->metric == OR_L2 ? 0.5 * (dv - delta) : (dv - delta);
+    const double ie = er->norm_e > 0.0 ? oracle_round_half(1.0 / er->norm_e) : INFINITY;
+    const int exact0 = v_is_p && tp->metric == OR_ANGULAR;
+    if (!isfinite(ie)) {
+        *kind = 0;
+        if (!v_is_p && fabs(diff) <= tau * (fabs(dv) + fabs(delta))) *flags |= F_A0;
+        return diff < 0.0;
+    }
+    const double gp = tp->metric == OR_L2
+                          ? oracle_round_half(0.5 * (er->nu2 - er->nv2) / er->norm_e) : 0.0;
+    const double wr = oracle_round_half(er->w_reg);
+    const double sr = oracle_round_half(sqrt((double)L) * er->w_res);
+    const double A = tp->metric == OR_L2 ? (gp + diff * ie) / qnorm : diff * ie;
+    *outA = A;
+    if (fabs(A - 1.0) < tau) *flags |= F_A1;
+    if (!exact0 && fabs(A) < tau) *flags |= F_A0;
+    if (A >= 1.0) { *kind = 1; return 0; }
+    if (A <= 0.0) { *kind = 2; return 1; }
+    *kind = 3;
+    double H1 = 0.0;
+    for (int i = 1; i <= L; ++i) H1 += lookup(table16, tp->m, i, er->codes[i]);
+    const double H2 = lookup(table16, tp->m, 0, er->codes[0]);
+    const double H = wr * H1 + sr * H2;
+    const double var = wr * wr + sr * sr - (double)L * A * A / (double)(L + 1);
+    const double T = A * tp->eta + tp->c_eps * sqrt(var);
     *outH = H;
     *outT = T;
     if (fabs(H - T) < tau * (fabs(H) + fabs(T) + 1e-30)) *flags |= F_HT;
@@ -468,6 +566,8 @@ static double dist64(const float* x, const float* q, double qnorm, int d, int me
  * sums are added as a fixed binary tree: (0+1), (2+3), ... then pairs of
  * those, and so on.  Angular distance = fmaf(-s, 1/|q|, 1), with |q| =
  * sqrtf((p0 + p1) + (p2 + p3)), p_j the fmaf chain of q_k^2 over k = j mod 4.
+ * With bf16 set, every coordinate of x is first rounded to bfloat16 (the
+ * traversal copy of the precision form).
  */
 static float qnorm32(const float* q, int d)
 {
@@ -480,7 +580,7 @@ static float qnorm32(const float* q, int d)
     return sqrtf((p[0] + p[1]) + (p[2] + p[3]));
 }
 
-static float dist32(const float* x, const float* q, int d, int metric, float inv_qn)
+static float dist32(const float* x, const float* q, int d, int metric, float inv_qn, int bf16)
 {
     float seg[16];
     const int nch = d / 4;
@@ -488,7 +588,8 @@ static float dist32(const float* x, const float* q, int d, int metric, float inv
         float acc = 0.0f;
         for (int c = s; c < nch; c += 16) {
             for (int t = 0; t < 4; ++t) {
-                const float xv = x[4 * c + t], qv = q[4 * c + t];
+                const float xv = bf16 ? oracle_round_bf16(x[4 * c + t]) : x[4 * c + t];
+                const float qv = q[4 * c + t];
                 if (metric == OR_L2) {
                     const float df = xv - qv;
                     acc = fmaf(df, df, acc);
@@ -508,7 +609,7 @@ typedef struct {
     const float *base, *A, *B, *queries;
     const int32_t *graph, *k, *ef;
     int64_t n, q0, q1;
-    int d, R, L, m, metric, mode, entry, kstride, pool, fp32;
+    int d, R, L, m, metric, mode, entry, kstride, pool, fp32, lowp;
     double eps, tau;
     int64_t* out_ids;
     double* out_dist;
@@ -553,7 +654,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
     double qnorm = sqrt(dot64(q, q, d));
     const float qn32 = qnorm32(q, d);
     const float inv_qn32 = 1.0f / qn32;
-#define DIST(xp) (j->fp32 ? (double)dist32((xp), q, d, j->metric, inv_qn32) \
+#define DIST(xp) (j->fp32 ? (double)dist32((xp), q, d, j->metric, inv_qn32, j->lowp & LP_BF16_BASE) \
                           : dist64((xp), q, qnorm, d, j->metric))
     if (!(qnorm > 0.0) || !isfinite(qnorm) || (j->fp32 && !(qn32 > 0.0f && isfinite(qn32)))) {
         j->status[qi] = -1;
@@ -564,7 +665,11 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         }
         return;
     }
-    if (j->mode == OR_MODE_PEOS) oracle_query_table(q, d, j->L, j->m, j->A, j->B, table);
+    if (j->mode == OR_MODE_PEOS) {
+        oracle_query_table(q, d, j->L, j->m, j->A, j->B, table);
+        if (j->lowp & LP_FP16)
+            for (int t = 0; t < (j->L + 1) * j->m; ++t) table[t] = oracle_round_half(table[t]);
+    }
 
     memset(visited, 0, (size_t)j->n);
     int size = 0;
@@ -587,6 +692,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         const int32_t v = R[pos].id;
         const float* xv = j->base + (size_t)v * d;
         const int full = (size >= efq);
+        const double dv = R[pos].dist;
         const double delta = full ? R[efq - 1].dist : INFINITY;
         const int32_t p = full ? R[efq - 1].id : -1;
         double vq = 0.0, r = 0.0;
@@ -611,7 +717,12 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
                 else num = -r - vq;
                 double A, H, T;
                 int kind;
-                pass = routing_test(tp, &er, table, num, qnorm, &A, &H, &T, &kind, &flags, v == p);
+                if (j->lowp & LP_FP16)
+                    pass = routing_test_lowp(tp, &er, table, dv, delta, qnorm, &A, &H, &T, &kind,
+                                             &flags, v == p);
+                else
+                    pass = routing_test(tp, &er, table, num, qnorm, &A, &H, &T, &kind, &flags,
+                                        v == p);
                 cnt[C_TESTS]++;
                 cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
                 if (pass) cnt[C_PASSES]++;
@@ -646,6 +757,14 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             double sc = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
             if (a != b && fabs(a - b) < j->tau * sc) flags |= F_ORDER;
         }
+    }
+    if (j->lowp & LP_BF16_BASE) {
+        /* precision form: the result list (first ef entries) re-ranked by
+           single-precision distances on the full-precision base */
+        const int nr = size < efq ? size : efq;
+        for (int i = 0; i < nr; ++i)
+            R[i].dist = (double)dist32(j->base + (size_t)R[i].id * d, q, d, j->metric, inv_qn32, 0);
+        qsort(R, (size_t)nr, sizeof(rentry), rcmp);
     }
     for (int t = 0; t < j->kstride; ++t) {
         int64_t o = (size_t)qi * j->kstride + t;
@@ -713,12 +832,18 @@ static void* search_worker(void* arg)
  * out_ids / out_dist: nq x kstride, first k entries of R, padded (-1, +inf).
  * Distances: squared l2, or 1 - x.q/|q| for the angular metric.
  * counters: nq x C_NCOUNT int64; fragile: nq flag words; status: 0 ok, -1
- * zero/non-finite query.  Returns 0, or -1 on bad arguments.
+ * zero/non-finite query.  lowp: precision-form flags (LP_*, implies fp32):
+ * LP_FP16 takes the routing test on half-rounded scalars and tables
+ * (routing_test_lowp); LP_BF16_BASE takes the traversal distances on the
+ * bfloat16-rounded base and re-ranks the final result list with
+ * full-precision single-precision distances before the first k are taken.
+ * Returns 0, or -1 on bad arguments.
  */
 int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,
                   int L, int m, const float* A, const float* B, int metric, const float* queries,
                   int64_t nq, const int32_t* k, const int32_t* ef, int kstride, int pool,
-                  double eps, int mode, double tau, int fp32, int nthreads, int64_t* out_ids,
+                  double eps, int mode, double tau, int fp32, int lowp, int nthreads,
+                  int64_t* out_ids,
                   double* out_dist, double* out_dist64, int64_t* counters, int32_t* fragile,
                   int32_t* status)
 {
@@ -733,18 +858,20 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
                                nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
-                               pool, fp32, eps, tau, out_ids, out_dist, out_dist64, counters,
-                               fragile, status};
+                               pool, fp32 || lowp, lowp, eps, tau, out_ids, out_dist, out_dist64,
+                               counters, fragile, status};
         pthread_create(&th[t], NULL, search_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
     return 0;
 }
 
-/* Public: one routing test, for the pins.  Returns pass (1/0); out = {A, H, T, kind}. */
+/* Public: one routing test, for the pins.  Returns pass (1/0); out = {A, H, T, kind}.
+ * lowp & LP_FP16: the precision-form test (routing_test_lowp) with dist_v and
+ * delta the single-precision distances of v and p. */
 int oracle_test_edge(const float* xv, const float* xu, const float* xp, const float* q, int d,
                      int L, int m, const float* A, const float* B, int metric, double eps,
-                     double* out)
+                     int lowp, double* out)
 {
     float* fw1 = (float*)malloc(sizeof(float) * d);
     float* fw2 = (float*)malloc(sizeof(float) * d);
@@ -760,7 +887,15 @@ int oracle_test_edge(const float* xv, const float* xu, const float* xp, const fl
     double num = metric == OR_L2 ? 0.5 * er.nu2 - r - vq : -r - vq;
     double a, h, t;
     int kind, flags = 0;
-    int pass = routing_test(&tp, &er, table, num, qnorm, &a, &h, &t, &kind, &flags, 0);
+    int pass;
+    if (lowp & LP_FP16) {
+        for (int i = 0; i < (L + 1) * m; ++i) table[i] = oracle_round_half(table[i]);
+        const float iq = 1.0f / qnorm32(q, d);
+        const double dv = dist32(xv, q, d, metric, iq, 0), dp = dist32(xp, q, d, metric, iq, 0);
+        pass = routing_test_lowp(&tp, &er, table, dv, dp, qnorm, &a, &h, &t, &kind, &flags, 0);
+    } else {
+        pass = routing_test(&tp, &er, table, num, qnorm, &a, &h, &t, &kind, &flags, 0);
+    }
     out[0] = a;
     out[1] = h;
     out[2] = t;

@@ -695,3 +695,138 @@ def test_fp32_decisions_equal_fp64_away_from_near_ties(metric, pool_mul):
     assert np.array_equal(o64["ids"][clean], o32["ids"][clean])
     assert np.array_equal(o64["counters"][clean], o32["counters"][clean])
     np.testing.assert_allclose(o32["dist64"][clean], o64["dist"][clean], rtol=0, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# the precision form: storage roundings, bfloat16 traversal + re-rank, half
+# tables and scalars
+# ---------------------------------------------------------------------------
+def test_round_half_matches_ieee_binary16():
+    """Against numpy's conversion of doubles to IEEE half (round to nearest
+    even), over normal, subnormal, tie and overflow values."""
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([
+        rng.normal(size=2000) * 10.0 ** rng.uniform(-9, 5, size=2000),
+        [0.0, -0.0, 1.0, 65504.0, 65519.99, 65520.0, 1e6, 2.0 ** -24, 2.0 ** -25,
+         3 * 2.0 ** -26, 2.0 ** -14, (1 + 2.0 ** -11), (1 + 3 * 2.0 ** -11), -(1 + 2.0 ** -11)],
+    ])
+    for x in xs:
+        with np.errstate(over="ignore"):
+            ref = float(np.float16(np.float64(x)))
+        got = O.round_half(x)
+        assert got == ref or (math.isinf(got) and math.isinf(ref) and got == ref), x
+
+
+def test_round_bf16_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(1)
+    xs = (rng.normal(size=3000) * 10.0 ** rng.uniform(-30, 30, size=3000)).astype(np.float32)
+    xs = np.concatenate([xs, np.float32([1.00390625, 1.01171875, -1.00390625, 3.0, 0.0])])
+    ref = torch.from_numpy(xs).to(torch.bfloat16).to(torch.float32).numpy()
+    got = np.array([O.round_bf16(v) for v in xs], np.float32)
+    assert np.array_equal(got, ref)
+
+
+def _tiny_case(metric, n=1500, nq=50):
+    w = W.TINY.with_sizes(n=n, nq=nq)
+    x, q = W.make_base(w), W.make_queries(w)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    return w, x, q, g, entry, A, B
+
+
+@pytest.mark.parametrize("mode", [O.MODE_PEOS, O.MODE_EXHAUSTIVE])
+def test_bf16_traversal_on_bf16_exact_data_equals_fp32(mode):
+    """Integer data in 0..255 is exact in bfloat16: the bfloat16 traversal
+    and its re-rank change nothing."""
+    w = W.SIFT_LIKE.with_sizes(n=3000, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    a = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, w.metric, 0.1, mode=mode, precision=32)
+    b = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, w.metric, 0.1, mode=mode,
+                 lowp=O.LP_BF16_BASE)
+    assert np.array_equal(a["ids"], b["ids"]) and np.array_equal(a["dist"], b["dist"])
+    assert np.array_equal(a["counters"], b["counters"])
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_bf16_rerank_returns_full_precision_order(metric):
+    """The bfloat16 traversal's output is re-ranked on the full base: the
+    returned distances are the single-precision distances of the returned
+    ids, ascending, within the single-precision bound of float64."""
+    w, x, q, g, entry, A, B = _tiny_case(metric)
+    out = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, lowp=O.LP_BF16_BASE)
+    d, d64 = out["dist"], out["dist64"]
+    assert np.all(np.diff(d, axis=1) >= 0)
+    u = 2.0 ** -24
+    if metric == W.L2:
+        assert np.all(np.abs(d - d64) <= (w.d + 2) * u * d64)
+    else:
+        assert np.all(np.abs(d - d64) <= (w.d + 4) * u)
+    # recall is essentially unchanged by the bfloat16 traversal
+    ref = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, precision=32)
+    gt, _ = O.brute_force(x, q, 10, metric)
+    r_lo = np.mean([len(set(out["ids"][i]) & set(gt[i])) for i in range(len(q))]) / 10
+    r_hi = np.mean([len(set(ref["ids"][i]) & set(gt[i])) for i in range(len(q))]) / 10
+    assert r_lo >= r_hi - 0.02
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_half_test_within_rounding_bound_of_exact_test(metric):
+    """The precision-form test (half scalars and table) differs from the
+    exact test only by the half rounding: |A' - A| and |H' - H| stay within
+    the bound that 2^-11 relative errors of each stored value give, and the
+    decision is the same whenever the exact margins exceed that bound."""
+    rng = np.random.default_rng(3)
+    d, L, m = 32, 4, 16
+    A_, B_ = W.make_directions(L, m, d, 5)
+    agree = checked = 0
+    for _ in range(400):
+        xv, xu, xp, q = (rng.normal(size=d).astype(np.float32) for _ in range(4))
+        xu = (xv + 0.4 * (xu - xv)).astype(np.float32)
+        if metric == W.ANGULAR:
+            xv, xu, xp = (v / np.linalg.norm(v) for v in (xv, xu, xp))
+            xv, xu, xp = (v.astype(np.float32) for v in (xv, xu, xp))
+        p0, A0, H0, T0, k0 = O.test_edge(xv, xu, xp, q, L, m, A_, B_, metric, 0.1)
+        p1, A1, H1, T1, k1 = O.test_edge(xv, xu, xp, q, L, m, A_, B_, metric, 0.1,
+                                         lowp=O.LP_FP16)
+        u = 2.0 ** -11
+        e = xu.astype(np.float64) - xv
+        ne = np.linalg.norm(e)
+        qn = np.linalg.norm(q.astype(np.float64))
+        if metric == W.L2:
+            g = 0.5 * (np.dot(xu, xu) - np.dot(xv, xv)) / ne
+            num_scale = (abs(g) + abs(A0 * qn - g)) / qn
+        else:
+            num_scale = abs(A0)
+        # A' = (g' + diff ie') / |q|: each stored factor off by <= 2^-11
+        # relative, the distances by single-precision rounding
+        bA = 3 * u * num_scale + 1e-5 * (1 + abs(A0))
+        assert abs(A1 - A0) <= bA
+        if k0 == 3 and k1 == 3:
+            t = O.query_table(q, L, m, A_, B_)
+            bH = 3 * u * (np.abs(t).sum() * 2.0)
+            assert abs(H1 - H0) <= bH
+            bT = abs(T0 - T1)
+            if abs(H0 - T0) > bH + 6.6 * bA + 3 * u * abs(T0) + bT:
+                checked += 1
+                agree += p0 == p1
+        elif k0 != 3 and abs(A0) > bA and abs(A0 - 1) > bA:
+            checked += 1
+            agree += p0 == p1
+    assert checked > 100 and agree == checked
+
+
+def test_half_search_mostly_equals_exact_decisions():
+    """Search with half-rounded scalars and tables (same traversal distances):
+    most queries take the same path as with exact values; the rest differ
+    only where a decision margin is within the rounding."""
+    w, x, q, g, entry, A, B = _tiny_case(W.L2, n=2000, nq=100)
+    a = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, w.metric, 0.1, precision=32)
+    b = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, w.metric, 0.1, lowp=O.LP_FP16)
+    same = np.all(a["ids"] == b["ids"], axis=1) & np.all(a["counters"] == b["counters"], axis=1)
+    assert same.mean() >= 0.8
+    assert np.array_equal(a["counters"][:, 0] > 0, b["counters"][:, 0] > 0)
