@@ -88,7 +88,8 @@ def main():
     ap.add_argument("--pool", default="ef")
     ap.add_argument("--eps", type=float, default=0.1)
     ap.add_argument("--hash-cap", type=int, default=0, help="with --profile-only: visited-hash capacity")
-    ap.add_argument("--mode", default="headline", choices=("headline", "batched", "serving"),
+    ap.add_argument("--mode", default="headline",
+                    choices=("headline", "batched", "serving", "precision"),
                     help="headline: the QPS-at-recall comparison (default); batched: one "
                          "captured launch over a batch of uneven k/ef; serving: the request "
                          "loop under Poisson arrivals")
@@ -123,6 +124,8 @@ def main():
         return batched(args)
     if args.mode == "serving":
         return serving(args)
+    if args.mode == "precision":
+        return precision(args)
 
     import paper_2402_11354_amd as P
     import workloads as W
@@ -386,47 +389,56 @@ def batched(args):
     ids = torch.empty((nq, kmax), dtype=torch.int64, device=dev)
     dists = torch.empty((nq, kmax), dtype=torch.float32, device=dev)
     stats = torch.empty((nq, P.PEOS_NSTATS), dtype=torch.int32, device=dev)
-    ws = torch.empty(P.peos_search_ws_bytes(index, nq, efmax, 1), dtype=torch.uint8, device=dev)
     out = {}
-    for mode, label in ((P.PEOS_MODE_PEOS, "peos"), (P.PEOS_MODE_EXHAUSTIVE, "exhaustive")):
-        caps = autotune.tune_classes(index, qt, k, ef, pool=1, eps=w.eps, mode=mode, log=log)
-        gr = P.peos_graph_create(index, qt, kt, eft, kmax, 1, w.eps, mode, ids, dists, stats, ws,
-                                 k_all=kmax, ef_all=efmax)
-        for _ in range(args.warmup):
-            gr.launch()
-        torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        t0 = time.perf_counter()
-        for e0, e1 in evs:
-            e0.record()
-            gr.launch()
-            e1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gr.close()
-        for c in range(8):
-            P.peos_set_class_tuning(c, 0, 0)
-        ms = np.array([a.elapsed_time(b) for a, b in evs])
-        st = stats.cpu().numpy()
-        ii = ids.cpu().numpy()
-        rec = {}
-        for kc in (1, 10, 100):
-            sel = np.nonzero(k == kc)[0]
-            rec[f"k={kc}"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :kc], kc,
-                                                 w.metric).mean()), 4)
-        sel = np.nonzero(k >= 10)[0]
-        rec["recall@10 (k>=10)"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :10], 10,
-                                                       w.metric).mean()), 4)
-        code_bytes = 4 * ((w.L + 4) // 4)
-        alg = float((4.0 * w.R * st[:, 0] + (code_bytes + 16.0) * st[:, 3] + 4.0 * w.d * st[:, 9]
-                     + 4.0 * w.d + 4.0 * (w.L + 1) * w.m + 12.0 * k).sum())
-        out[label] = dict(qps=round(nq * args.steps / wall, 1), ms=round(float(ms.mean()), 4),
-                          p99_ms=round(float(np.percentile(ms, 99)), 4), recall=rec,
-                          ndist=round(float(st[:, 9].mean()), 1),
-                          gbs=round(alg / (ms.mean() / 1e3) / 1e9, 1), class_hash_caps=caps)
-        log(f"batched {label}: {out[label]}")
-    pe = out["peos"]
+    # stopping rules: the HNSW rule (pool = ef) and a queue of twice each
+    # query's ef (the bounded form of the printed Alg. 1)
+    for pool, rule in ((1, "hnsw"), (-2, "queue_2ef")):
+        ws = torch.empty(P.peos_search_ws_bytes(index, nq, efmax, pool), dtype=torch.uint8,
+                         device=dev)
+        for mode, label in ((P.PEOS_MODE_PEOS, "peos"), (P.PEOS_MODE_EXHAUSTIVE, "exhaustive")):
+            caps = autotune.tune_classes(index, qt, k, ef, pool=pool, eps=w.eps, mode=mode,
+                                         log=log)
+            gr = P.peos_graph_create(index, qt, kt, eft, kmax, pool, w.eps, mode, ids, dists,
+                                     stats, ws, k_all=kmax, ef_all=efmax)
+            for _ in range(args.warmup):
+                gr.launch()
+            torch.cuda.synchronize()
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(args.steps)]
+            t0 = time.perf_counter()
+            for e0, e1 in evs:
+                e0.record()
+                gr.launch()
+                e1.record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            gr.close()
+            for c in range(8):
+                P.peos_set_class_tuning(c, 0, 0)
+            ms = np.array([a.elapsed_time(b) for a, b in evs])
+            st = stats.cpu().numpy()
+            ii = ids.cpu().numpy()
+            rec = {}
+            for kc in (1, 10, 100):
+                sel = np.nonzero(k == kc)[0]
+                rec[f"k={kc}"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :kc], kc,
+                                                     w.metric).mean()), 4)
+            sel = np.nonzero(k >= 10)[0]
+            rec["recall@10 (k>=10)"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :10],
+                                                           10, w.metric).mean()), 4)
+            code_bytes = 4 * ((w.L + 4) // 4)
+            alg = float((4.0 * w.R * st[:, 0] + (code_bytes + 16.0) * st[:, 3]
+                         + 4.0 * w.d * st[:, 9] + 4.0 * w.d + 4.0 * (w.L + 1) * w.m
+                         + 12.0 * k).sum())
+            r = dict(qps=round(nq * args.steps / wall, 1), ms=round(float(ms.mean()), 4),
+                     p99_ms=round(float(np.percentile(ms, 99)), 4), recall=rec,
+                     ndist=round(float(st[:, 9].mean()), 1),
+                     expansions=round(float(st[:, 0].mean()), 1),
+                     gbs=round(float(alg / (ms.mean() / 1e3) / 1e9), 1),
+                     class_hash_caps={str(c): v for c, v in caps.items()})
+            out[f"{label}_{rule}"] = r
+            log(f"batched {label} {rule}: {r}")
+    pe, ex = out["peos_queue_2ef"], out["exhaustive_queue_2ef"]
     print(json.dumps({
         "metric": "QPS of one launch over a batch of uneven k/ef (batched persistent form)",
         "value": pe["qps"], "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -434,11 +446,80 @@ def batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L, "m": w.m,
                    "eps": w.eps, "k": "U{1,10,100}", "ef": "U{32,64,128,256}, max(ef,k)",
-                   "stop_rule": "hnsw (pool=ef)", "launch": "hip graph, ef classes"},
-        "peos": pe, "exhaustive": out["exhaustive"],
-        "speedup_vs_exhaustive": round(pe["qps"] / out["exhaustive"]["qps"], 3),
+                   "stop_rule": "queue of 2 ef per query", "launch": "hip graph, ef classes"},
+        "runs": out,
+        "speedup_vs_exhaustive": round(pe["qps"] / ex["qps"], 3),
         "roofline": {"bound": "hbm", "achieved": pe["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(pe["gbs"] / PEAK_HBM_GBS, 4), "traffic": None},
+    }), flush=True)
+
+
+def precision(args):
+    """The precision form (bfloat16 traversal copy, half scalars and tables,
+    single-precision re-rank) against the full-precision path on the same
+    graph: QPS at recall >= target for k = 10 and k = 100, recall loss at
+    equal ef, and the distance error of every returned result."""
+    import torch
+
+    import paper_2402_11354_amd as P
+    import workloads as W
+
+    name = args.workload if args.workload != "sift_like_1m_d128" else "gist_like_1m_d960"
+    w, x, q, g, entry, index, gt_d = _setup(name, args.n, args.nq, 100)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    A, B = W.directions_for(w)
+    lowp = P.peos_build_tables(index._keep[0], index._keep[1], entry, w.L, w.m, T(A), T(B),
+                               w.metric, flags=P.PEOS_FLAG_BF16_BASE | P.PEOS_FLAG_FP16)
+    qt = T(q)
+    nq = w.nq
+    xs = torch.from_numpy(x).to(dev).double()
+    qs = qt.double()
+    result = {}
+    for k, efs in ((10, (16, 24, 32, 48, 64, 96, 128, 192, 256)),
+                   (100, (100, 128, 160, 192, 256, 320, 384, 512))):
+        ws = torch.empty(P.peos_search_ws_bytes(index, nq, max(efs), max(efs)),
+                         dtype=torch.uint8, device=dev)
+        rows = {}
+        for label, ix in (("fp32", index), ("precision", lowp)):
+            pts = []
+            for ef in efs:
+                ids, dd, st = P.search(ix, qt, k, ef, eps=w.eps, pool=ef, ws=ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    P.search(ix, qt, k, ef, eps=w.eps, pool=ef, ws=ws)
+                torch.cuda.synchronize()
+                qps = nq * args.steps / (time.perf_counter() - t0)
+                ii = ids.cpu().numpy()
+                rec = float(_recall(x, q, ii, gt_d[:, :k], k, w.metric).mean())
+                if w.metric == W.L2:
+                    d64 = ((xs[ids] - qs[:, None, :]) ** 2).sum(-1)
+                else:
+                    d64 = 1.0 - (xs[ids] * qs[:, None, :]).sum(-1) / qs.norm(dim=1)[:, None]
+                err = ((dd.double() - d64).abs() / d64.clamp(min=1e-30)).max().item()
+                pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
+                                max_rel_dist_err=err))
+                log(f"precision k={k} {label} ef={ef}: recall={rec:.4f} qps={qps:.0f} "
+                    f"max rel err={err:.2e}")
+            ok = [p_ for p_ in pts if p_["recall"] >= args.target]
+            rows[label] = dict(points=pts, at_target=(max(ok, key=lambda p_: p_["qps"])
+                                                      if ok else None))
+        loss = [round(a_["recall"] - b_["recall"], 4)
+                for a_, b_ in zip(rows["fp32"]["points"], rows["precision"]["points"])]
+        rows["recall_loss_at_equal_ef"] = dict(zip([str(e) for e in efs], loss))
+        result[f"k={k}"] = rows
+    r10 = result["k=10"]
+    val = r10["precision"]["at_target"]
+    print(json.dumps({
+        "metric": "QPS at recall@10>=0.95, precision form vs fp32 path (same graph)",
+        "value": val["qps"] if val else None, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16/f16 storage, f32 arithmetic",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L,
+                   "m": w.m, "eps": w.eps, "stop_rule": "hnsw (pool=ef)"},
+        "results": result,
     }), flush=True)
 
 

@@ -53,6 +53,19 @@ extern "C" {
  * i.e. Alg. 1 with RoutingTest returning true. */
 #define PEOS_MODE_PEOS 0
 #define PEOS_MODE_EXHAUSTIVE 1
+/* index flags: the precision form (storage only; arithmetic stays single
+ * precision).
+ * PEOS_FLAG_BF16_BASE: index_mem also holds a bfloat16 copy of the base
+ *   (round to nearest even); the search's traversal distances read it, and
+ *   the result list (first ef entries) is re-ranked by single-precision
+ *   distances on the full base before the first k are returned.
+ * PEOS_FLAG_FP16: the per-edge scalars are stored as four IEEE halves
+ *   {g_e/|e|, 1/|e| (infinite for a zero-length edge), w_reg, sqrt(L) w_res}
+ *   and the projection tables as halves; the test of step (6) then takes
+ *   A_r = (g_e/|e| + (dist_v - delta)/2 * 1/|e|) / |q| (l2) or
+ *   (dist_v - delta)/|e| (angular), the same quantity as the full form's. */
+#define PEOS_FLAG_BF16_BASE 1
+#define PEOS_FLAG_FP16 2
 
 /* per-query status bits written to stats[.. + PEOS_STAT_STATUS] */
 #define PEOS_STATUS_ZERO_QUERY 1    /* |q| = 0 or not finite: outputs padded  */
@@ -86,7 +99,9 @@ typedef struct peos_graph peos_graph;
  * byte c encodes the index j* = c mod m of the extreme projection vector and
  * its sign (negative iff c >= m).  Scalars: edge j owns 4 floats at
  * scalars_offset + 16*j: g_e = (|u|^2 - |v|^2)/2 (zero for ANGULAR), |e|,
- * w_reg, sqrt(L)*w_res. */
+ * w_reg, sqrt(L)*w_res; with PEOS_FLAG_FP16, 4 halves at scalars_offset + 8*j
+ * (see PEOS_FLAG_FP16).  With PEOS_FLAG_BF16_BASE the bfloat16 copy of the
+ * base (n x d) starts at bf16_offset. */
 typedef struct {
     int64_t n;
     int32_t d, R, L, m, metric, flags, entry;
@@ -94,6 +109,8 @@ typedef struct {
     int64_t codes_offset;   /* bytes, within a record */
     int64_t scalars_offset; /* bytes, within a record */
     int64_t code_bytes;     /* bytes of codes per edge */
+    int64_t scalar_bytes;   /* bytes of scalars per edge (16, or 8 with halves) */
+    int64_t bf16_offset;    /* bytes, within index_mem; 0 without the copy */
 } peos_layout;
 
 /*
@@ -101,11 +118,11 @@ typedef struct {
  * Implements: storage of PEOS steps (1)-(3) results per edge (Sec. 4.3,
  * "Implementation of PEOs": codes and scalars are precomputed at build time).
  * n, d, R, L, m: base size, dimension, max out-degree, subspaces, projection
- * vectors per subspace.  flags: 0 (reserved for storage variants).
+ * vectors per subspace.  flags: 0, or PEOS_FLAG_* (the precision form).
  * Outputs (host pointers): index_bytes = bytes of index_mem;
  * build_ws_bytes = bytes of the build workspace.  Pure, no device work.
  * Errors: PEOS_EINVAL if n < 1, d < 1, R < 1, L < 1, d % L != 0, d/L % 4 != 0,
- * m < 16, m % 16 != 0, 2*m > 256, or a null output pointer.
+ * m < 16, m % 16 != 0, 2*m > 256, an unknown flag, or a null output pointer.
  */
 int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int32_t flags,
                      size_t* index_bytes, size_t* build_ws_bytes);
@@ -147,7 +164,9 @@ void peos_free(peos_index* index);
  * once per query (Alg. 2, "only once and used throughout the search").
  *   queries  nq x d float.
  *   tables   out, nq x (L+1) x m float: row 0 = q'.b_j, row i = q'_i . a^i_j
- *            with q' = q/|q| and q'_i its i-th block (not renormalized).
+ *            with q' = q/|q| and q'_i its i-th block (not renormalized);
+ *            IEEE halves (nq x (L+1) x m x 2 bytes) if the index has
+ *            PEOS_FLAG_FP16.
  *   qnorms   out, nq float: |q| (0 for a zero query, whose table is 0).
  * Runs the dense query-by-direction product on the matrix cores.
  * Errors: PEOS_EINVAL (null pointer with nq > 0, nq < 0), PEOS_EHIP.
@@ -175,8 +194,11 @@ int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int
  *            held as one list sorted by (distance, id)).  pool = 0: the queue
  *            is unbounded as printed in Alg. 1, up to the kernel's capacity
  *            (a query that reaches it gets PEOS_STATUS_POOL_FULL and from then
- *            on behaves as pool = that capacity); pool <= max(ef, k): the HNSW
- *            stopping rule (stop when R holds no unexpanded node).
+ *            on behaves as pool = that capacity); 0 < pool <= max(ef, k): the
+ *            HNSW stopping rule (stop when R holds no unexpanded node);
+ *            pool > max(ef, k): a bounded queue of pool entries; pool in
+ *            [-16, -1]: a bounded queue of |pool| x (that query's list size)
+ *            entries, at most 8192.
  *   eps      error bound epsilon of probabilistic routing (Def. 3.2), in
  *            (0, 0.5]; ignored by EXHAUSTIVE.
  *   mode     PEOS_MODE_*.

@@ -183,7 +183,8 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
            tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0):
     """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
     pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
-    pool <= ef = the HNSW stopping rule.  precision: 64 = distances in float64;
+    0 < pool <= ef = the HNSW stopping rule, pool < 0 = |pool| x each
+    query's ef.  precision: 64 = distances in float64;
     32 = the distance decisions taken on the canonical single-precision
     distances (the GPU kernel's precision; see dist32 in peos_oracle.c).
     lowp: precision form (implies precision 32): LP_FP16 = routing test on

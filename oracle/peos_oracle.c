@@ -647,7 +647,11 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
     const int kq = j->k ? j->k[qi] : 1;
     int efq = j->ef ? j->ef[qi] : kq;
     if (efq < kq) efq = kq;
-    const int cap = j->pool > efq ? j->pool : (j->pool > 0 ? efq : (int)(j->n < INT32_MAX ? j->n : INT32_MAX));
+    /* list capacity: pool > 0 fixed (at least ef), pool < 0 |pool| x ef,
+       pool = 0 unbounded */
+    const int cap = j->pool > efq ? j->pool
+                  : (j->pool > 0 ? efq
+                  : (j->pool < 0 ? -j->pool * efq : (int)(j->n < INT32_MAX ? j->n : INT32_MAX)));
     int64_t* cnt = j->counters + (size_t)qi * C_NCOUNT;
     int flags = 0;
     memset(cnt, 0, sizeof(int64_t) * C_NCOUNT);
@@ -713,8 +717,18 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             if (full && j->mode == OR_MODE_PEOS) {
                 edge_record(xv, xu, d, j->L, j->m, j->A, j->B, fw1, fw2, dw, &er);
                 double num;
-                if (j->metric == OR_L2) num = 0.5 * er.nu2 - r - vq;
-                else num = -r - vq;
+                if (j->lowp & LP_BF16_BASE) {
+                    /* the numerator from the search's own (bfloat16 traversal)
+                       distances: g_e + (dist_v - delta)/2 for l2, and
+                       (dist_v - delta) |q| for angular -- equal to the
+                       expression below on exact distances */
+                    if (j->metric == OR_L2) num = 0.5 * (er.nu2 - er.nv2) + 0.5 * (dv - delta);
+                    else num = (dv - delta) * qnorm;
+                } else if (j->metric == OR_L2) {
+                    num = 0.5 * er.nu2 - r - vq;
+                } else {
+                    num = -r - vq;
+                }
                 double A, H, T;
                 int kind;
                 if (j->lowp & LP_FP16)
@@ -802,7 +816,8 @@ static void* search_worker(void* arg)
     tp.eta = sqrt(2.0 * (double)j->L * log((double)j->m));
     tp.c_eps = oracle_norm_ppf(j->eps);
     uint8_t* visited = (uint8_t*)malloc((size_t)j->n);
-    int64_t lcap = j->pool > 0 ? (j->pool > efmax ? j->pool : efmax) : j->n;
+    int64_t lcap = j->pool > 0 ? (j->pool > efmax ? j->pool : efmax)
+                 : (j->pool < 0 ? (int64_t)-j->pool * efmax : j->n);
     rentry* R = (rentry*)malloc(sizeof(rentry) * (size_t)(lcap + j->R + 1));
     rentry* S = (rentry*)malloc(sizeof(rentry) * (size_t)(j->R + 1));
     double* table = (double*)malloc(sizeof(double) * (size_t)(j->L + 1) * j->m);
@@ -823,8 +838,9 @@ static void* search_worker(void* arg)
 
 /*
  * Public: batched search.  k and ef are per-query arrays (ef := max(ef, k)).
- * pool: capacity of the candidate list (<= 0: unbounded, Alg. 1 as printed;
- * values below ef act as ef, the HNSW stopping rule).
+ * pool: capacity of the candidate list (0: unbounded, Alg. 1 as printed;
+ * positive values below ef act as ef, the HNSW stopping rule; negative:
+ * |pool| times each query's ef).
  * fp32: 0 = distances in double precision; 1 = the search's distance
  * decisions (order, delta, insertion) taken on the single-precision
  * distances of dist32(), the precision of the GPU kernel.  out_dist then
@@ -835,8 +851,9 @@ static void* search_worker(void* arg)
  * zero/non-finite query.  lowp: precision-form flags (LP_*, implies fp32):
  * LP_FP16 takes the routing test on half-rounded scalars and tables
  * (routing_test_lowp); LP_BF16_BASE takes the traversal distances on the
- * bfloat16-rounded base and re-ranks the final result list with
- * full-precision single-precision distances before the first k are taken.
+ * bfloat16-rounded base (and the numerator of A_r from them) and re-ranks the
+ * final result list with full-precision single-precision distances before
+ * the first k are taken.
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,

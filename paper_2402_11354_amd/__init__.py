@@ -27,6 +27,8 @@ PEOS_METRIC_L2 = 0
 PEOS_METRIC_ANGULAR = 1
 PEOS_MODE_PEOS = 0
 PEOS_MODE_EXHAUSTIVE = 1
+PEOS_FLAG_BF16_BASE = 1
+PEOS_FLAG_FP16 = 2
 PEOS_NSTATS = 12
 STATS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0", "test_h",
          "test_zero", "passes", "ndist", "inserted", "status")
@@ -46,7 +48,8 @@ class peos_layout(ctypes.Structure):
                 ("L", ctypes.c_int32), ("m", ctypes.c_int32), ("metric", ctypes.c_int32),
                 ("flags", ctypes.c_int32), ("entry", ctypes.c_int32),
                 ("node_stride", ctypes.c_int64), ("codes_offset", ctypes.c_int64),
-                ("scalars_offset", ctypes.c_int64), ("code_bytes", ctypes.c_int64)]
+                ("scalars_offset", ctypes.c_int64), ("code_bytes", ctypes.c_int64),
+                ("scalar_bytes", ctypes.c_int64), ("bf16_offset", ctypes.c_int64)]
 
 
 class peos_serve_config(ctypes.Structure):

@@ -32,6 +32,7 @@ struct EdgeBuildArgs {
     int64_t n;
     int64_t node_stride, codes_off, scal_off;
     int d, R, L, m, metric;
+    int half_scalars;  // precision form: scalars as four halves per edge
 };
 
 // LDS: xv[d] | e[4][d] | s[4][L] | row[R]
@@ -180,7 +181,9 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 for (int pz = L + 1; pz < cbytes; ++pz) codes[j * cbytes + pz] = 0;
             }
         }
-        // scalars: g_e, |e|, w_reg, sqrt(L) w_res
+        // scalars: g_e, |e|, w_reg, sqrt(L) w_res; in the precision form
+        // the halves of g_e/|e|, 1/|e| (infinite for a zero edge), w_reg,
+        // sqrt(L) w_res
         if (s == 0 && j < R) {
             float ge = 0.f, ne = 0.f, wreg = 0.f, swres = 0.f;
             if (u >= 0) {
@@ -194,9 +197,31 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 }
                 if (a.metric == 0) ge = 0.5f * (nu2 - nv2);
             }
-            *reinterpret_cast<float4*>(scal + 4 * j) = make_float4(ge, ne, wreg, swres);
+            if (a.half_scalars) {
+                const float gp = ne > 0.f ? ge / ne : 0.f;
+                const float ie = ne > 0.f ? 1.f / ne : INFINITY;
+                _Float16* hs = reinterpret_cast<_Float16*>(rv + a.scal_off) + 4 * j;
+                hs[0] = (_Float16)(u >= 0 ? gp : 0.f);
+                hs[1] = (_Float16)(u >= 0 ? ie : 0.f);
+                hs[2] = (_Float16)wreg;
+                hs[3] = (_Float16)swres;
+            } else {
+                *reinterpret_cast<float4*>(scal + 4 * j) = make_float4(ge, ne, wreg, swres);
+            }
         }
         __syncthreads();
+    }
+}
+
+// bfloat16 copy of the base (round to nearest even), the traversal copy of
+// the precision form
+__global__ void k_to_bf16(const float* x, uint16_t* y, int64_t count)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+        uint32_t u = __float_as_uint(x[i]);
+        if ((u & 0x7f800000u) != 0x7f800000u) u += 0x7fffu + ((u >> 16) & 1u);
+        y[i] = (uint16_t)(u >> 16);
     }
 }
 

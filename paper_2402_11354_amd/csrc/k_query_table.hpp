@@ -9,7 +9,8 @@
 // One wave computes 16 queries x 16 directions with v_mfma_f32_16x16x4f32
 // (fp32 in, fp32 accumulate): per K step of 4, lane l feeds A[row = l%16][k =
 // l/16] (queries) and B[k = l/16][col = l%16] (directions), and receives
-// D[row = 4*(l/16) + r][col = l%16], r = 0..3.
+// D[row = 4*(l/16) + r][col = l%16], r = 0..3.  The precision form stores
+// the table as halves.
 #pragma once
 
 #include "peos_device.hpp"
@@ -22,10 +23,11 @@ struct QueryTableArgs {
     const float* queries;  // nq x d
     const float* dirs_a;   // L x m x dp
     const float* dirs_b;   // m x d
-    float* tables;         // nq x (L+1) x m
+    float* tables;         // nq x (L+1) x m floats, or halves when half_out
     float* qnorms;         // nq
     int64_t nq;
     int d, L, m;
+    int half_out;          // store the table as IEEE halves (round to nearest even)
 };
 
 __global__ __launch_bounds__(64) void k_query_table(QueryTableArgs a)
@@ -75,8 +77,12 @@ __global__ __launch_bounds__(64) void k_query_table(QueryTableArgs a)
             for (int r = 0; r < 4; ++r) {
                 const int orow = 4 * (lane >> 4) + r;
                 const int64_t qq = q0 + orow;
-                if (qq < a.nq)
-                    a.tables[(qq * (L + 1) + i) * m + jdir] = acc[r] * inv_norm[orow];
+                if (qq < a.nq) {
+                    const float t = acc[r] * inv_norm[orow];
+                    const int64_t o = (qq * (L + 1) + i) * m + jdir;
+                    if (a.half_out) reinterpret_cast<_Float16*>(a.tables)[o] = (_Float16)t;
+                    else a.tables[o] = t;
+                }
             }
         }
     }

@@ -25,8 +25,14 @@
 
 namespace peos {
 
+// precision-form flags (the index flags): bfloat16 traversal copy of the
+// base; halves for the edge scalars and the projection tables
+constexpr int kFlagBf16Base = 1;
+constexpr int kFlagFp16 = 2;
+
 struct SearchArgs {
     const float* base;
+    const uint16_t* base16;  // bfloat16 copy of the base (kFlagBf16Base)
     const int32_t* graph;
     const uint8_t* rec;
     int64_t node_stride, codes_off, scal_off;
@@ -97,12 +103,31 @@ __device__ __forceinline__ bool bitmap_test(const uint32_t* bm, uint32_t u)
 // tree levels that pair segments of different lanes are xor shuffles (an add
 // is commutative, so both partners get the same bits), the remaining levels
 // are local.  Angular distance = fma(-sum, 1/|q|, 1).
-template <int G, int PER, int K>
-__device__ __forceinline__ void gather_distances(const float* base, int d, const uint32_t* Su, int ns,
+// one chunk (four coordinates) of a stored vector, as floats
+template <bool BF>
+struct Chunk;
+template <>
+struct Chunk<false> {
+    typedef float4 raw;
+    static __device__ __forceinline__ float4 get(raw v) { return v; }
+};
+template <>
+struct Chunk<true> {
+    typedef uint2 raw;  // four bfloat16
+    static __device__ __forceinline__ float4 get(raw v)
+    {
+        return make_float4(__uint_as_float(v.x << 16), __uint_as_float(v.x & 0xffff0000u),
+                           __uint_as_float(v.y << 16), __uint_as_float(v.y & 0xffff0000u));
+    }
+};
+
+template <int G, int PER, int K, bool BF>
+__device__ __forceinline__ void gather_distances(const void* base, int d, const uint32_t* Su, int ns,
                                                  const float* qv, int metric, float inv_qn,
                                                  float* Sdist)
 {
 #pragma clang fp contract(off)
+    typedef typename Chunk<BF>::raw raw;
     constexpr int NP = 16 / G;        // segments per lane
     constexpr int SPR = kWave / G;    // vectors per pass of the wave, per slot
     static_assert(K % NP == 0, "a load step must cover whole segment rounds");
@@ -117,18 +142,18 @@ __device__ __forceinline__ void gather_distances(const float* base, int d, const
     // any of them is used.
     for (int b0 = 0; b0 < ns; b0 += SPR * PER) {
         float part[PER][NP];
-        const float4* x4[PER];
+        const raw* x4[PER];
         bool act[PER];
 #pragma unroll
         for (int pp = 0; pp < PER; ++pp) {
             const int idx = b0 + t + pp * SPR;
             act[pp] = idx < ns;
-            x4[pp] = reinterpret_cast<const float4*>(base + (int64_t)(act[pp] ? Su[idx] : 0u) * d);
+            x4[pp] = reinterpret_cast<const raw*>(base) + (int64_t)(act[pp] ? Su[idx] : 0u) * (d >> 2);
 #pragma unroll
             for (int j = 0; j < NP; ++j) part[pp][j] = 0.f;
         }
         for (int k0 = 0; s + G * k0 < nch; k0 += K) {
-            float4 xv[PER][K];
+            raw xv[PER][K];
 #pragma unroll
             for (int pp = 0; pp < PER; ++pp)
 #pragma unroll
@@ -142,7 +167,7 @@ __device__ __forceinline__ void gather_distances(const float* base, int d, const
                 for (int kk = 0; kk < K; ++kk) {
                     const int c = s + G * (k0 + kk);
                     if (act[pp] && c < nch) {
-                        const float4 x = xv[pp][kk];
+                        const float4 x = Chunk<BF>::get(xv[pp][kk]);
                         const float4 q = q4[c];
                         float acc = part[pp][kk % NP];
                         if (metric == 0) {
@@ -180,24 +205,28 @@ __device__ __forceinline__ void gather_distances(const float* base, int d, const
     }
 }
 
-__device__ __forceinline__ void distances(const float* base, int d, const uint32_t* Su, int ns,
+template <bool BF>
+__device__ __forceinline__ void distances(const void* base, int d, const uint32_t* Su, int ns,
                                           const float* qv, int metric, float inv_qn, float* Sdist)
 {
-    // 4..16 lanes per vector; each lane keeps at most 8 float4 loads in
-    // flight (one round trip for up to 16 vectors of 128 floats)
-    if (ns <= 4) gather_distances<16, 1, 8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 8) gather_distances<8, 1, 8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 16) gather_distances<4, 1, 8>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else gather_distances<4, 2, 4>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    // 4..16 lanes per vector; each lane keeps at most 8 chunk loads in
+    // flight (one round trip for up to 16 vectors of 128 coordinates)
+    if (ns <= 4) gather_distances<16, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 8) gather_distances<8, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 16) gather_distances<4, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else gather_distances<4, 2, 4, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
 }
 
 #ifndef PEOS_SEARCH_WAVES_PER_EU
 #define PEOS_SEARCH_WAVES_PER_EU 4
 #endif
 
-template <int MAXL>
+template <int MAXL, int FLAGS>
 __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchArgs a)
 {
+    constexpr bool BF = (FLAGS & kFlagBf16Base) != 0;
+    constexpr bool H16 = (FLAGS & kFlagFp16) != 0;
+    const void* tbase = BF ? (const void*)a.base16 : (const void*)a.base;
     extern __shared__ __align__(16) unsigned char sm[];
     const int lane = lane_id();
     const int d = a.d, R = a.R, L = a.L, m = a.m;
@@ -230,7 +259,9 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
         int efq = a.efq ? a.efq[qi] : a.ef_all;
         efq = efq > a.ef_all ? a.ef_all : efq;
         efq = efq > kq ? efq : kq;
-        int cap = a.pool > 0 ? (a.pool > efq ? a.pool : efq) : a.listcap;
+        // list capacity: pool > 0 a fixed capacity (at least ef), pool < 0
+        // |pool| times this query's ef, 0 the kernel's (the unbounded queue)
+        int cap = a.pool > 0 ? (a.pool > efq ? a.pool : efq) : (a.pool < 0 ? -a.pool * efq : a.listcap);
         cap = cap < a.listcap ? cap : a.listcap;
         const float qn = a.qnorms[qi];
         int status = 0;
@@ -242,12 +273,17 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             const float inv_qn = 1.f / qn;
             const float* qg = a.queries + qi * d;
             for (int t = lane; t < d; t += kWave) qv[t] = qg[t];
-            const float* tg = a.tables + qi * (int64_t)(L + 1) * m;
-            for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = tg[t];
+            if (H16) {
+                const _Float16* tg = reinterpret_cast<const _Float16*>(a.tables) + qi * (int64_t)(L + 1) * m;
+                for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = (float)tg[t];
+            } else {
+                const float* tg = a.tables + qi * (int64_t)(L + 1) * m;
+                for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = tg[t];
+            }
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
             if (lane == 0) Su[0] = (uint32_t)a.entry;
             wave_sync();
-            distances(a.base, d, Su, 1, qv, a.metric, inv_qn, Sdist);
+            distances<BF>(tbase, d, Su, 1, qv, a.metric, inv_qn, Sdist);
             if (lane == 0) {
                 hash_insert(hash, (uint32_t)hcap, (uint32_t)a.entry);
             }
@@ -297,7 +333,16 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                     u = a.graph[(int64_t)vid * R + lane];
                     if (testing) {
                         const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
-                        sc4 = reinterpret_cast<const float4*>(rv + a.scal_off)[lane];
+                        if (H16) {
+                            // halves: g_e/|e|, 1/|e|, w_reg, sqrt(L) w_res
+                            const uint2 h = reinterpret_cast<const uint2*>(rv + a.scal_off)[lane];
+                            sc4 = make_float4((float)__builtin_bit_cast(_Float16, (uint16_t)(h.x & 0xffffu)),
+                                              (float)__builtin_bit_cast(_Float16, (uint16_t)(h.x >> 16)),
+                                              (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y & 0xffffu)),
+                                              (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y >> 16)));
+                        } else {
+                            sc4 = reinterpret_cast<const float4*>(rv + a.scal_off)[lane];
+                        }
                         const uint32_t* cb =
                             reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
 #pragma unroll
@@ -318,12 +363,16 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 if (testing) {
                     int kind = -1;
                     if (cand) {
-                        const float num = (a.metric == 0) ? sg + 0.5f * (dv - delta) : (dv - delta);
-                        if (se == 0.f) {
+                        // full precision: sg = g_e, se = |e|; halves: sg =
+                        // g_e/|e|, se = 1/|e| (infinite for a zero edge)
+                        const float diff = (a.metric == 0) ? 0.5f * (dv - delta) : (dv - delta);
+                        const float num = H16 ? diff : ((a.metric == 0) ? sg + diff : diff);
+                        if (H16 ? !(se < INFINITY) : se == 0.f) {
                             kind = 0;
                             pass = num < 0.f;
                         } else {
-                            const float A = num * __builtin_amdgcn_rcpf((a.metric == 0 ? qn : 1.f) * se);
+                            const float A = H16 ? ((a.metric == 0) ? fmaf(diff, se, sg) * inv_qn : diff * se)
+                                                : num * __builtin_amdgcn_rcpf((a.metric == 0 ? qn : 1.f) * se);
                             if (A >= 1.f) {
                                 kind = 1;
                                 pass = false;
@@ -382,7 +431,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 nvis += ns;
                 wave_sync();
-                distances(a.base, d, Su, ns, qv, a.metric, inv_qn, Sdist);
+                distances<BF>(tbase, d, Su, ns, qv, a.metric, inv_qn, Sdist);
                 st_ndist += ns;
                 wave_sync();
 
@@ -474,7 +523,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 } else {
                     w = total;
                 }
-                if (w > cap && a.pool <= 0) status |= kStatusPoolFull;
+                if (w > cap && a.pool == 0) status |= kStatusPoolFull;
                 size = w < cap ? w : cap;
                 minpos = wave_uniform(minpos);
                 lb = lb < efq ? lb : efq;
@@ -485,11 +534,42 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             status |= kStatusZeroQuery;
         }
 
-        // results: first k entries of the list, padded with (-1, +inf)
-        for (int t = lane; t < a.kstride; t += kWave) {
-            const bool ok = t < kq && t < size;
-            a.ids[qi * a.kstride + t] = ok ? (int64_t)(Li[t] & kIdMask) : (int64_t)-1;
-            a.dists[qi * a.kstride + t] = ok ? Ld[t] : INFINITY;
+        if (BF && size > 0) {
+            // precision form: the result list (first ef entries) re-ranked by
+            // full-precision distances; entry t goes to its rank among them
+            const int nr = size < efq ? size : efq;
+            const float inv_qn = 1.f / qn;
+            for (int c0 = 0; c0 < nr; c0 += kWave) {
+                const int cnt = nr - c0 < kWave ? nr - c0 : kWave;
+                if (lane < cnt) Su[lane] = Li[c0 + lane] & kIdMask;
+                wave_sync();
+                distances<false>(a.base, d, Su, cnt, qv, a.metric, inv_qn, Sdist);
+                wave_sync();
+                if (lane < cnt) Ld[c0 + lane] = Sdist[lane];
+                wave_sync();
+            }
+            for (int t = lane; t < nr; t += kWave) {
+                const uint32_t id = Li[t] & kIdMask;
+                const uint64_t key = sort_key(Ld[t], id);
+                int rank = 0;
+                for (int o = 0; o < nr; ++o) rank += sort_key(Ld[o], Li[o] & kIdMask) < key;
+                if (rank < kq) {
+                    a.ids[qi * a.kstride + rank] = (int64_t)id;
+                    a.dists[qi * a.kstride + rank] = Ld[t];
+                }
+            }
+            const int kout = kq < nr ? kq : nr;
+            for (int t = kout + lane; t < a.kstride; t += kWave) {
+                a.ids[qi * a.kstride + t] = -1;
+                a.dists[qi * a.kstride + t] = INFINITY;
+            }
+        } else {
+            // results: first k entries of the list, padded with (-1, +inf)
+            for (int t = lane; t < a.kstride; t += kWave) {
+                const bool ok = t < kq && t < size;
+                a.ids[qi * a.kstride + t] = ok ? (int64_t)(Li[t] & kIdMask) : (int64_t)-1;
+                a.dists[qi * a.kstride + t] = ok ? Ld[t] : INFINITY;
+            }
         }
         if (a.stats && lane == 0) {
             int32_t* o = a.stats + qi * 12;

@@ -21,13 +21,14 @@ struct peos_graph {
 
 struct peos_index {
     const float* base;
+    const uint16_t* base16;  // bfloat16 traversal copy inside index_mem, or null
     const int32_t* graph;
     const float* dirs_a;
     const float* dirs_b;
     uint8_t* rec;
     int64_t n;
     int32_t d, R, L, m, metric, flags, entry;
-    int64_t node_stride, codes_off, scal_off;
+    int64_t node_stride, codes_off, scal_off, bf16_off;
     int device;
 };
 
@@ -61,14 +62,17 @@ struct Layout {
     int64_t stride, codes_off, scal_off;
 };
 
+constexpr int kFlagsAll = PEOS_FLAG_BF16_BASE | PEOS_FLAG_FP16;
+
 // record of a node: codes [R][round_up(L+1, 4)] bytes | pad to 16 | scalars
-// [R][4] floats | pad to 128
-Layout layout_of(int R, int L)
+// [R][4] floats (halves with PEOS_FLAG_FP16) | pad to 128.  With
+// PEOS_FLAG_BF16_BASE the n x d bfloat16 copy follows the records.
+Layout layout_of(int R, int L, int flags)
 {
     Layout l;
     l.codes_off = 0;
     l.scal_off = round_up((int64_t)R * round_up(L + 1, 4), 16);
-    l.stride = round_up(l.scal_off + 16LL * R, 128);
+    l.stride = round_up(l.scal_off + ((flags & PEOS_FLAG_FP16) ? 8LL : 16LL) * R, 128);
     return l;
 }
 
@@ -147,9 +151,15 @@ int ensure_kernel_attrs(int dev)
     std::lock_guard<std::mutex> g(mu);
     if (dev < 0 || dev >= 64) return fail(PEOS_EDEVICE, "device index %d", dev);
     if (!done[dev]) {
-        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<8>, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
-        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<16>, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
-        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_search<32>, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+        const void* fns[] = {
+            (const void*)peos::k_search<8, 0>,  (const void*)peos::k_search<8, 1>,
+            (const void*)peos::k_search<8, 2>,  (const void*)peos::k_search<8, 3>,
+            (const void*)peos::k_search<16, 0>, (const void*)peos::k_search<16, 1>,
+            (const void*)peos::k_search<16, 2>, (const void*)peos::k_search<16, 3>,
+            (const void*)peos::k_search<32, 0>, (const void*)peos::k_search<32, 1>,
+            (const void*)peos::k_search<32, 2>, (const void*)peos::k_search<32, 3>};
+        for (const void* f : fns)
+            HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
         done[dev] = true;
     }
     return PEOS_OK;
@@ -175,11 +185,11 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
             if (g_class_tune[cls].slots > 0) t.slots = g_class_tune[cls].slots;
         }
     }
-    const int lmin = pool > efmax ? pool : efmax;
+    const int lmin = pool < 0 ? -pool * efmax : (pool > efmax ? pool : efmax);
     // unbounded queue: room for 16 ef entries (the list of the printed Alg. 1
     // stays well below that in practice), at most 2048
-    int lc = pool > 0 ? lmin : (16 * efmax > 256 ? 16 * efmax : 256);
-    if (pool <= 0 && lc > 2048) lc = lmin > 2048 ? lmin : 2048;
+    int lc = pool != 0 ? lmin : (16 * efmax > 256 ? 16 * efmax : 256);
+    if (pool == 0 && lc > 2048) lc = lmin > 2048 ? lmin : 2048;
     if (t.listcap > 0) lc = t.listcap > lmin ? t.listcap : lmin;
     lc = (int)round_up(lc, 64);
     if (lc > kMaxEf * 2) lc = kMaxEf * 2;
@@ -288,11 +298,13 @@ int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int3
                      size_t* index_bytes, size_t* build_ws_bytes)
 {
     if (!index_bytes || !build_ws_bytes) return fail(PEOS_EINVAL, "null output pointer");
-    if (flags != 0) return fail(PEOS_EINVAL, "flags=%d not supported", flags);
+    if (flags & ~kFlagsAll) return fail(PEOS_EINVAL, "flags=%d not supported", flags);
     int rc = check_shape(n, d, R, L, m);
     if (rc) return rc;
-    Layout l = layout_of(R, L);
-    *index_bytes = (size_t)(n * l.stride);
+    Layout l = layout_of(R, L, flags);
+    int64_t bytes = n * l.stride;
+    if (flags & PEOS_FLAG_BF16_BASE) bytes = round_up(bytes, 256) + n * (int64_t)d * 2;
+    *index_bytes = (size_t)bytes;
     *build_ws_bytes = 256;
     return PEOS_OK;
 }
@@ -319,7 +331,7 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
     rc = check_device(&dev);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
-    Layout l = layout_of(R, L);
+    Layout l = layout_of(R, L, flags);
     int32_t* err = (int32_t*)ws;
     hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, (uint32_t*)err, 1);
     peos::EdgeBuildArgs a;
@@ -338,9 +350,16 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
     a.L = L;
     a.m = m;
     a.metric = metric;
+    a.half_scalars = (flags & PEOS_FLAG_FP16) ? 1 : 0;
     size_t lds = sizeof(float) * (size_t)(5 * d + 4 * L) + sizeof(int32_t) * (size_t)R;
     hipLaunchKernelGGL(peos::k_edge_build, dim3((unsigned)n), dim3(64), lds, s, a);
     HIP_TRY(hipGetLastError());
+    const int64_t bf16_off = (flags & PEOS_FLAG_BF16_BASE) ? round_up(n * l.stride, 256) : 0;
+    if (flags & PEOS_FLAG_BF16_BASE) {
+        hipLaunchKernelGGL(peos::k_to_bf16, dim3(4096), dim3(256), 0, s, base,
+                           (uint16_t*)((uint8_t*)index_mem + bf16_off), n * (int64_t)d);
+        HIP_TRY(hipGetLastError());
+    }
     int32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err, sizeof herr, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -348,6 +367,8 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
     peos_index* ix = new (std::nothrow) peos_index;
     if (!ix) return fail(PEOS_EINVAL, "out of host memory");
     ix->base = base;
+    ix->base16 = (flags & PEOS_FLAG_BF16_BASE) ? (const uint16_t*)((uint8_t*)index_mem + bf16_off) : nullptr;
+    ix->bf16_off = bf16_off;
     ix->graph = graph;
     ix->dirs_a = dirs_a;
     ix->dirs_b = dirs_b;
@@ -383,6 +404,8 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
     out->codes_offset = ix->codes_off;
     out->scalars_offset = ix->scal_off;
     out->code_bytes = round_up(ix->L + 1, 4);
+    out->scalar_bytes = (ix->flags & PEOS_FLAG_FP16) ? 8 : 16;
+    out->bf16_offset = ix->bf16_off;
     return PEOS_OK;
 }
 
@@ -405,6 +428,7 @@ int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, fl
     a.d = ix->d;
     a.L = ix->L;
     a.m = ix->m;
+    a.half_out = (ix->flags & PEOS_FLAG_FP16) ? 1 : 0;
     const int64_t blocks = (nq + 15) / 16;
     hipLaunchKernelGGL(peos::k_query_table, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, a);
     HIP_TRY(hipGetLastError());
@@ -415,7 +439,7 @@ int peos_search_ws_bytes(const peos_index* ix, int64_t nq, int32_t efmax, int32_
                          size_t* ws_bytes)
 {
     if (!ix || !ws_bytes) return fail(PEOS_EINVAL, "null pointer");
-    if (nq < 0 || efmax < 1 || efmax > kMaxEf || pool < 0 || pool > 2 * kMaxEf)
+    if (nq < 0 || efmax < 1 || efmax > kMaxEf || pool < -16 || pool > 2 * kMaxEf)
         return fail(PEOS_EINVAL, "nq=%lld efmax=%d pool=%d", (long long)nq, efmax, pool);
     WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
     *ws_bytes = (size_t)w.total;
@@ -439,9 +463,18 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     a.hcap = plan.hcap;
     a.visit_limit = plan.visit_limit;
     const dim3 grid((unsigned)plan.slots);
-    if (ix->L <= 8) hipLaunchKernelGGL(peos::k_search<8>, grid, dim3(64), (size_t)plan.lds, s, a);
-    else if (ix->L <= 16) hipLaunchKernelGGL(peos::k_search<16>, grid, dim3(64), (size_t)plan.lds, s, a);
-    else hipLaunchKernelGGL(peos::k_search<32>, grid, dim3(64), (size_t)plan.lds, s, a);
+    const size_t lds = (size_t)plan.lds;
+#define PEOS_LAUNCH(ML)                                                                          \
+    switch (ix->flags & kFlagsAll) {                                                             \
+    case 0: hipLaunchKernelGGL((peos::k_search<ML, 0>), grid, dim3(64), lds, s, a); break;        \
+    case 1: hipLaunchKernelGGL((peos::k_search<ML, 1>), grid, dim3(64), lds, s, a); break;        \
+    case 2: hipLaunchKernelGGL((peos::k_search<ML, 2>), grid, dim3(64), lds, s, a); break;        \
+    default: hipLaunchKernelGGL((peos::k_search<ML, 3>), grid, dim3(64), lds, s, a); break;       \
+    }
+    if (ix->L <= 8) { PEOS_LAUNCH(8) }
+    else if (ix->L <= 16) { PEOS_LAUNCH(16) }
+    else { PEOS_LAUNCH(32) }
+#undef PEOS_LAUNCH
     HIP_TRY(hipGetLastError());
     return PEOS_OK;
 }
@@ -459,6 +492,7 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     if (rc) return rc;
     peos::SearchArgs a;
     a.base = ix->base;
+    a.base16 = ix->base16;
     a.graph = ix->graph;
     a.rec = ix->rec;
     a.node_stride = ix->node_stride;
@@ -525,7 +559,8 @@ static int check_search_args(const peos_index* ix, const float* queries, int64_t
     if (nq < 0 || nq > 0x7fffffffLL) return fail(PEOS_EINVAL, "nq=%lld", (long long)nq);
     if (k_all < 1 || kstride < k_all) return fail(PEOS_EINVAL, "k_all=%d kstride=%d", k_all, kstride);
     if (ef_all < 1 || ef_all > kMaxEf || k_all > kMaxEf) return fail(PEOS_EINVAL, "ef_all=%d (max %d)", ef_all, kMaxEf);
-    if (pool < 0 || pool > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d", pool);
+    if (pool < -16 || pool > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d", pool);
+    if (pool < 0 && -pool * ef_all > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d x ef=%d above %d", pool, ef_all, 2 * kMaxEf);
     if (mode != PEOS_MODE_PEOS && mode != PEOS_MODE_EXHAUSTIVE) return fail(PEOS_EINVAL, "mode=%d", mode);
     if (mode == PEOS_MODE_PEOS && !(eps > 0.f && eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g not in (0, 0.5]", (double)eps);
     if (nq > 0 && (!queries || !ids || !dists || !ws)) return fail(PEOS_EINVAL, "null device pointer");
@@ -587,22 +622,22 @@ int peos_graph_create(const peos_index* ix, const float* queries, int64_t nq, co
                          stats, ws, ws_bytes, cs);
         e = hipStreamEndCapture(cs, &g);
     }
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (rc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return rc;
     }
     if (e != hipSuccess) return fail(PEOS_EHIP, "stream capture: %s", hipGetErrorString(e));
     hipGraphExec_t x = nullptr;
     e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);
         return fail(PEOS_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     peos_graph* pg = new (std::nothrow) peos_graph;
     if (!pg) {
-        hipGraphExecDestroy(x);
-        hipGraphDestroy(g);
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
         return fail(PEOS_EINVAL, "out of host memory");
     }
     pg->graph = g;
@@ -622,8 +657,8 @@ int peos_graph_launch(peos_graph* g, void* stream)
 void peos_graph_destroy(peos_graph* g)
 {
     if (!g) return;
-    hipGraphExecDestroy(g->exec);
-    hipGraphDestroy(g->graph);
+    (void)hipGraphExecDestroy(g->exec);
+    (void)hipGraphDestroy(g->graph);
     delete g;
 }
 

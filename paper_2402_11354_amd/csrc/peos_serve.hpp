@@ -72,11 +72,11 @@ int64_t align256(int64_t x) { return (x + 255) / 256 * 256; }
 
 void release_slot(ServeSlot& s)
 {
-    if (s.stream) hipStreamSynchronize(s.stream);
-    if (s.done) hipEventDestroy(s.done);
-    if (s.stream) hipStreamDestroy(s.stream);
-    if (s.dmem) hipFree(s.dmem);
-    if (s.hmem) hipHostFree(s.hmem);
+    if (s.stream) (void)hipStreamSynchronize(s.stream);
+    if (s.done) (void)hipEventDestroy(s.done);
+    if (s.stream) (void)hipStreamDestroy(s.stream);
+    if (s.dmem) (void)hipFree(s.dmem);
+    if (s.hmem) (void)hipHostFree(s.hmem);
     s = ServeSlot();
 }
 
@@ -201,7 +201,8 @@ int peos_serve_open(const peos_index* ix, const peos_serve_config* cfg, peos_ser
     if (c.max_ef < 1 || c.max_ef > kMaxEf) return fail(PEOS_EINVAL, "max_ef=%d", c.max_ef);
     if (c.max_inflight < 1 || c.max_inflight > 16) return fail(PEOS_EINVAL, "max_inflight=%d", c.max_inflight);
     if (c.max_pending < c.max_batch) return fail(PEOS_EINVAL, "max_pending=%d < max_batch", c.max_pending);
-    if (c.pool < 0 || c.pool > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d", c.pool);
+    if (c.pool < -16 || c.pool > 2 * kMaxEf || (c.pool < 0 && -c.pool * c.max_ef > 2 * kMaxEf))
+        return fail(PEOS_EINVAL, "pool=%d", c.pool);
     if (c.mode != PEOS_MODE_PEOS && c.mode != PEOS_MODE_EXHAUSTIVE) return fail(PEOS_EINVAL, "mode=%d", c.mode);
     if (c.mode == PEOS_MODE_PEOS && !(c.eps > 0.f && c.eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g", (double)c.eps);
     if (c.launch_waves < 0 || c.launch_waves > kMaxSlots) return fail(PEOS_EINVAL, "launch_waves=%d", c.launch_waves);

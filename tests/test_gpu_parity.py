@@ -386,3 +386,19 @@ def test_graph_capture_replays(tiny, per_query):
         assert torch.equal(ids, eager2[0]) and torch.equal(dists, eager2[1])
     finally:
         g.close()
+
+
+def test_per_query_bounded_queue_matches_oracle(angular):
+    """pool = -2: each query keeps a queue of twice its own ef (the bounded
+    form of the printed Alg. 1), in one launch of uneven ef."""
+    case, w = angular, angular.w
+    k, ef = W.query_params(w, len(case.q), seed=3)
+    ids, d, st = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=-2, kstride=100)
+    torch.cuda.synchronize()
+    ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    ref = O.search(case.x, case.g, case.entry, case.q, k, ef, w.L, w.m, case.A, case.B, w.metric,
+                   w.eps, kstride=100, pool=-2, precision=32)
+    res = compare(ids, d, st, ref, 100)
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+    assert np.all(st[:, 11] & P.PEOS_STATUS_POOL_FULL == 0)

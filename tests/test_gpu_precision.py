@@ -1,0 +1,210 @@
+"""The precision form (index flags PEOS_FLAG_BF16_BASE, PEOS_FLAG_FP16) against
+the oracle's precision form.
+
+What is exact: the bfloat16 copy (round to nearest even of every float), the
+edge codes (unchanged), the bfloat16 traversal distances and the final
+re-rank (single precision in the canonical order on both sides).  What is
+not: a half-rounded scalar or table entry can round the other way when the
+GPU's single-precision value and the oracle's double-precision value straddle
+a rounding boundary, so those values are checked to one half-ulp and the
+search with halves is checked by the fraction of identical queries, the
+per-result distance error and the recall loss.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from parity import compare
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2402_11354_amd")
+
+pytestmark = pytest.mark.gpu
+
+
+def T(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(torch.device("cuda:0"))
+
+
+class Case:
+    def __init__(self, w):
+        self.w = w
+        self.x = W.make_base(w)
+        self.q = W.make_queries(w)
+        self.g, self.entry = W.build_graph(self.x, w.R, w.cand)
+        self.A, self.B = W.directions_for(w)
+        self.xt, self.gt, self.At, self.Bt, self.qt = (T(a) for a in (self.x, self.g, self.A,
+                                                                        self.B, self.q))
+        self.idx = {}
+
+    def index(self, flags):
+        if flags not in self.idx:
+            w = self.w
+            self.idx[flags] = P.peos_build_tables(self.xt, self.gt, self.entry, w.L, w.m, self.At,
+                                                  self.Bt, w.metric, flags=flags)
+        return self.idx[flags]
+
+    def oracle(self, lowp, k=None, ef=None, pool=0, mode=0):
+        w = self.w
+        return O.search(self.x, self.g, self.entry, self.q, k or w.k, ef or w.ef, w.L, w.m, self.A,
+                        self.B, w.metric, w.eps, mode=mode, pool=pool, lowp=lowp)
+
+    def run(self, flags, k=None, ef=None, pool=0, mode=0):
+        w = self.w
+        ids, d, st = P.search(self.index(flags), self.qt, k or w.k, ef or w.ef, eps=w.eps,
+                              mode=mode, pool=pool)
+        torch.cuda.synchronize()
+        return ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def gauss():
+    print("[gpu] precision: tiny gaussian workload", flush=True)
+    return Case(W.TINY.with_sizes(n=3000, nq=120))
+
+
+@pytest.fixture(scope="module")
+def ints():
+    print("[gpu] precision: small integer-valued workload", flush=True)
+    return Case(W.SIFT_LIKE.with_sizes(n=4000, nq=100))
+
+
+@pytest.fixture(scope="module")
+def ang():
+    print("[gpu] precision: angular workload", flush=True)
+    return Case(W.Workload("prec_sphere_5k_d64", 5000, 100, 64, 16, 32, 4, 16, W.ANGULAR,
+                           "sphere500", 0.1, 10, 32, 1007))
+
+
+def half_adjacent(got, ref):
+    """got equals ref or is the adjacent half (a straddled rounding boundary)."""
+    g = got.astype(np.float16)
+    r = ref.astype(np.float16)
+    same = (g == r) | (np.isinf(g) & np.isinf(r) & (np.sign(g) == np.sign(r)))
+    up = np.nextafter(r, np.float16(np.inf))
+    dn = np.nextafter(r, np.float16(-np.inf))
+    return same, same | (g == up) | (g == dn)
+
+
+@pytest.mark.parametrize("which", ["gauss", "ang"])
+def test_precision_records(which, request):
+    case = request.getfixturevalue(which)
+    w = case.w
+    ix = case.index(3)
+    lay = ix.layout()
+    assert lay.scalar_bytes == 8 and lay.bf16_offset > 0
+    mem = ix._keep[-1]
+    # bfloat16 copy: round to nearest even of every coordinate, bit for bit
+    n, d = case.x.shape
+    b16 = mem[lay.bf16_offset:lay.bf16_offset + 2 * n * d].view(torch.int16).cpu().numpy()
+    ref = torch.from_numpy(case.x).to(torch.bfloat16).view(torch.int16).numpy().reshape(-1)
+    assert np.array_equal(b16, ref)
+    # records: codes as in the full-precision form, scalars as halves
+    rec = mem[:n * lay.node_stride].view(n, lay.node_stride).cpu().numpy()
+    cb = lay.code_bytes
+    codes = rec[:, lay.codes_offset:lay.codes_offset + cb * w.R].reshape(n, w.R, cb)[..., :w.L + 1]
+    hs = rec[:, lay.scalars_offset:lay.scalars_offset + 8 * w.R].copy().view(np.float16)
+    hs = hs.reshape(n, w.R, 4).astype(np.float64)
+    rc, rs, _ = O.build_tables(case.x, case.g, w.L, w.m, case.A, case.B)
+    valid = case.g >= 0
+    assert np.array_equal(codes[valid], rc[valid])
+    ne, wreg, wres, ge = (rs[..., i][valid] for i in range(4))
+    if w.metric == W.ANGULAR:
+        ge = np.zeros_like(ge)  # the angular test has no g_e term
+    want = np.stack([np.where(ne > 0, ge / np.where(ne > 0, ne, 1), 0.0),
+                     np.where(ne > 0, 1.0 / np.where(ne > 0, ne, 1), np.inf),
+                     wreg, np.sqrt(w.L) * wres], 1)
+    exact_gp = want[:, 0].copy()
+    want = np.vectorize(O.round_half)(want)
+    got = hs[valid]
+    same, near = half_adjacent(got, want)
+    # 1/|e|, w_reg, sqrt(L) w_res: the nearest half, or the adjacent one
+    assert near[:, 1:].all()
+    # g_e/|e|: g_e = (|u|^2 - |v|^2)/2 is a single-precision difference of
+    # two squared norms (cancellation), then rounded to a half
+    scale = float((case.x.astype(np.float64) ** 2).sum(1).max())
+    ulp = np.abs(want[:, 0]) * 2.0 ** -10 + 2.0 ** -24
+    lim = ulp + 2e-6 * scale / np.where(ne > 0, ne, 1.0)
+    assert np.all(np.abs(got[:, 0] - exact_gp) <= lim)
+    assert same.mean() >= 0.99
+    print(f"[gpu] {which}: half scalars equal to the oracle's rounding: {same.mean():.5f}")
+
+
+@pytest.mark.parametrize("which", ["gauss", "ang"])
+def test_precision_tables(which, request):
+    case = request.getfixturevalue(which)
+    w = case.w
+    nq = len(case.q)
+    ix = case.index(3)
+    tables = torch.zeros((nq, w.L + 1, w.m), dtype=torch.float16, device="cuda:0")
+    norms = torch.empty(nq, dtype=torch.float32, device="cuda:0")
+    P.peos_query_tables(ix, case.qt, tables, norms)
+    torch.cuda.synchronize()
+    got = tables.cpu().numpy()
+    ref = np.stack([O.query_table(case.q[i], w.L, w.m, case.A, case.B) for i in range(nq)])
+    ref = np.vectorize(O.round_half)(ref)
+    same, near = half_adjacent(got, ref)
+    assert near.all() and same.mean() >= 0.99
+
+
+@pytest.mark.parametrize("mode", [P.PEOS_MODE_PEOS, P.PEOS_MODE_EXHAUSTIVE])
+def test_bf16_traversal_on_exact_data_equals_fp32_path(ints, mode):
+    """Integer data in 0..255 is exact in bfloat16: flag BF16_BASE gives the
+    full-precision results, and the oracle's precision form agrees."""
+    w = ints.w
+    a = ints.run(0, mode=mode, pool=w.ef)
+    b = ints.run(P.PEOS_FLAG_BF16_BASE, mode=mode, pool=w.ef)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2], b[2])
+    ref = ints.oracle(O.LP_BF16_BASE, pool=w.ef, mode=mode)
+    res = compare(b[0], b[1], b[2], ref, w.k)
+    assert not res["bad"], res["bad"][:5]
+
+
+@pytest.mark.parametrize("which", ["gauss", "ang"])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_bf16_traversal_matches_oracle(which, pool_mul, request):
+    """bfloat16 traversal + single-precision re-rank: exact parity on
+    non-fragile queries (both sides use the canonical order on the same
+    rounded values)."""
+    case = request.getfixturevalue(which)
+    w = case.w
+    ids, d, st = case.run(P.PEOS_FLAG_BF16_BASE, pool=pool_mul * w.ef)
+    ref = case.oracle(O.LP_BF16_BASE, pool=pool_mul * w.ef)
+    res = compare(ids, d, st, ref, w.k)
+    print(f"[gpu] {which} bf16: checked={res['checked']} fragile={res['fragile']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+
+
+@pytest.mark.parametrize("which", ["gauss", "ang"])
+@pytest.mark.parametrize("flags", [P.PEOS_FLAG_FP16, P.PEOS_FLAG_FP16 | P.PEOS_FLAG_BF16_BASE])
+def test_half_form_against_oracle(which, flags, request):
+    """Halves for scalars and tables: most queries identical to the oracle's
+    precision form; every returned distance within 1e-5 of float64 (the
+    re-rank or the traversal is single precision on exact values); recall
+    within half a point of the full-precision path's."""
+    case = request.getfixturevalue(which)
+    w = case.w
+    ids, d, st = case.run(flags, pool=w.ef)
+    ref = case.oracle(flags, pool=w.ef)
+    frag = ref["fragile"] != 0
+    same = np.all(ids == ref["ids"], axis=1) & np.all(d.astype(np.float64) == ref["dist"], axis=1)
+    print(f"[gpu] {which} flags={flags}: identical {same[~frag].mean():.3f} of non-fragile")
+    assert same[~frag].mean() >= 0.9
+    d64 = O.brute_force(case.x, case.q, w.k, w.metric)
+    valid = ids >= 0
+    xs = case.x.astype(np.float64)
+    for i in range(len(ids)):
+        row = ids[i][valid[i]]
+        if w.metric == W.L2:
+            exact = ((xs[row] - case.q[i]) ** 2).sum(1)
+        else:
+            exact = 1.0 - xs[row] @ case.q[i].astype(np.float64) / np.linalg.norm(case.q[i])
+        assert np.all(np.abs(d[i][valid[i]] - exact) <= 1e-5 * np.abs(exact) + 1e-6)
+    full = case.run(0, pool=w.ef)
+    gt = d64[0]
+    rec = lambda I: np.mean([len(set(I[i]) & set(gt[i])) / w.k for i in range(len(I))])
+    print(f"[gpu] {which} flags={flags}: recall {rec(ids):.4f} vs full {rec(full[0]):.4f}")
+    assert rec(ids) >= rec(full[0]) - 0.005

@@ -830,3 +830,16 @@ def test_half_search_mostly_equals_exact_decisions():
     same = np.all(a["ids"] == b["ids"], axis=1) & np.all(a["counters"] == b["counters"], axis=1)
     assert same.mean() >= 0.8
     assert np.array_equal(a["counters"][:, 0] > 0, b["counters"][:, 0] > 0)
+
+
+@pytest.mark.parametrize("mult", [1, 2, 3])
+def test_pool_multiple_of_ef_equals_fixed_pool(mult):
+    """pool = -m (a queue of m x each query's ef) equals pool = m x ef when all
+    queries share ef, and pool = -1 is the HNSW stopping rule."""
+    w = W.TINY.with_sizes(n=1500, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    a = O.search(x, g, entry, q, 10, 24, w.L, w.m, A, B, w.metric, 0.1, pool=-mult)
+    b = O.search(x, g, entry, q, 10, 24, w.L, w.m, A, B, w.metric, 0.1, pool=mult * 24)
+    assert np.array_equal(a["ids"], b["ids"]) and np.array_equal(a["counters"], b["counters"])

@@ -98,7 +98,7 @@ def knn(base: torch.Tensor, queries: torch.Tensor, k: int, exclude_self: bool = 
     return out_i, out_d
 
 
-def knn_ivf(x: torch.Tensor, k: int, nlist: int = 2048, nprobe: int = 12, iters: int = 8,
+def knn_ivf(x: torch.Tensor, k: int, nlist: int = 1024, nprobe: int = 16, iters: int = 8,
             seed: int = 0, log=None):
     """Approximate k nearest neighbours of every row of x among the rows of x
     (self excluded), for bases too large for the exact product: k-means
