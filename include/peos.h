@@ -243,7 +243,9 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
  *              in the workspace (PEOS_STATUS_VISITED_SPILL);
  *   listcap    candidate-list capacity in LDS (rounded up to a multiple of 64
  *              and to at least max(pool, ef)); with pool = 0 it is the
- *              kernel capacity that PEOS_STATUS_POOL_FULL refers to;
+ *              kernel capacity that PEOS_STATUS_POOL_FULL refers to.  Setting
+ *              it also keeps the list in LDS where it would otherwise live in
+ *              registers (capacity = ef <= 64);
  *   slots      resident waves of the persistent grid, 1..4096.
  * Results do not depend on the tuning except through the pool capacity.
  * Errors: PEOS_EINVAL for values out of range.

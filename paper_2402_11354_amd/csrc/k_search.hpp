@@ -221,7 +221,10 @@ __device__ __forceinline__ void distances(const void* base, int d, const uint32_
 #define PEOS_SEARCH_WAVES_PER_EU 4
 #endif
 
-template <int MAXL, int FLAGS>
+// REGL: the candidate list is the result list alone (capacity = ef <= 64,
+// the HNSW stopping rule): entry i lives in lane i's registers (rd, ri), so
+// the pop is a ballot and the merge a register scatter through LDS staging.
+template <int MAXL, int FLAGS, bool REGL>
 __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchArgs a)
 {
     constexpr bool BF = (FLAGS & kFlagBf16Base) != 0;
@@ -263,6 +266,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
         // |pool| times this query's ef, 0 the kernel's (the unbounded queue)
         int cap = a.pool > 0 ? (a.pool > efq ? a.pool : efq) : (a.pool < 0 ? -a.pool * efq : a.listcap);
         cap = cap < a.listcap ? cap : a.listcap;
+        if (REGL) cap = cap < kWave ? cap : kWave;
         const float qn = a.qnorms[qi];
         int status = 0;
         int st_exp = 0, st_edges = 0, st_skip = 0, st_tests = 0, st_ge1 = 0, st_le0 = 0, st_h = 0,
@@ -288,7 +292,15 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 hash_insert(hash, (uint32_t)hcap, (uint32_t)a.entry);
             }
             wave_sync();
-            if (lane == 0) {
+            // list entry `lane` (REGL)
+            float rd = INFINITY;
+            uint32_t ri = 0u;
+            if (REGL) {
+                if (lane == 0) {
+                    rd = Sdist[0];
+                    ri = (uint32_t)a.entry;
+                }
+            } else if (lane == 0) {
                 Ld[0] = Sdist[0];
                 Li[0] = (uint32_t)a.entry;
             }
@@ -304,22 +316,35 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             for (;;) {
                 // pop: first unexpanded entry of the list
                 int pos = -1;
-                for (int c0 = lb; c0 < size; c0 += kWave) {
-                    const int p = c0 + lane;
-                    const uint64_t mk = ballot(p < size && !(Li[p] & kExpanded));
-                    if (mk) {
-                        pos = c0 + __ffsll((unsigned long long)mk) - 1;
-                        break;
-                    }
-                }
-                if (pos < 0) break;
-                lb = pos + 1;
-                const uint32_t vid = wave_uniform(Li[pos] & kIdMask);
-                const float dv = Ld[pos];
+                uint32_t vid;
+                float dv, delta;
                 const bool full = size >= efq;
-                const float delta = full ? Ld[efq - 1] : INFINITY;
-                wave_sync();
-                if (lane == 0) Li[pos] = vid | kExpanded;
+                if (REGL) {
+                    const uint64_t mk = ballot(lane < size && !(ri & kExpanded));
+                    if (!mk) break;
+                    pos = __ffsll((unsigned long long)mk) - 1;
+                    vid = (uint32_t)__builtin_amdgcn_readlane((int)ri, pos) & kIdMask;
+                    dv = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rd), pos));
+                    delta = full ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rd), efq - 1))
+                                 : INFINITY;
+                    if (lane == pos) ri |= kExpanded;
+                } else {
+                    for (int c0 = lb; c0 < size; c0 += kWave) {
+                        const int p = c0 + lane;
+                        const uint64_t mk = ballot(p < size && !(Li[p] & kExpanded));
+                        if (mk) {
+                            pos = c0 + __ffsll((unsigned long long)mk) - 1;
+                            break;
+                        }
+                    }
+                    if (pos < 0) break;
+                    lb = pos + 1;
+                    vid = wave_uniform(Li[pos] & kIdMask);
+                    dv = Ld[pos];
+                    delta = full ? Ld[efq - 1] : INFINITY;
+                    wave_sync();
+                    if (lane == 0) Li[pos] = vid | kExpanded;
+                }
                 ++st_exp;
                 const bool testing = (a.mode == 0) && full;
 
@@ -452,6 +477,43 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 st_ins += nS;
                 if (nS == 0) continue;
 
+                if (REGL) {
+                    // list entry i (lane i) moves up by the number of
+                    // survivors below it; survivor t goes to (survivors below
+                    // it) + (list entries below it).  Positions from cap = ef
+                    // on are dropped (the launch guarantees cap = ef).
+                    const bool inl = lane < size;
+                    const uint64_t lk = inl ? sort_key(rd, ri) : ~0ull;
+                    int rS = 0, lo = 0, sh = 0;
+                    for (uint64_t mm = km; mm; mm &= mm - 1) {
+                        const int t = __ffsll((unsigned long long)mm) - 1;
+                        const uint64_t kt = readlane64(skey, t);
+                        rS += kt < skey;
+                        const bool below = inl && lk < kt;
+                        sh += (inl && !below) ? 1 : 0;
+                        const int nb = popc(ballot(below));
+                        lo += (lane == t) ? nb : 0;
+                    }
+                    const int lpos = lane + sh;
+                    const int spos = lo + rS;
+                    wave_sync();  // Sdist / Su were read above
+                    if (inl && lpos < cap) {
+                        Sdist[lpos] = rd;
+                        Su[lpos] = ri;
+                    }
+                    if (keep && spos < cap) {
+                        Sdist[spos] = dt;
+                        Su[spos] = ut;
+                    }
+                    const int total = size + nS < cap ? size + nS : cap;
+                    wave_sync();
+                    rd = lane < total ? Sdist[lane] : INFINITY;
+                    ri = lane < total ? Su[lane] : 0u;
+                    size = total;
+                    wave_sync();
+                    continue;
+                }
+
                 // merge in place: rank of each survivor among the survivors,
                 // number of list entries below it (lo), and for each list
                 // entry the number of survivors below it (its shift).  Keys
@@ -528,6 +590,14 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 minpos = wave_uniform(minpos);
                 lb = lb < efq ? lb : efq;
                 lb = lb < minpos ? lb : minpos;
+                wave_sync();
+            }
+            if (REGL) {
+                // the list to LDS for the output (and the re-rank)
+                if (lane < size) {
+                    Ld[lane] = rd;
+                    Li[lane] = ri;
+                }
                 wave_sync();
             }
         } else {

@@ -151,13 +151,12 @@ int ensure_kernel_attrs(int dev)
     std::lock_guard<std::mutex> g(mu);
     if (dev < 0 || dev >= 64) return fail(PEOS_EDEVICE, "device index %d", dev);
     if (!done[dev]) {
-        const void* fns[] = {
-            (const void*)peos::k_search<8, 0>,  (const void*)peos::k_search<8, 1>,
-            (const void*)peos::k_search<8, 2>,  (const void*)peos::k_search<8, 3>,
-            (const void*)peos::k_search<16, 0>, (const void*)peos::k_search<16, 1>,
-            (const void*)peos::k_search<16, 2>, (const void*)peos::k_search<16, 3>,
-            (const void*)peos::k_search<32, 0>, (const void*)peos::k_search<32, 1>,
-            (const void*)peos::k_search<32, 2>, (const void*)peos::k_search<32, 3>};
+#define PEOS_FNS(ML, RG)                                                                      \
+    (const void*)peos::k_search<ML, 0, RG>, (const void*)peos::k_search<ML, 1, RG>,          \
+        (const void*)peos::k_search<ML, 2, RG>, (const void*)peos::k_search<ML, 3, RG>
+        const void* fns[] = {PEOS_FNS(8, false),  PEOS_FNS(16, false), PEOS_FNS(32, false),
+                             PEOS_FNS(8, true),   PEOS_FNS(16, true),  PEOS_FNS(32, true)};
+#undef PEOS_FNS
         for (const void* f : fns)
             HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
         done[dev] = true;
@@ -166,6 +165,7 @@ int ensure_kernel_attrs(int dev)
 }
 
 struct SearchPlan {
+    bool list_in_lds;  // a list capacity was forced: keep the list in LDS
     int listcap, listslack, hcap, visit_limit, slots;
     int64_t lds;
     int64_t spill_words;
@@ -191,6 +191,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     int lc = pool != 0 ? lmin : (16 * efmax > 256 ? 16 * efmax : 256);
     if (pool == 0 && lc > 2048) lc = lmin > 2048 ? lmin : 2048;
     if (t.listcap > 0) lc = t.listcap > lmin ? t.listcap : lmin;
+    p.list_in_lds = t.listcap > 0;
     lc = (int)round_up(lc, 64);
     if (lc > kMaxEf * 2) lc = kMaxEf * 2;
     p.listcap = lc;
@@ -453,6 +454,10 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
                          int slots_cap, hipStream_t s)
 {
     SearchPlan plan = plan_search(ix, nq, efmax, pool, per_query, cls);
+    // the list in registers when every query's capacity is its own ef
+    // (<= 64): pool = 1 with per-query lists, or pool <= ef with one list size
+    const bool regl = efmax <= 64 && pool > 0 && (per_query ? pool == 1 : pool <= efmax) &&
+                      !plan.list_in_lds;
     if (slots_cap > 0 && plan.slots > slots_cap) plan.slots = slots_cap;
     if (plan.lds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
     peos::SearchArgs a = base_args;
@@ -464,17 +469,20 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     a.visit_limit = plan.visit_limit;
     const dim3 grid((unsigned)plan.slots);
     const size_t lds = (size_t)plan.lds;
-#define PEOS_LAUNCH(ML)                                                                          \
-    switch (ix->flags & kFlagsAll) {                                                             \
-    case 0: hipLaunchKernelGGL((peos::k_search<ML, 0>), grid, dim3(64), lds, s, a); break;        \
-    case 1: hipLaunchKernelGGL((peos::k_search<ML, 1>), grid, dim3(64), lds, s, a); break;        \
-    case 2: hipLaunchKernelGGL((peos::k_search<ML, 2>), grid, dim3(64), lds, s, a); break;        \
-    default: hipLaunchKernelGGL((peos::k_search<ML, 3>), grid, dim3(64), lds, s, a); break;       \
+#define PEOS_LAUNCH2(ML, RG)                                                                      \
+    switch (ix->flags & kFlagsAll) {                                                              \
+    case 0: hipLaunchKernelGGL((peos::k_search<ML, 0, RG>), grid, dim3(64), lds, s, a); break;     \
+    case 1: hipLaunchKernelGGL((peos::k_search<ML, 1, RG>), grid, dim3(64), lds, s, a); break;     \
+    case 2: hipLaunchKernelGGL((peos::k_search<ML, 2, RG>), grid, dim3(64), lds, s, a); break;     \
+    default: hipLaunchKernelGGL((peos::k_search<ML, 3, RG>), grid, dim3(64), lds, s, a); break;    \
     }
+#define PEOS_LAUNCH(ML)                                                                           \
+    if (regl) { PEOS_LAUNCH2(ML, true) } else { PEOS_LAUNCH2(ML, false) }
     if (ix->L <= 8) { PEOS_LAUNCH(8) }
     else if (ix->L <= 16) { PEOS_LAUNCH(16) }
     else { PEOS_LAUNCH(32) }
 #undef PEOS_LAUNCH
+#undef PEOS_LAUNCH2
     HIP_TRY(hipGetLastError());
     return PEOS_OK;
 }

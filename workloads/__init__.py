@@ -50,7 +50,7 @@ class Workload:
 # The five workloads.  Seeds follow 1000+c / 2000+c / 3000+c for workload c.
 TINY = Workload("tiny_gmm_2k_d32", 2000, 100, 32, 16, 32, 4, 16, L2, "gmm10", 0.1, 10, 32, 1001)
 SIFT_LIKE = Workload("sift_like_1m_d128", 1_000_000, 10_000, 128, 32, 64, 8, 16, L2, "expint100", 0.1, 10, 64, 1002)
-GIST_LIKE = Workload("gist_like_1m_d960", 1_000_000, 1_000, 960, 32, 64, 16, 16, L2, "gmm256aniso", 0.1, 10, 128, 1003)
+GIST_LIKE = Workload("gist_like_1m_d960", 1_000_000, 1_000, 960, 32, 64, 16, 16, L2, "gmm256lowrank", 0.1, 10, 128, 1003)
 DEEP_LIKE = Workload("deep_like_10m_d96", 10_000_000, 100_000, 96, 32, 64, 8, 16, ANGULAR, "sphere1000", 0.1, 10, 64, 1004)
 SERVING = Workload("serving_1m_d256", 1_000_000, 10_000, 256, 32, 64, 8, 16, ANGULAR, "sphere500", 0.1, 10, 64, 1005)
 
@@ -80,24 +80,36 @@ class _Model:
             wts = 1.0 / (c + 1.0)
             self.weights = wts / wts.sum()
             self.means = np.exp(rng.uniform(math.log(2.0), math.log(64.0), size=(100, w.d)))
-        elif w.family == "gmm256aniso":
-            # 256 anisotropic Gaussian clusters.
-            self.kind = "gmm"
-            self.centers = rng.normal(0.0, 1.0, size=(256, w.d))
-            self.scales = np.exp(rng.normal(math.log(0.3), 0.5, size=(256, w.d)))
+        elif w.family == "gmm256lowrank":
+            # 256 anisotropic clusters in a 48-dimensional latent space (the
+            # strong correlations of global image descriptors): x = mu_c +
+            # F (s_c * z) + 0.05 N(0, I), F a fixed d x 48 random factor
+            # matrix with unit-norm columns, s_c a decaying latent spectrum
+            # (j+1)^-1/2 scaled to norm 24 times a per-cluster LogNormal(0, 0.3)
+            # factor, centres N(0, 0.5^2 I) so that neighbouring clusters
+            # overlap.
+            self.kind = "lowrank"
+            k = 48
+            self.centers = rng.normal(0.0, 0.5, size=(256, w.d))
+            F = rng.normal(size=(w.d, k))
+            self.factors = F / np.linalg.norm(F, axis=0, keepdims=True)
+            spec = (np.arange(k) + 1.0) ** -0.5
+            spec = 24.0 * spec / np.linalg.norm(spec)
+            self.latent = spec[None, :] * np.exp(rng.normal(0.0, 0.3, size=(256, k)))
             self.weights = np.full(256, 1.0 / 256)
         elif w.family in ("sphere1000", "sphere500"):
             # vMF-like clusters on the sphere: normalize(mu_c + 2.5 s * z),
             # mu_c uniform on the sphere, z ~ N(0, I), and a decaying
-            # per-dimension spectrum s_j ~ (j+1)^-1/2 with |s| = 1, the shape of
-            # PCA-compressed descriptors (the noise norm of 2.5 makes
-            # neighbouring clusters overlap, as real descriptor clusters do).
+            # per-dimension spectrum s_j ~ (j+1)^-0.8 with |s| = 1, the shape of
+            # PCA-compressed descriptors (low intrinsic dimension; the noise
+            # norm of 2.5 makes neighbouring clusters overlap, as real
+            # descriptor clusters do).
             self.kind = "sphere"
             ncl = 1000 if w.family == "sphere1000" else 500
             mu = rng.normal(size=(ncl, w.d))
             self.centers = mu / np.linalg.norm(mu, axis=1, keepdims=True)
             self.weights = np.full(ncl, 1.0 / ncl)
-            spec = (np.arange(w.d) + 1.0) ** -0.5
+            spec = (np.arange(w.d) + 1.0) ** -0.8
             self.spectrum = 2.5 * spec / np.linalg.norm(spec)
         else:
             raise ValueError(f"unknown family {w.family}")
@@ -109,6 +121,10 @@ class _Model:
             z = rng.choice(len(self.weights), size=c, p=self.weights)
             if self.kind == "gmm":
                 x = self.centers[z] + self.scales[z] * rng.standard_normal((c, self.w.d))
+            elif self.kind == "lowrank":
+                lat = self.latent[z] * rng.standard_normal((c, self.latent.shape[1]))
+                x = (self.centers[z] + lat @ self.factors.T
+                     + 0.05 * rng.standard_normal((c, self.w.d)))
             elif self.kind == "expint":
                 x = np.minimum(255.0, np.floor(rng.exponential(1.0, size=(c, self.w.d)) * self.means[z]))
             else:
