@@ -60,31 +60,43 @@ constexpr int kStatusZeroQuery = 1;
 constexpr int kStatusPoolFull = 2;
 constexpr int kStatusSpill = 4;
 
-// visited set: open addressing with linear probing over cap slots (any
-// capacity: the home slot is the multiplicative hash scaled to [0, cap))
-__device__ __forceinline__ uint32_t hash_slot(uint32_t u, uint32_t cap)
+// visited set: open addressing over buckets of four slots (one 16-byte LDS
+// read per probe), linear probing over cap/4 buckets (any number: the home
+// bucket is the multiplicative hash scaled to [0, cap/4)).  A bucket fills
+// front to back and nothing is ever removed, so a lookup may stop at the
+// first bucket that still has an empty slot.
+__device__ __forceinline__ uint32_t hash_bucket(uint32_t u, uint32_t nb)
 {
-    return (uint32_t)(((uint64_t)(u * 0x9E3779B1u) * cap) >> 32);
+    return (uint32_t)(((uint64_t)(u * 0x9E3779B1u) * nb) >> 32);
 }
 
 __device__ __forceinline__ bool hash_lookup(const uint32_t* h, uint32_t cap, uint32_t u)
 {
-    uint32_t s = hash_slot(u, cap);
+    const uint32_t nb = cap >> 2;
+    uint32_t b = hash_bucket(u, nb);
     for (;;) {
-        const uint32_t k = h[s];
-        if (k == u) return true;
-        if (k == kEmpty) return false;
-        s = (s + 1u == cap) ? 0u : s + 1u;
+        const uint4 k = reinterpret_cast<const uint4*>(h)[b];
+        if (k.x == u || k.y == u || k.z == u || k.w == u) return true;
+        if (k.w == kEmpty) return false;
+        b = (b + 1u == nb) ? 0u : b + 1u;
     }
 }
 
 __device__ __forceinline__ void hash_insert(uint32_t* h, uint32_t cap, uint32_t u)
 {
-    uint32_t s = hash_slot(u, cap);
+    const uint32_t nb = cap >> 2;
+    uint32_t b = hash_bucket(u, nb);
     for (;;) {
-        const uint32_t prev = atomicCAS(&h[s], kEmpty, u);
+        const uint4 k = reinterpret_cast<const uint4*>(h)[b];
+        if (k.x == u || k.y == u || k.z == u || k.w == u) return;
+        const int e = k.x == kEmpty ? 0 : k.y == kEmpty ? 1 : k.z == kEmpty ? 2 : k.w == kEmpty ? 3 : -1;
+        if (e < 0) {
+            b = (b + 1u == nb) ? 0u : b + 1u;
+            continue;
+        }
+        const uint32_t prev = atomicCAS(&h[4 * b + e], kEmpty, u);
         if (prev == kEmpty || prev == u) return;
-        s = (s + 1u == cap) ? 0u : s + 1u;
+        // another lane took the slot: read the bucket again
     }
 }
 
@@ -190,9 +202,12 @@ __device__ __forceinline__ void gather_distances(const void* base, int d, const 
         for (int pp = 0; pp < PER; ++pp) {
             // tree levels across lanes (segment index bits below log2 G)
 #pragma unroll
-            for (int o = 1; o < G; o <<= 1)
-#pragma unroll
-                for (int j = 0; j < NP; ++j) part[pp][j] = part[pp][j] + __shfl_xor(part[pp][j], o, G);
+            for (int j = 0; j < NP; ++j) {
+                if (G > 1) part[pp][j] = part[pp][j] + xor_lane<1>(part[pp][j]);
+                if (G > 2) part[pp][j] = part[pp][j] + xor_lane<2>(part[pp][j]);
+                if (G > 4) part[pp][j] = part[pp][j] + xor_lane<4>(part[pp][j]);
+                if (G > 8) part[pp][j] = part[pp][j] + xor_lane<8>(part[pp][j]);
+            }
             // remaining levels inside the lane
 #pragma unroll
             for (int h = 1; h < NP; h <<= 1)

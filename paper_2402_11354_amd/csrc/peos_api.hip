@@ -200,6 +200,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     int hc = 2048;
     while (hc < 32 * efmax && hc < 8192) hc *= 2;
     if (t.hash_cap > 0) hc = t.hash_cap;
+    hc &= ~3;  // whole buckets of four slots
     p.hcap = hc;
     p.visit_limit = (3 * hc) / 4;
     // A merge writes up to one wave of survivors past the capacity; that room

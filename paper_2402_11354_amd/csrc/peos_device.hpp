@@ -48,10 +48,28 @@ __device__ __forceinline__ uint64_t readlane64(uint64_t v, int t)
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
+// value of v in lane (this lane xor O), all lanes active: lane swaps within
+// quads are DPP moves (no LDS round trip), xor 4 / 8 / 16 a swizzle, wider
+// ones a permute through the LDS crossbar
+template <int O>
+__device__ __forceinline__ float xor_lane(float v)
+{
+    static_assert(O >= 1 && O < 64 && (O & (O - 1)) == 0, "power of two below 64");
+    const int b = __float_as_int(v);
+    if (O == 1) return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0xB1, 0xF, 0xF, false));
+    if (O == 2) return __int_as_float(__builtin_amdgcn_mov_dpp(b, 0x4E, 0xF, 0xF, false));
+    if (O < 32) return __int_as_float(__builtin_amdgcn_ds_swizzle(b, 0x1F | (O << 10)));
+    return __shfl_xor(v, O, kWave);
+}
+
 __device__ __forceinline__ float wave_sum(float v)
 {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    v += xor_lane<32>(v);
+    v += xor_lane<16>(v);
+    v += xor_lane<8>(v);
+    v += xor_lane<4>(v);
+    v += xor_lane<2>(v);
+    v += xor_lane<1>(v);
     return v;
 }
 
@@ -59,8 +77,12 @@ __device__ __forceinline__ float wave_sum(float v)
 template <int G>
 __device__ __forceinline__ float group_sum(float v)
 {
-#pragma unroll
-    for (int o = G / 2; o >= 1; o >>= 1) v += __shfl_xor(v, o, G);
+    if (G >= 64) v += xor_lane<32>(v);
+    if (G >= 32) v += xor_lane<16>(v);
+    if (G >= 16) v += xor_lane<8>(v);
+    if (G >= 8) v += xor_lane<4>(v);
+    if (G >= 4) v += xor_lane<2>(v);
+    if (G >= 2) v += xor_lane<1>(v);
     return v;
 }
 
