@@ -238,9 +238,10 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
 /*
  * peos_set_search_tuning -- override the search kernel's launch plan for all
  * later calls in this process (0 keeps the automatic choice):
- *   hash_cap   visited-hash capacity in LDS, 64..16384 entries; a query that
- *              visits more than 3/4 of it moves its visited set to a bitmap
- *              in the workspace (PEOS_STATUS_VISITED_SPILL);
+ *   hash_cap   visited-hash capacity in LDS, 64..16384 entries (rounded down
+ *              to a multiple of 4); a query that visits more than 3/4 of it
+ *              moves its visited set to a bitmap in the workspace
+ *              (PEOS_STATUS_VISITED_SPILL);
  *   listcap    candidate-list capacity in LDS (rounded up to a multiple of 64
  *              and to at least max(pool, ef)); with pool = 0 it is the
  *              kernel capacity that PEOS_STATUS_POOL_FULL refers to.  Setting

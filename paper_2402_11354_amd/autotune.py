@@ -18,7 +18,7 @@ import torch
 from . import peos_search_ws_bytes, peos_set_search_tuning, search
 
 CACHE = os.environ.get("PEOS_TUNE_CACHE", os.path.expanduser("~/.cache/peos_tune.json"))
-HASH_CAPS = (0, 1024, 1536, 1920, 3072, 4096, 8192)  # 0 = the library's default plan
+HASH_CAPS = (0, 1024, 1536, 1792, 2048, 3072, 4096, 8192)  # 0 = the library's default plan
 KEEP_DEFAULT = 0.03  # another plan must be this much faster to replace the default
 
 

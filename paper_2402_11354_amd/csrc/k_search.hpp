@@ -247,42 +247,52 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
     const void* tbase = BF ? (const void*)a.base16 : (const void*)a.base;
     extern __shared__ __align__(16) unsigned char sm[];
     const int lane = lane_id();
+    // The arguments used once per query live in LDS and are read where they
+    // are used, so they do not hold scalar registers across the expansion
+    // loop (which would otherwise spill).
+    __shared__ SearchArgs ca;
+    for (int t = lane; t < (int)(sizeof(SearchArgs) / 4); t += kWave)
+        reinterpret_cast<uint32_t*>(&ca)[t] = reinterpret_cast<const uint32_t*>(&a)[t];
+    wave_sync();
     const int d = a.d, R = a.R, L = a.L, m = a.m;
     const int hcap = a.hcap;
-    const int slack = a.listslack;  // room past the capacity during a merge
+    const int slack = wave_uniform(ca.listslack);  // room past the capacity during a merge
+    const int listcap = wave_uniform(ca.listcap);
     float* qv = reinterpret_cast<float*>(sm);
     float* tab = qv + d;
     float* Ld = tab + (L + 1) * m;
-    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + a.listcap + slack);
-    uint32_t* hash = Li + a.listcap + slack;
+    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + listcap + slack);
+    uint32_t* hash = Li + listcap + slack;
     uint32_t* Su = hash + hcap;
     float* Sdist = reinterpret_cast<float*>(Su + kWave);
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
 
-    uint32_t qbegin = 0, qend = (uint32_t)a.nq;
-    if (a.qperm) {
-        qbegin = a.qrange[0];
-        qend = a.qrange[1];
+    uint32_t qbegin = 0, qend = wave_uniform((uint32_t)ca.nq);
+    if (ca.qperm) {
+        qbegin = wave_uniform(ca.qrange[0]);
+        qend = wave_uniform(ca.qrange[1]);
     }
     for (;;) {
         uint32_t qtaken = 0;
-        if (lane == 0) qtaken = atomicAdd(a.counter, 1u);
+        if (lane == 0) qtaken = atomicAdd(ca.counter, 1u);
         const uint32_t slot = wave_uniform((uint32_t)__shfl((int)qtaken, 0, kWave)) + qbegin;
         if (slot >= qend) break;
-        const int64_t qi = a.qperm ? (int64_t)wave_uniform(a.qperm[slot]) : (int64_t)slot;
+        const int64_t qi = ca.qperm ? (int64_t)wave_uniform(ca.qperm[slot]) : (int64_t)slot;
 
         // per-query k and ef are clamped to the launch bounds k_all, ef_all
-        int kq = a.kq ? a.kq[qi] : a.k_all;
-        kq = kq < 1 ? 1 : (kq > a.k_all ? a.k_all : kq);
-        int efq = a.efq ? a.efq[qi] : a.ef_all;
-        efq = efq > a.ef_all ? a.ef_all : efq;
+        const int k_all = wave_uniform(ca.k_all), ef_all = wave_uniform(ca.ef_all);
+        const int pool = wave_uniform(ca.pool);
+        int kq = ca.kq ? wave_uniform(ca.kq[qi]) : k_all;
+        kq = kq < 1 ? 1 : (kq > k_all ? k_all : kq);
+        int efq = ca.efq ? wave_uniform(ca.efq[qi]) : ef_all;
+        efq = efq > ef_all ? ef_all : efq;
         efq = efq > kq ? efq : kq;
         // list capacity: pool > 0 a fixed capacity (at least ef), pool < 0
         // |pool| times this query's ef, 0 the kernel's (the unbounded queue)
-        int cap = a.pool > 0 ? (a.pool > efq ? a.pool : efq) : (a.pool < 0 ? -a.pool * efq : a.listcap);
-        cap = cap < a.listcap ? cap : a.listcap;
+        int cap = pool > 0 ? (pool > efq ? pool : efq) : (pool < 0 ? -pool * efq : listcap);
+        cap = cap < listcap ? cap : listcap;
         if (REGL) cap = cap < kWave ? cap : kWave;
-        const float qn = a.qnorms[qi];
+        const float qn = wave_uniform(ca.qnorms[qi]);
         int status = 0;
         int st_exp = 0, st_edges = 0, st_skip = 0, st_tests = 0, st_ge1 = 0, st_le0 = 0, st_h = 0,
             st_zero = 0, st_pass = 0, st_ndist = 0, st_ins = 0;
@@ -290,21 +300,21 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
 
         if (qn > 0.f && qn < INFINITY) {
             const float inv_qn = 1.f / qn;
-            const float* qg = a.queries + qi * d;
+            const float* qg = ca.queries + qi * d;
             for (int t = lane; t < d; t += kWave) qv[t] = qg[t];
             if (H16) {
-                const _Float16* tg = reinterpret_cast<const _Float16*>(a.tables) + qi * (int64_t)(L + 1) * m;
+                const _Float16* tg = reinterpret_cast<const _Float16*>(ca.tables) + qi * (int64_t)(L + 1) * m;
                 for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = (float)tg[t];
             } else {
-                const float* tg = a.tables + qi * (int64_t)(L + 1) * m;
+                const float* tg = ca.tables + qi * (int64_t)(L + 1) * m;
                 for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = tg[t];
             }
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
-            if (lane == 0) Su[0] = (uint32_t)a.entry;
+            if (lane == 0) Su[0] = (uint32_t)wave_uniform(ca.entry);
             wave_sync();
             distances<BF>(tbase, d, Su, 1, qv, a.metric, inv_qn, Sdist);
             if (lane == 0) {
-                hash_insert(hash, (uint32_t)hcap, (uint32_t)a.entry);
+                hash_insert(hash, (uint32_t)hcap, (uint32_t)wave_uniform(ca.entry));
             }
             wave_sync();
             // list entry `lane` (REGL)
@@ -313,11 +323,11 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             if (REGL) {
                 if (lane == 0) {
                     rd = Sdist[0];
-                    ri = (uint32_t)a.entry;
+                    ri = (uint32_t)wave_uniform(ca.entry);
                 }
             } else if (lane == 0) {
                 Ld[0] = Sdist[0];
-                Li[0] = (uint32_t)a.entry;
+                Li[0] = (uint32_t)wave_uniform(ca.entry);
             }
             size = 1;
             int nvis = 1;
@@ -600,7 +610,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 } else {
                     w = total;
                 }
-                if (w > cap && a.pool == 0) status |= kStatusPoolFull;
+                if (w > cap && pool == 0) status |= kStatusPoolFull;
                 size = w < cap ? w : cap;
                 minpos = wave_uniform(minpos);
                 lb = lb < efq ? lb : efq;
@@ -619,6 +629,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             status |= kStatusZeroQuery;
         }
 
+        const int kstride = wave_uniform(ca.kstride);
         if (BF && size > 0) {
             // precision form: the result list (first ef entries) re-ranked by
             // full-precision distances; entry t goes to its rank among them
@@ -639,25 +650,25 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 int rank = 0;
                 for (int o = 0; o < nr; ++o) rank += sort_key(Ld[o], Li[o] & kIdMask) < key;
                 if (rank < kq) {
-                    a.ids[qi * a.kstride + rank] = (int64_t)id;
-                    a.dists[qi * a.kstride + rank] = Ld[t];
+                    ca.ids[qi * kstride + rank] = (int64_t)id;
+                    ca.dists[qi * kstride + rank] = Ld[t];
                 }
             }
             const int kout = kq < nr ? kq : nr;
-            for (int t = kout + lane; t < a.kstride; t += kWave) {
-                a.ids[qi * a.kstride + t] = -1;
-                a.dists[qi * a.kstride + t] = INFINITY;
+            for (int t = kout + lane; t < kstride; t += kWave) {
+                ca.ids[qi * kstride + t] = -1;
+                ca.dists[qi * kstride + t] = INFINITY;
             }
         } else {
             // results: first k entries of the list, padded with (-1, +inf)
-            for (int t = lane; t < a.kstride; t += kWave) {
+            for (int t = lane; t < kstride; t += kWave) {
                 const bool ok = t < kq && t < size;
-                a.ids[qi * a.kstride + t] = ok ? (int64_t)(Li[t] & kIdMask) : (int64_t)-1;
-                a.dists[qi * a.kstride + t] = ok ? Ld[t] : INFINITY;
+                ca.ids[qi * kstride + t] = ok ? (int64_t)(Li[t] & kIdMask) : (int64_t)-1;
+                ca.dists[qi * kstride + t] = ok ? Ld[t] : INFINITY;
             }
         }
-        if (a.stats && lane == 0) {
-            int32_t* o = a.stats + qi * 12;
+        if (ca.stats && lane == 0) {
+            int32_t* o = ca.stats + qi * 12;
             o[0] = st_exp;
             o[1] = st_edges;
             o[2] = st_skip;

@@ -54,6 +54,7 @@ int fail(int code, const char* fmt, ...)
 constexpr int kMaxSlots = 4096;      // resident search waves at most
 constexpr int kMaxEf = 4096;
 constexpr int64_t kLdsPerCu = 160 * 1024;
+constexpr int64_t kStaticLds = 256;  // the search kernel's copy of its arguments
 constexpr int kNumCu = 256;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
@@ -195,22 +196,31 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     lc = (int)round_up(lc, 64);
     if (lc > kMaxEf * 2) lc = kMaxEf * 2;
     p.listcap = lc;
-    // visited hash: 32 slots per list entry, 2048 to 8192 (a query that visits
-    // more than 3/4 of it moves to the HBM bitmap)
+    // list entries first (the visited hash is sized below)
+    p.listslack = (pool > 0 && pool <= efmax && !per_query) ? 0 : 64;
+    const int64_t fixed = 4LL * ix->d + 4LL * (ix->L + 1) * ix->m + 8LL * (lc + p.listslack) +
+                          4LL * 2 * 64;
+    // visited hash: 32 slots per list entry, 2048 to 8192; for lists up to
+    // 64 no more than fits the LDS share of the 16 waves per CU the kernel's
+    // registers allow (down to 1024).  A query that fills 3/4 of it moves
+    // to the HBM bitmap (probes grow quickly past that load).
     int hc = 2048;
     while (hc < 32 * efmax && hc < 8192) hc *= 2;
+    if (hc == 2048) {
+        int64_t fit = (kLdsPerCu / 16 - kStaticLds - fixed) / 4;
+        fit = fit < 1024 ? 1024 : fit;
+        hc = fit < hc ? (int)fit : hc;
+    }
     if (t.hash_cap > 0) hc = t.hash_cap;
     hc &= ~3;  // whole buckets of four slots
     p.hcap = hc;
     p.visit_limit = (3 * hc) / 4;
-    // A merge writes up to one wave of survivors past the capacity; that room
-    // is needed only when entries past ef are kept (pool above ef, or the
-    // unbounded queue).  When the capacity is ef they are dropped instead.
-    p.listslack = (pool > 0 && pool <= efmax && !per_query) ? 0 : 64;
-    // qv | table | list (lc + slack) | hash | survivor ids and distances
-    p.lds = 4LL * ix->d + 4LL * (ix->L + 1) * ix->m + 8LL * (lc + p.listslack) + 4LL * hc +
-            4LL * 2 * 64;
-    int64_t per_cu = kLdsPerCu / p.lds;
+    // qv | table | list (lc + slack) | hash | survivor ids and distances.
+    // A merge writes up to one wave of survivors past the capacity; that
+    // room (slack) is needed only when entries past ef are kept (pool above
+    // ef, or the unbounded queue); when the capacity is ef they are dropped.
+    p.lds = fixed + 4LL * hc;
+    int64_t per_cu = kLdsPerCu / (p.lds + kStaticLds);
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 16) per_cu = 16;
     int64_t slots = per_cu * kNumCu;
@@ -460,7 +470,7 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     const bool regl = efmax <= 64 && pool > 0 && (per_query ? pool == 1 : pool <= efmax) &&
                       !plan.list_in_lds;
     if (slots_cap > 0 && plan.slots > slots_cap) plan.slots = slots_cap;
-    if (plan.lds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
+    if (plan.lds + kStaticLds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
     peos::SearchArgs a = base_args;
     a.counter = const_cast<uint32_t*>(counter);
     a.spill_words = plan.spill_words;
@@ -469,6 +479,7 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     a.hcap = plan.hcap;
     a.visit_limit = plan.visit_limit;
     const dim3 grid((unsigned)plan.slots);
+    static_assert(sizeof(peos::SearchArgs) <= kStaticLds, "argument copy must fit its LDS share");
     const size_t lds = (size_t)plan.lds;
 #define PEOS_LAUNCH2(ML, RG)                                                                      \
     switch (ix->flags & kFlagsAll) {                                                              \

@@ -34,10 +34,14 @@ __device__ __forceinline__ uint64_t lanemask_lt()
 
 __device__ __forceinline__ int popc(uint64_t x) { return __popcll(x); }
 
-template <typename T>
-__device__ __forceinline__ T wave_uniform(T v)
+__device__ __forceinline__ int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v)
 {
-    return __builtin_amdgcn_readfirstlane(v);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ float wave_uniform(float v)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
 // value of v in lane t (t uniform across the wave), as a scalar
