@@ -73,8 +73,10 @@ def _load():
         lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, i32, P]
         lib.oracle_test_edge.restype = i32
         lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
-                                      i32, i32, f64, i32, f64, i32, i32, i32, P, P, P, P, P, P]
+                                      i32, i32, f64, i32, f64, i32, i32, P, i32, P, P, P, P, P, P]
         lib.oracle_search.restype = i32
+        lib.oracle_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P]
+        lib.oracle_dimension_permutation.restype = i32
         lib.oracle_round_half.argtypes = [f64]
         lib.oracle_round_half.restype = f64
         lib.oracle_round_bf16.argtypes = [ctypes.c_float]
@@ -84,7 +86,7 @@ def _load():
 
 
 def _p(a):
-    return a.ctypes.data_as(ctypes.c_void_p)
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
 def _f32(a):
@@ -180,7 +182,7 @@ def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps, lowp=0):
 # Alg. 1
 # ---------------------------------------------------------------------------
 def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MODE_PEOS,
-           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0):
+           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0, perm=None):
     """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
     pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
     0 < pool <= ef = the HNSW stopping rule, pool < 0 = |pool| x each
@@ -191,6 +193,8 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     half-rounded edge scalars and tables; LP_BF16_BASE = traversal on the
     bfloat16-rounded base, result list re-ranked in single precision on the
     full base (see routing_test_lowp and oracle_search in peos_oracle.c).
+    perm: optional dimension permutation (d ints) of the test: edge records
+    and tables on permuted coordinates, distances on the original ones.
     Returns dict(ids (nq, kstride) int64, dist (as decided), dist64 float64,
     counters (nq, 11) int64, fragile (nq,) int32 flag words, status (nq,) int32)."""
     if precision not in (32, 64):
@@ -211,14 +215,33 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     frag = np.zeros(nq, np.int32)
     status = np.zeros(nq, np.int32)
     nt = nthreads or min(16, os.cpu_count() or 1)
+    perm_arr = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+    if perm_arr is not None and sorted(perm_arr.tolist()) != list(range(d)):
+        raise ValueError("perm must be a permutation of range(d)")
     rc = _load().oracle_search(_p(base), n, d, _p(graph), graph.shape[1], int(entry), L, m, _p(A),
                                _p(B), metric, _p(queries), nq, _p(karr), _p(efarr), ks,
                                int(pool), float(eps), mode, float(tau), 1 if precision == 32 else 0,
-                               int(lowp), nt, _p(ids), _p(dist), _p(dist64), _p(cnt), _p(frag),
-                               _p(status))
+                               int(lowp), _p(perm_arr), nt, _p(ids), _p(dist), _p(dist64),
+                               _p(cnt), _p(frag), _p(status))
     if rc:
         raise ValueError("bad search arguments")
     return dict(ids=ids, dist=dist, dist64=dist64, counters=cnt, fragile=frag, status=status)
+
+
+def dimension_permutation(base, graph, L):
+    """The optional dimension permutation (appendix "Dimension Permutation"):
+    returns (perm, avg) with perm[i*d/L + t] the original dimension placed at
+    coordinate t of sub-vector i, avg[j] = mean squared j-th edge coordinate."""
+    base = _f32(base)
+    graph = np.ascontiguousarray(graph, dtype=np.int32)
+    n, d = base.shape
+    perm = np.zeros(d, np.int32)
+    avg = np.zeros(d, np.float64)
+    rc = _load().oracle_dimension_permutation(_p(base), n, d, _p(graph), graph.shape[1], L,
+                                              _p(perm), _p(avg))
+    if rc:
+        raise ValueError("bad arguments")
+    return perm, avg
 
 
 # ---------------------------------------------------------------------------

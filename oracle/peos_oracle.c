@@ -519,6 +519,74 @@ static int routing_test_lowp(const test_params* tp, const edge_rec* er, const do
 }
 
 /* ------------------------------------------------------------------ */
+/* Optional dimension permutation (appendix "Dimension Permutation")   */
+/* ------------------------------------------------------------------ */
+/*
+ * Avg(e_j) = mean over the graph's edges of the squared j-th coordinate of
+ * e = x_u - x_v.  The dimensions are sorted by ascending Avg (ties: smaller
+ * index first) and handed out in d/L rounds of L: in each round the next L
+ * dimensions, in that order, go one each to the subspace with the largest
+ * running sum of Avg among those not yet served this round (ties: smaller
+ * subspace index).  perm[i*d' + t] = the dimension that subspace i received
+ * in round t, i.e. coordinate t of sub-vector i of the permuted vector.
+ * avg (optional, d doubles) receives Avg.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_dimension_permutation(const float* base, int64_t n, int d, const int32_t* graph, int R,
+                                 int L, int32_t* perm, double* avg_out)
+{
+    if (n <= 0 || d <= 0 || R <= 0 || L <= 0 || d % L) return -1;
+    const int dp = d / L;
+    double* avg = (double*)calloc((size_t)d, sizeof(double));
+    int* order = (int*)malloc(sizeof(int) * (size_t)d);
+    double* sum = (double*)calloc((size_t)L, sizeof(double));
+    int* served = (int*)malloc(sizeof(int) * (size_t)L);
+    int* fill = (int*)calloc((size_t)L, sizeof(int));
+    int64_t ne = 0;
+    for (int64_t v = 0; v < n; ++v)
+        for (int r = 0; r < R; ++r) {
+            const int32_t u = graph[(size_t)v * R + r];
+            if (u < 0) continue;
+            ++ne;
+            for (int j = 0; j < d; ++j) {
+                const double t = (double)base[(size_t)u * d + j] - (double)base[(size_t)v * d + j];
+                avg[j] += t * t;
+            }
+        }
+    for (int j = 0; j < d; ++j) avg[j] = ne > 0 ? avg[j] / (double)ne : 0.0;
+    /* ascending Avg, ties by index (insertion sort: d is small) */
+    for (int j = 0; j < d; ++j) order[j] = j;
+    for (int a = 1; a < d; ++a) {
+        const int x = order[a];
+        int b = a - 1;
+        while (b >= 0 && (avg[order[b]] > avg[x] || (avg[order[b]] == avg[x] && order[b] > x))) {
+            order[b + 1] = order[b];
+            --b;
+        }
+        order[b + 1] = x;
+    }
+    for (int round = 0; round < dp; ++round) {
+        for (int i = 0; i < L; ++i) served[i] = 0;
+        for (int j = 0; j < L; ++j) {
+            const int dim = order[round * L + j];
+            int best = -1;
+            for (int i = 0; i < L; ++i)
+                if (!served[i] && (best < 0 || sum[i] > sum[best])) best = i;
+            served[best] = 1;
+            sum[best] += avg[dim];
+            perm[(size_t)best * dp + fill[best]] = dim;
+            fill[best]++;
+        }
+    }
+    if (avg_out) memcpy(avg_out, avg, sizeof(double) * (size_t)d);
+    free(avg);
+    free(order);
+    free(sum);
+    free(served);
+    free(fill);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
 /* Alg. 1 with the routing hook                                        */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -610,6 +678,7 @@ typedef struct {
     const int32_t *graph, *k, *ef;
     int64_t n, q0, q1;
     int d, R, L, m, metric, mode, entry, kstride, pool, fp32, lowp;
+    const int32_t* perm; /* dimension permutation of the test, or NULL */
     double eps, tau;
     int64_t* out_ids;
     double* out_dist;
@@ -669,8 +738,15 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         }
         return;
     }
+    /* the test works on permuted coordinates (codes, scalars, table); the
+       distances on the original ones */
+    float* qperm = NULL;
+    if (j->perm) {
+        qperm = (float*)malloc(sizeof(float) * (size_t)d);
+        for (int k = 0; k < d; ++k) qperm[k] = q[j->perm[k]];
+    }
     if (j->mode == OR_MODE_PEOS) {
-        oracle_query_table(q, d, j->L, j->m, j->A, j->B, table);
+        oracle_query_table(qperm ? qperm : q, d, j->L, j->m, j->A, j->B, table);
         if (j->lowp & LP_FP16)
             for (int t = 0; t < (j->L + 1) * j->m; ++t) table[t] = oracle_round_half(table[t]);
     }
@@ -715,7 +791,17 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             const float* xu = j->base + (size_t)u * d;
             int pass = 1;
             if (full && j->mode == OR_MODE_PEOS) {
-                edge_record(xv, xu, d, j->L, j->m, j->A, j->B, fw1, fw2, dw, &er);
+                if (j->perm) {
+                    float* xvp = fw1 + d;
+                    float* xup = fw2 + d;
+                    for (int k = 0; k < d; ++k) {
+                        xvp[k] = xv[j->perm[k]];
+                        xup[k] = xu[j->perm[k]];
+                    }
+                    edge_record(xvp, xup, d, j->L, j->m, j->A, j->B, fw1, fw2, dw, &er);
+                } else {
+                    edge_record(xv, xu, d, j->L, j->m, j->A, j->B, fw1, fw2, dw, &er);
+                }
                 double num;
                 if (j->lowp & LP_BF16_BASE) {
                     /* the numerator from the search's own (bfloat16 traversal)
@@ -795,6 +881,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
     }
     j->fragile[qi] = flags;
     j->status[qi] = 0;
+    free(qperm);
 #undef DIST
 }
 
@@ -821,8 +908,8 @@ static void* search_worker(void* arg)
     rentry* R = (rentry*)malloc(sizeof(rentry) * (size_t)(lcap + j->R + 1));
     rentry* S = (rentry*)malloc(sizeof(rentry) * (size_t)(j->R + 1));
     double* table = (double*)malloc(sizeof(double) * (size_t)(j->L + 1) * j->m);
-    float* fw1 = (float*)malloc(sizeof(float) * j->d);
-    float* fw2 = (float*)malloc(sizeof(float) * j->d);
+    float* fw1 = (float*)malloc(sizeof(float) * 2 * (size_t)j->d);
+    float* fw2 = (float*)malloc(sizeof(float) * 2 * (size_t)j->d);
     double* dw = (double*)malloc(sizeof(double) * j->d);
     for (int64_t qi = j->q0; qi < j->q1; ++qi)
         search_one(j, qi, &tp, visited, R, S, table, fw1, fw2, dw);
@@ -853,14 +940,16 @@ static void* search_worker(void* arg)
  * (routing_test_lowp); LP_BF16_BASE takes the traversal distances on the
  * bfloat16-rounded base (and the numerator of A_r from them) and re-ranks the
  * final result list with full-precision single-precision distances before
- * the first k are taken.
+ * the first k are taken.  perm (optional, d entries): the dimension
+ * permutation of the test -- edge records and the table are taken on the
+ * permuted coordinates, distances on the original ones.
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,
                   int L, int m, const float* A, const float* B, int metric, const float* queries,
                   int64_t nq, const int32_t* k, const int32_t* ef, int kstride, int pool,
-                  double eps, int mode, double tau, int fp32, int lowp, int nthreads,
-                  int64_t* out_ids,
+                  double eps, int mode, double tau, int fp32, int lowp, const int32_t* perm,
+                  int nthreads, int64_t* out_ids,
                   double* out_dist, double* out_dist64, int64_t* counters, int32_t* fragile,
                   int32_t* status)
 {
@@ -875,8 +964,8 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
                                nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
-                               pool, fp32 || lowp, lowp, eps, tau, out_ids, out_dist, out_dist64,
-                               counters, fragile, status};
+                               pool, fp32 || lowp, lowp, perm, eps, tau, out_ids, out_dist,
+                               out_dist64, counters, fragile, status};
         pthread_create(&th[t], NULL, search_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);

@@ -843,3 +843,65 @@ def test_pool_multiple_of_ef_equals_fixed_pool(mult):
     a = O.search(x, g, entry, q, 10, 24, w.L, w.m, A, B, w.metric, 0.1, pool=-mult)
     b = O.search(x, g, entry, q, 10, 24, w.L, w.m, A, B, w.metric, 0.1, pool=mult * 24)
     assert np.array_equal(a["ids"], b["ids"]) and np.array_equal(a["counters"], b["counters"])
+
+
+# ---------------------------------------------------------------------------
+# optional dimension permutation (appendix "Dimension Permutation")
+# ---------------------------------------------------------------------------
+def test_dimension_permutation_worked_example():
+    """d = 4, L = 2, one edge with squared coordinates (4, 1, 3, 2): ascending
+    order 1, 3, 2, 0; round 1: dim 1 -> S1 (both sums 0, first set), dim 3 ->
+    S2; round 2: dim 2 -> S2 (larger sum 2), dim 0 -> S1; sums 5 and 5."""
+    x = np.array([[0, 0, 0, 0], [2, 1, np.sqrt(3), np.sqrt(2)]], np.float32)
+    g = np.array([[1], [-1]], np.int32)
+    perm, avg = O.dimension_permutation(x, g, 2)
+    np.testing.assert_allclose(avg, [4, 1, 3, 2], rtol=1e-6)
+    assert perm.tolist() == [1, 0, 3, 2]
+
+
+def test_dimension_permutation_is_balanced_partition():
+    """A valid permutation, d/L dimensions per subspace, and subspace energies
+    no less balanced than the identity split (on strongly anisotropic data)."""
+    rng = np.random.default_rng(4)
+    d, L = 64, 8
+    scale = np.exp(rng.normal(0, 1.0, size=d))
+    x = (rng.normal(size=(600, d)) * scale).astype(np.float32)
+    g, _ = W.build_graph(x, 12, 24)
+    perm, avg = O.dimension_permutation(x, g, L)
+    assert sorted(perm.tolist()) == list(range(d))
+    dp = d // L
+    e_perm = avg[perm].reshape(L, dp).sum(1)
+    e_id = avg.reshape(L, dp).sum(1)
+    assert e_perm.max() - e_perm.min() <= e_id.max() - e_id.min()
+    # every round hands out one dimension per subspace, in ascending Avg
+    order = np.lexsort((np.arange(d), avg))
+    for t in range(dp):
+        assert sorted(perm.reshape(L, dp)[:, t].tolist()) == sorted(order[t * L:(t + 1) * L].tolist())
+    # the spread is at most the largest single Avg (greedy balancing bound)
+    assert e_perm.max() - e_perm.min() <= avg.max() + 1e-12
+
+
+def test_permuted_test_equals_permuted_directions():
+    """Permuting coordinates inside each block is the same as permuting the
+    projection vectors' coordinates the other way: the search with such a
+    permutation equals the unpermuted search with permuted directions."""
+    w = W.TINY.with_sizes(n=1500, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    d, L = w.d, w.L
+    dp = d // L
+    rng = np.random.default_rng(9)
+    perm = np.concatenate([i * dp + rng.permutation(dp) for i in range(L)]).astype(np.int32)
+    inv = np.argsort(perm)
+    # direction coordinate t of block i pairs with original coordinate perm[i*dp+t]
+    A2 = np.empty_like(A)
+    for i in range(L):
+        A2[i][:, perm[i * dp:(i + 1) * dp] - i * dp] = A[i]
+    B2 = B[:, inv]
+    a = O.search(x, g, entry, q, 10, 32, L, w.m, A, B, w.metric, 0.1, perm=perm, precision=32)
+    b = O.search(x, g, entry, q, 10, 32, L, w.m, A2, B2, w.metric, 0.1, precision=32)
+    same = (a["fragile"] == 0) & (b["fragile"] == 0)
+    assert same.mean() > 0.8
+    assert np.array_equal(a["ids"][same], b["ids"][same])
+    assert np.array_equal(a["counters"][same], b["counters"][same])
