@@ -141,7 +141,7 @@ def main():
     A, B = W.directions_for(w)
     log(f"data {w.name} n={w.n} nq={w.nq} d={w.d} in {time.time() - t0:.1f}s")
     t0 = time.time()
-    g, entry = W.build_graph(x, w.R, w.cand, device=dev, log=lambda m: log("graph:", m))
+    g, entry = W.graph_for(w, x, device=dev, log=lambda m: log("graph:", m))
     log(f"graph R={w.R} mean degree {(g >= 0).sum(1).mean():.2f} entry={entry} "
         f"in {time.time() - t0:.1f}s")
     xt, qt, gt_ = (torch.from_numpy(a).to(dev) for a in (x, q, g))
@@ -247,6 +247,18 @@ def main():
     pe, pe_ok = best(pe_sweeps.values())
     ex, ex_ok = best(ex_sweeps.values())
 
+    def interpolated(sweeps):
+        """QPS at exactly the target recall, linear in (recall, QPS) between
+        the two swept points that bracket it, best over the sweeps."""
+        out = None
+        for pts in sweeps:
+            for a_, b_ in zip(pts, pts[1:]):
+                if a_["recall"] < args.target <= b_["recall"]:
+                    t = (args.target - a_["recall"]) / (b_["recall"] - a_["recall"])
+                    v = a_["qps"] + t * (b_["qps"] - a_["qps"])
+                    out = v if out is None else max(out, v)
+        return None if out is None else round(out, 1)
+
     from paper_2402_11354_amd import autotune
 
     def tuned(cfg):
@@ -324,6 +336,9 @@ def main():
                        "search_ms": round(float(ex_search_ms.mean()), 4),
                        "ndist_per_query": round(float(ex["stats"][:, 9].mean()), 1)},
         "speedup_vs_exhaustive": round(qps / ex_qps, 3),
+        "interpolated_at_target": {"peos": interpolated(pe_sweeps.values()),
+                                   "exhaustive": interpolated(ex_sweeps.values()),
+                                   "note": "sweep timing (3 steps per point)"},
         "per_query": {"ndist": round(float(st[:, 9].mean()), 1),
                       "tests": round(float(st[:, 3].mean()), 1),
                       "expansions": round(float(st[:, 0].mean()), 1),
@@ -355,7 +370,7 @@ def _setup(name, n, nq, gt_k):
     A, B = W.directions_for(w)
     log(f"data {w.name} n={w.n} nq={w.nq} d={w.d} in {time.time() - t0:.1f}s")
     t0 = time.time()
-    g, entry = W.build_graph(x, w.R, w.cand, device=dev, log=lambda m: log("graph:", m))
+    g, entry = W.graph_for(w, x, device=dev, log=lambda m: log("graph:", m))
     log(f"graph R={w.R} mean degree {(g >= 0).sum(1).mean():.2f} in {time.time() - t0:.1f}s")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     index = P.peos_build_tables(T(x), T(g), entry, w.L, w.m, T(A), T(B), w.metric)
@@ -478,8 +493,8 @@ def precision(args):
     xs = torch.from_numpy(x).to(dev).double()
     qs = qt.double()
     result = {}
-    for k, efs in ((10, (16, 24, 32, 48, 64, 96, 128, 192, 256)),
-                   (100, (100, 128, 160, 192, 256, 320, 384, 512))):
+    for k, efs in ((10, (32, 64, 128, 192, 256, 384, 512)),
+                   (100, (128, 192, 256, 384, 512, 768, 1024))):
         ws = torch.empty(P.peos_search_ws_bytes(index, nq, max(efs), max(efs)),
                          dtype=torch.uint8, device=dev)
         rows = {}

@@ -153,6 +153,37 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
                       size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
                       peos_index** out);
 
+/*
+ * peos_dimension_permutation -- the optional dimension permutation of the
+ * paper's appendix "Dimension Permutation" (also Sec. 4.3): per coordinate j
+ * the energy sum over the graph's edges (v, u) of (x_u[j] - x_v[j])^2
+ * (proportional to Avg(e_j)); the dimensions sorted by ascending energy
+ * (ties: smaller index) are handed out in d/L rounds of L, each to the
+ * subspace with the largest running energy among those not yet served in
+ * the round (ties: smaller subspace).  perm (host, d int32) receives
+ * perm[i*(d/L) + t] = the original coordinate placed at coordinate t of
+ * sub-vector i.  ws: device workspace of peos_dimension_permutation_ws_bytes.
+ * Synchronous on `stream`.  Errors: PEOS_EINVAL, PEOS_ENOSPACE, PEOS_EHIP.
+ */
+int peos_dimension_permutation_ws_bytes(int32_t d, size_t* ws_bytes);
+int peos_dimension_permutation(const float* base, int64_t n, int32_t d, const int32_t* graph,
+                               int32_t R, int32_t L, int32_t* perm, void* ws, size_t ws_bytes,
+                               void* stream);
+/*
+ * peos_build_tables_permuted -- peos_build_tables with the dimension
+ * permutation perm (device, d int32, a permutation of 0..d-1; kept by the
+ * index, must stay valid until peos_free): steps (1)-(3) and the projection
+ * tables of step (5) take coordinate k of every vector from original
+ * coordinate perm[k]; distances and everything else use the original
+ * coordinates (the permutation changes neither the graph nor the guarantee).
+ * perm = NULL is peos_build_tables.
+ */
+int peos_build_tables_permuted(const float* base, int64_t n, int32_t d, const int32_t* graph,
+                               int32_t R, int32_t entry, int32_t L, int32_t m,
+                               const float* dirs_a, const float* dirs_b, int32_t metric,
+                               int32_t flags, const int32_t* perm, void* index_mem,
+                               size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
+                               peos_index** out);
 /* Fill *out (host) with the record layout of an index.  Errors: PEOS_EINVAL. */
 int peos_index_layout(const peos_index* index, peos_layout* out);
 

@@ -79,6 +79,10 @@ def lib():
         L.peos_build_tables.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, i32, P, sz,
                                         P, sz, P, ctypes.POINTER(P)]
         L.peos_index_layout.argtypes = [P, ctypes.POINTER(peos_layout)]
+        L.peos_build_tables_permuted.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32,
+                                                 i32, P, P, sz, P, sz, P, ctypes.POINTER(P)]
+        L.peos_dimension_permutation_ws_bytes.argtypes = [i32, Psz]
+        L.peos_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P, sz, P]
         L.peos_free.argtypes = [P]
         L.peos_free.restype = None
         L.peos_query_tables.argtypes = [P, P, i64, P, P, P]
@@ -103,6 +107,8 @@ def lib():
         L.peos_strerror.restype = ctypes.c_char_p
         L.peos_last_error.restype = ctypes.c_char_p
         for name in ("peos_index_bytes", "peos_build_tables", "peos_index_layout",
+                     "peos_build_tables_permuted", "peos_dimension_permutation_ws_bytes",
+                     "peos_dimension_permutation",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
                      "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
                      "peos_graph_create", "peos_graph_launch", "peos_serve_open",
@@ -163,20 +169,39 @@ class PeosIndex:
             pass
 
 
-def peos_build_tables(base, graph, entry, L, m, dirs_a, dirs_b, metric, flags=0, stream=None):
+def peos_build_tables(base, graph, entry, L, m, dirs_a, dirs_b, metric, flags=0, stream=None,
+                      perm=None):
     """Build the edge records.  base (n, d) float32, graph (n, R) int32,
-    dirs_a (L, m, d/L) float32, dirs_b (m, d) float32, all on the device."""
+    dirs_a (L, m, d/L) float32, dirs_b (m, d) float32, all on the device.
+    perm: optional int32 device tensor (d), the test's dimension permutation
+    (peos_build_tables_permuted)."""
     n, d = base.shape
     R = graph.shape[1]
     ib, wb = peos_index_bytes(n, d, R, L, m, flags)
     mem = torch.empty(ib, dtype=torch.uint8, device=base.device)
     ws = torch.empty(wb, dtype=torch.uint8, device=base.device)
     h = ctypes.c_void_p()
-    _check("peos_build_tables",
-           lib().peos_build_tables(_ptr(base), n, d, _ptr(graph), R, int(entry), L, m,
-                                   _ptr(dirs_a), _ptr(dirs_b), metric, flags, _ptr(mem), ib,
-                                   _ptr(ws), wb, _stream(stream), ctypes.byref(h)))
-    return PeosIndex(h, (base, graph, dirs_a, dirs_b, mem))
+    _check("peos_build_tables_permuted",
+           lib().peos_build_tables_permuted(_ptr(base), n, d, _ptr(graph), R, int(entry), L, m,
+                                            _ptr(dirs_a), _ptr(dirs_b), metric, flags,
+                                            _ptr(perm), _ptr(mem), ib, _ptr(ws), wb,
+                                            _stream(stream), ctypes.byref(h)))
+    return PeosIndex(h, (base, graph, dirs_a, dirs_b, perm, mem))
+
+
+def peos_dimension_permutation(base, graph, L, stream=None):
+    """The dimension permutation (host int32 numpy array of d entries)."""
+    n, d = base.shape
+    wb = ctypes.c_size_t()
+    _check("peos_dimension_permutation_ws_bytes",
+           lib().peos_dimension_permutation_ws_bytes(d, ctypes.byref(wb)))
+    ws = torch.empty(wb.value, dtype=torch.uint8, device=base.device)
+    perm = np.zeros(d, np.int32)
+    _check("peos_dimension_permutation",
+           lib().peos_dimension_permutation(_ptr(base), n, d, _ptr(graph), graph.shape[1], L,
+                                            perm.ctypes.data, _ptr(ws), wb.value,
+                                            _stream(stream)))
+    return perm
 
 
 def peos_index_layout(index):

@@ -33,6 +33,8 @@ struct EdgeBuildArgs {
     int64_t node_stride, codes_off, scal_off;
     int d, R, L, m, metric;
     int half_scalars;  // precision form: scalars as four halves per edge
+    const int32_t* perm;  // optional dimension permutation: coordinate k of
+                          // the test's vectors is original coordinate perm[k]
 };
 
 // LDS: xv[d] | e[4][d] | s[4][L] | row[R]
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
     const float* xvg = a.base + v * (int64_t)d;
     float nv2 = 0.f;
     for (int k = lane; k < d; k += kWave) {
-        float x = xvg[k];
+        float x = xvg[a.perm ? a.perm[k] : k];
         xv[k] = x;
         nv2 = fmaf(x, x, nv2);
     }
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
         if (u >= 0) {
             const float* xu = a.base + (int64_t)u * d;
             for (int k = s; k < d; k += 16) {
-                float x = xu[k];
+                float x = xu[a.perm ? a.perm[k] : k];
                 float t = x - xv[k];
                 e[k] = t;
                 nu2 = fmaf(x, x, nu2);
@@ -210,6 +212,27 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
             }
         }
         __syncthreads();
+    }
+}
+
+// Energy of the edge coordinates for the optional dimension permutation:
+// partial[b][j] = sum over the edges (v, u) of the nodes v = b, b + grid, ...
+// of (x_u[j] - x_v[j])^2, in that fixed order (threads over coordinates).
+__global__ __launch_bounds__(256) void k_edge_energy(const float* base, const int32_t* graph,
+                                                     int64_t n, int d, int R, float* partial)
+{
+    for (int j = threadIdx.x; j < d; j += blockDim.x) {
+        float acc = 0.f;
+        for (int64_t v = blockIdx.x; v < n; v += gridDim.x) {
+            const float xv = base[v * d + j];
+            for (int r = 0; r < R; ++r) {
+                const int32_t u = graph[v * R + r];
+                if (u < 0 || u >= n) continue;
+                const float t = base[(int64_t)u * d + j] - xv;
+                acc = fmaf(t, t, acc);
+            }
+        }
+        partial[(int64_t)blockIdx.x * d + j] = acc;
     }
 }
 

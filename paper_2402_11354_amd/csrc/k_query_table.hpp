@@ -28,6 +28,7 @@ struct QueryTableArgs {
     int64_t nq;
     int d, L, m;
     int half_out;          // store the table as IEEE halves (round to nearest even)
+    const int32_t* perm;   // optional dimension permutation of the test
 };
 
 __global__ __launch_bounds__(64) void k_query_table(QueryTableArgs a)
@@ -69,7 +70,8 @@ __global__ __launch_bounds__(64) void k_query_table(QueryTableArgs a)
             const float* bv = (i == 0) ? a.dirs_b + (int64_t)jdir * d
                                        : a.dirs_a + ((int64_t)(i - 1) * m + jdir) * dp;
             for (int k0 = 0; k0 < k_len; k0 += 4) {
-                const float av = valid ? qv[k_begin + k0 + kq] : 0.f;
+                const int kk = k_begin + k0 + kq;
+                const float av = valid ? qv[a.perm ? a.perm[kk] : kk] : 0.f;
                 const float bvv = bv[k0 + kb];
                 acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bvv, acc, 0, 0, 0);
             }

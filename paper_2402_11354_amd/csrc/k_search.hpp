@@ -220,12 +220,18 @@ __device__ __forceinline__ void gather_distances(const void* base, int d, const 
     }
 }
 
-template <bool BF>
+template <bool BF, bool WIDE = false>
 __device__ __forceinline__ void distances(const void* base, int d, const uint32_t* Su, int ns,
                                           const float* qv, int metric, float inv_qn, float* Sdist)
 {
     // 4..16 lanes per vector; each lane keeps at most 8 chunk loads in
-    // flight (one round trip for up to 16 vectors of 128 coordinates)
+    // flight (one round trip for up to 16 vectors of 128 coordinates).
+    // Long bfloat16 vectors: 16 lanes x 16 chunks (8 bytes each) cover up to
+    // 1024 coordinates in one round trip per 4 vectors.
+    if (WIDE && d > 512) {
+        gather_distances<16, 1, 16, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+        return;
+    }
     if (ns <= 4) gather_distances<16, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
     else if (ns <= 8) gather_distances<8, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
     else if (ns <= 16) gather_distances<4, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
             if (lane == 0) Su[0] = (uint32_t)wave_uniform(ca.entry);
             wave_sync();
-            distances<BF>(tbase, d, Su, 1, qv, a.metric, inv_qn, Sdist);
+            distances<BF, (MAXL >= 16) && BF>(tbase, d, Su, 1, qv, a.metric, inv_qn, Sdist);
             if (lane == 0) {
                 hash_insert(hash, (uint32_t)hcap, (uint32_t)wave_uniform(ca.entry));
             }
@@ -481,7 +487,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 nvis += ns;
                 wave_sync();
-                distances<BF>(tbase, d, Su, ns, qv, a.metric, inv_qn, Sdist);
+                distances<BF, (MAXL >= 16) && BF>(tbase, d, Su, ns, qv, a.metric, inv_qn, Sdist);
                 st_ndist += ns;
                 wave_sync();
 
@@ -639,7 +645,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 const int cnt = nr - c0 < kWave ? nr - c0 : kWave;
                 if (lane < cnt) Su[lane] = Li[c0 + lane] & kIdMask;
                 wave_sync();
-                distances<false>(a.base, d, Su, cnt, qv, a.metric, inv_qn, Sdist);
+                distances<false, false>(a.base, d, Su, cnt, qv, a.metric, inv_qn, Sdist);
                 wave_sync();
                 if (lane < cnt) Ld[c0 + lane] = Sdist[lane];
                 wave_sync();

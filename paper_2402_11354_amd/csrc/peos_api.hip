@@ -5,8 +5,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <mutex>
 #include <new>
+#include <vector>
 
 #include "../../include/peos.h"
 #include "k_edge_build.hpp"
@@ -20,6 +22,7 @@ struct peos_graph {
 };
 
 struct peos_index {
+    const int32_t* perm;     // dimension permutation of the test, or null
     const float* base;
     const uint16_t* base16;  // bfloat16 traversal copy inside index_mem, or null
     const int32_t* graph;
@@ -327,6 +330,18 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
                       size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
                       peos_index** out)
 {
+    return peos_build_tables_permuted(base, n, d, graph, R, entry, L, m, dirs_a, dirs_b, metric,
+                                      flags, nullptr, index_mem, index_bytes, ws, ws_bytes, stream,
+                                      out);
+}
+
+int peos_build_tables_permuted(const float* base, int64_t n, int32_t d, const int32_t* graph,
+                               int32_t R, int32_t entry, int32_t L, int32_t m,
+                               const float* dirs_a, const float* dirs_b, int32_t metric,
+                               int32_t flags, const int32_t* perm, void* index_mem,
+                               size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
+                               peos_index** out)
+{
     if (!out) return fail(PEOS_EINVAL, "null output handle");
     *out = nullptr;
     size_t need = 0, need_ws = 0;
@@ -363,6 +378,7 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
     a.m = m;
     a.metric = metric;
     a.half_scalars = (flags & PEOS_FLAG_FP16) ? 1 : 0;
+    a.perm = perm;
     size_t lds = sizeof(float) * (size_t)(5 * d + 4 * L) + sizeof(int32_t) * (size_t)R;
     hipLaunchKernelGGL(peos::k_edge_build, dim3((unsigned)n), dim3(64), lds, s, a);
     HIP_TRY(hipGetLastError());
@@ -378,6 +394,7 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
     if (herr) return fail(PEOS_EGRAPH, "graph has an id out of range, a self loop or a repeated neighbour");
     peos_index* ix = new (std::nothrow) peos_index;
     if (!ix) return fail(PEOS_EINVAL, "out of host memory");
+    ix->perm = perm;
     ix->base = base;
     ix->base16 = (flags & PEOS_FLAG_BF16_BASE) ? (const uint16_t*)((uint8_t*)index_mem + bf16_off) : nullptr;
     ix->bf16_off = bf16_off;
@@ -441,6 +458,7 @@ int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, fl
     a.L = ix->L;
     a.m = ix->m;
     a.half_out = (ix->flags & PEOS_FLAG_FP16) ? 1 : 0;
+    a.perm = ix->perm;
     const int64_t blocks = (nq + 15) / 16;
     hipLaunchKernelGGL(peos::k_query_table, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, a);
     HIP_TRY(hipGetLastError());
@@ -617,6 +635,62 @@ int peos_search(const peos_index* ix, const float* queries, int64_t nq, const in
     if (rc) return rc;
     return search_impl(ix, queries, tables, qnorms, nq, k, ef, k_all, ef_all, kstride, pool, eps,
                        mode, ids, dists, stats, ws, ws_bytes, (hipStream_t)stream);
+}
+
+constexpr int kEnergyBlocks = 2048;
+
+int peos_dimension_permutation_ws_bytes(int32_t d, size_t* ws_bytes)
+{
+    if (!ws_bytes || d < 1) return fail(PEOS_EINVAL, "bad arguments");
+    *ws_bytes = (size_t)kEnergyBlocks * (size_t)d * sizeof(float);
+    return PEOS_OK;
+}
+
+int peos_dimension_permutation(const float* base, int64_t n, int32_t d, const int32_t* graph,
+                               int32_t R, int32_t L, int32_t* perm, void* ws, size_t ws_bytes,
+                               void* stream)
+{
+    if (!base || !graph || !perm || !ws) return fail(PEOS_EINVAL, "null pointer");
+    if (n < 1 || d < 1 || R < 1 || L < 1 || d % L) return fail(PEOS_EINVAL, "n=%lld d=%d R=%d L=%d", (long long)n, d, R, L);
+    size_t need = 0;
+    peos_dimension_permutation_ws_bytes(d, &need);
+    if (ws_bytes < need) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %zu", ws_bytes, need);
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int blocks = (int)(n < kEnergyBlocks ? n : kEnergyBlocks);
+    hipLaunchKernelGGL(peos::k_edge_energy, dim3(blocks), dim3(256), 0, s, base, graph, n, d, R,
+                       (float*)ws);
+    HIP_TRY(hipGetLastError());
+    std::vector<float> part((size_t)blocks * d);
+    HIP_TRY(hipMemcpyAsync(part.data(), ws, part.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    // per-dimension energy (the common 1/|E| factor changes no decision)
+    std::vector<double> avg((size_t)d, 0.0);
+    for (int b = 0; b < blocks; ++b)
+        for (int j = 0; j < d; ++j) avg[j] += (double)part[(size_t)b * d + j];
+    // ascending energy, ties by index; d/L rounds of L, each dimension to
+    // the subspace with the largest running sum not yet served this round
+    std::vector<int> order((size_t)d);
+    for (int j = 0; j < d; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return avg[x] < avg[y]; });
+    const int dp = d / L;
+    std::vector<double> sum((size_t)L, 0.0);
+    std::vector<int> fill((size_t)L, 0);
+    for (int round = 0; round < dp; ++round) {
+        std::vector<char> served((size_t)L, 0);
+        for (int j = 0; j < L; ++j) {
+            const int dim = order[(size_t)round * L + j];
+            int best = -1;
+            for (int i = 0; i < L; ++i)
+                if (!served[i] && (best < 0 || sum[i] > sum[best])) best = i;
+            served[best] = 1;
+            sum[best] += avg[dim];
+            perm[(size_t)best * dp + fill[best]++] = dim;
+        }
+    }
+    return PEOS_OK;
 }
 
 int peos_graph_create(const peos_index* ix, const float* queries, int64_t nq, const int32_t* k,

@@ -402,3 +402,78 @@ def test_per_query_bounded_queue_matches_oracle(angular):
     assert not res["bad"], res["bad"][:5]
     assert res["checked"] >= 0.8 * len(ids)
     assert np.all(st[:, 11] & P.PEOS_STATUS_POOL_FULL == 0)
+
+
+def test_search_on_graph_with_random_long_edges():
+    """A graph with random long-range edges in its free slots (the GIST-like
+    workload's graph): uneven degrees, far neighbours."""
+    w = W.TINY.with_sizes(n=2500, nq=80)
+    w = W.Workload(w.name, w.n, w.nq, w.d, w.R, w.cand, w.L, w.m, w.metric, w.family, w.eps, w.k,
+                   w.ef, w.seed, rand_edges=6)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.graph_for(w, x)
+    A, B = W.directions_for(w)
+    idx = P.peos_build_tables(T(x), T(g), entry, w.L, w.m, T(A), T(B), w.metric)
+    for pool in (0, w.ef):
+        ids, d, st = P.search(idx, T(q), w.k, w.ef, eps=w.eps, pool=pool)
+        torch.cuda.synchronize()
+        ref = O.search(x, g, entry, q, w.k, w.ef, w.L, w.m, A, B, w.metric, w.eps, pool=pool,
+                       precision=32)
+        res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, w.k)
+        assert not res["bad"], res["bad"][:5]
+        assert res["checked"] >= 0.8 * len(q)
+
+
+# ---------------------------------------------------------------------------
+# optional dimension permutation
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def aniso():
+    """Strongly anisotropic coordinates (per-dimension scales exp(N(0, 1))),
+    where the permutation matters and energies are well separated."""
+    rng = np.random.default_rng(21)
+    n, d = 3000, 64
+    x = (rng.normal(size=(n, d)) * np.exp(rng.normal(0, 1.0, size=d))).astype(np.float32)
+    q = (rng.normal(size=(80, d)) * np.exp(rng.normal(0, 1.0, size=d))).astype(np.float32)
+    g, entry = W.build_graph(x, 16, 32)
+    A, B = W.make_directions(8, 16, d, 77)
+    return x, q, g, entry, A, B
+
+
+def test_dimension_permutation_matches_oracle(aniso):
+    x, q, g, entry, A, B = aniso
+    perm = P.peos_dimension_permutation(T(x), T(g), 8)
+    ref, _ = O.dimension_permutation(x, g, 8)
+    assert np.array_equal(perm, ref)
+
+
+@pytest.mark.parametrize("pool", [0, 32])
+def test_permuted_index_matches_oracle(aniso, pool):
+    x, q, g, entry, A, B = aniso
+    L, m = 8, 16
+    perm, _ = O.dimension_permutation(x, g, L)
+    idx = P.peos_build_tables(T(x), T(g), entry, L, m, T(A), T(B), W.L2, perm=T(perm))
+    # records: codes of the permuted edges, bit-exact
+    lay = idx.layout()
+    mem = idx._keep[-1].cpu().numpy().reshape(lay.n, lay.node_stride)
+    cb = lay.code_bytes
+    R = g.shape[1]
+    codes = mem[:, lay.codes_offset:lay.codes_offset + cb * R].reshape(lay.n, R, cb)[..., :L + 1]
+    rc, _, _ = O.build_tables(x[:, perm], g, L, m, A, B)
+    valid = g >= 0
+    assert np.array_equal(codes[valid], rc[valid])
+    # tables on the permuted query
+    tables = torch.empty((len(q), L + 1, m), dtype=torch.float32, device=dev())
+    norms = torch.empty(len(q), dtype=torch.float32, device=dev())
+    P.peos_query_tables(idx, T(q), tables, norms)
+    torch.cuda.synchronize()
+    ref_t = np.stack([O.query_table(q[i][perm], L, m, A, B) for i in range(len(q))])
+    np.testing.assert_allclose(tables.cpu().numpy(), ref_t, rtol=0, atol=2e-5)
+    # search
+    ids, d, st = P.search(idx, T(q), 10, 32, eps=0.1, pool=pool)
+    torch.cuda.synchronize()
+    ref = O.search(x, g, entry, q, 10, 32, L, m, A, B, W.L2, 0.1, pool=pool, precision=32,
+                   perm=perm)
+    res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, 10)
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(q)

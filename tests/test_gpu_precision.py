@@ -208,3 +208,27 @@ def test_half_form_against_oracle(which, flags, request):
     rec = lambda I: np.mean([len(set(I[i]) & set(gt[i])) / w.k for i in range(len(I))])
     print(f"[gpu] {which} flags={flags}: recall {rec(ids):.4f} vs full {rec(full[0]):.4f}")
     assert rec(ids) >= rec(full[0]) - 0.005
+
+
+@pytest.fixture(scope="module")
+def wide():
+    print("[gpu] precision: long-vector workload (d = 768)", flush=True)
+    return Case(W.Workload("wide_lowrank_3k_d768", 3000, 60, 768, 16, 32, 16, 16, W.L2,
+                           "gmm256lowrank", 0.1, 10, 32, 1008))
+
+
+@pytest.mark.parametrize("flags", [0, P.PEOS_FLAG_BF16_BASE])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_long_vectors_match_oracle(wide, flags, pool_mul):
+    """d > 512 with the bfloat16 traversal takes the wide gather (16 lanes x
+    16 chunks per vector) in the kernels built for L > 8: same canonical
+    order, exact parity (and the fp32 path on the same data)."""
+    w = wide.w
+    ids, d, st = wide.run(flags, pool=pool_mul * w.ef)
+    ref = wide.oracle(flags, pool=pool_mul * w.ef) if flags else O.search(
+        wide.x, wide.g, wide.entry, wide.q, w.k, w.ef, w.L, w.m, wide.A, wide.B, w.metric, w.eps,
+        pool=pool_mul * w.ef, precision=32)
+    res = compare(ids, d, st, ref, w.k)
+    print(f"[gpu] wide flags={flags} pool={pool_mul * w.ef}: checked={res['checked']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)

@@ -41,6 +41,7 @@ class Workload:
     k: int
     ef: int
     seed: int       # base seed; queries use seed+1000, directions seed+2000
+    rand_edges: int = 0  # random long-range edges per node added to the graph
 
     def with_sizes(self, n=None, nq=None):
         return dataclasses.replace(self, n=self.n if n is None else n,
@@ -50,7 +51,7 @@ class Workload:
 # The five workloads.  Seeds follow 1000+c / 2000+c / 3000+c for workload c.
 TINY = Workload("tiny_gmm_2k_d32", 2000, 100, 32, 16, 32, 4, 16, L2, "gmm10", 0.1, 10, 32, 1001)
 SIFT_LIKE = Workload("sift_like_1m_d128", 1_000_000, 10_000, 128, 32, 64, 8, 16, L2, "expint100", 0.1, 10, 64, 1002)
-GIST_LIKE = Workload("gist_like_1m_d960", 1_000_000, 1_000, 960, 32, 64, 16, 16, L2, "gmm256lowrank", 0.1, 10, 128, 1003)
+GIST_LIKE = Workload("gist_like_1m_d960", 1_000_000, 1_000, 960, 32, 64, 16, 16, L2, "gmm256lowrank", 0.1, 10, 128, 1003, rand_edges=8)
 DEEP_LIKE = Workload("deep_like_10m_d96", 10_000_000, 100_000, 96, 32, 64, 8, 16, ANGULAR, "sphere1000", 0.1, 10, 64, 1004)
 SERVING = Workload("serving_1m_d256", 1_000_000, 10_000, 256, 32, 64, 8, 16, ANGULAR, "sphere500", 0.1, 10, 64, 1005)
 
@@ -189,3 +190,10 @@ def query_params(w: Workload, nq: int, seed: int = 0):
 
 
 from .graph import build_graph, ground_truth, medoid  # noqa: E402,F401
+
+
+def graph_for(w: Workload, base: np.ndarray, device="cpu", log=None):
+    """The workload's graph: pruned kNN graph of degree R from `cand`
+    candidates, plus its random long-range edges."""
+    return build_graph(base, w.R, w.cand, device=device, log=log, rand_edges=w.rand_edges,
+                       seed=w.seed)

@@ -321,11 +321,29 @@ def medoid(x: torch.Tensor, exact_limit: int = 20000) -> int:
 EXACT_KNN_LIMIT = 2_000_000
 
 
+def _random_edges(g: torch.Tensor, count: int, seed: int):
+    """Fill up to `count` free slots of every row with distinct random ids
+    (not the row itself, not already in the row): long-range shortcuts that
+    keep a pruned kNN graph navigable when its clusters are tight."""
+    n, R = g.shape
+    gen = torch.Generator(device="cpu").manual_seed(seed)
+    for _ in range(count):
+        free = (g < 0).any(1)
+        pos = torch.argmax((g < 0).to(torch.int8), dim=1)  # first free slot
+        r = torch.randint(0, n, (n,), generator=gen).to(g.device)
+        rows = torch.arange(n, device=g.device)
+        ok = free & (r != rows) & ~(g == r[:, None]).any(1)
+        g[rows[ok], pos[ok]] = r[ok]
+    return g
+
+
 def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool = True,
-                log=None):
+                log=None, rand_edges: int = 0, seed: int = 0):
     """Pruned exact-kNN graph (module docstring).  Returns (graph int32 n x R
     padded with -1, entry id).  `log` receives progress lines.  Above
-    EXACT_KNN_LIMIT rows the candidates come from knn_ivf (approximate)."""
+    EXACT_KNN_LIMIT rows the candidates come from knn_ivf (approximate).
+    rand_edges > 0 adds that many random long-range edges per node (in free
+    slots) before the connectivity repair."""
     device, dt = _dev_dtype(device)
     x = torch.as_tensor(base).to(device=device, dtype=dt)
     if x.shape[0] > EXACT_KNN_LIMIT:
@@ -346,6 +364,8 @@ def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool
         gi = torch.where(small[:, None], ci[:, :R], pi)
         gd = torch.where(small[:, None], cd[:, :R], pd)
     entry = medoid(x)
+    if rand_edges > 0:
+        gi = _random_edges(gi, rand_edges, seed)
     kc, _ = knn(x, x, cand, exclude_self=True) if not reverse else (ci, cd)
     if log:
         log("connectivity")
