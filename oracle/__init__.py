@@ -29,6 +29,7 @@ L2 = 0
 ANGULAR = 1
 MODE_PEOS = 0
 MODE_EXHAUSTIVE = 1
+MODE_SIMHASH = 2
 
 COUNTERS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0",
             "test_h", "test_zero", "passes", "ndist", "inserted")
@@ -73,9 +74,12 @@ def _load():
         lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, i32, P]
         lib.oracle_test_edge.restype = i32
         lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
-                                      i32, i32, f64, i32, f64, i32, i32, P, i32, P, P, P, P, P, P]
+                                      i32, i32, f64, i32, f64, i32, i32, P, P, i32, i32, P, P, P, P,
+                                      P, P]
         lib.oracle_search.restype = i32
         lib.oracle_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P]
+        lib.oracle_simhash_bits.argtypes = [P, i32, P, i32, P]
+        lib.oracle_simhash_bits.restype = None
         lib.oracle_dimension_permutation.restype = i32
         lib.oracle_round_half.argtypes = [f64]
         lib.oracle_round_half.restype = f64
@@ -182,7 +186,8 @@ def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps, lowp=0):
 # Alg. 1
 # ---------------------------------------------------------------------------
 def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MODE_PEOS,
-           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0, perm=None):
+           tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0, perm=None,
+           simhash=None):
     """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
     pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
     0 < pool <= ef = the HNSW stopping rule, pool < 0 = |pool| x each
@@ -195,6 +200,7 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     full base (see routing_test_lowp and oracle_search in peos_oracle.c).
     perm: optional dimension permutation (d ints) of the test: edge records
     and tables on permuted coordinates, distances on the original ones.
+    simhash: (nb, d) sign-projection vectors, required by MODE_SIMHASH.
     Returns dict(ids (nq, kstride) int64, dist (as decided), dist64 float64,
     counters (nq, 11) int64, fragile (nq,) int32 flag words, status (nq,) int32)."""
     if precision not in (32, 64):
@@ -218,14 +224,25 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     perm_arr = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
     if perm_arr is not None and sorted(perm_arr.tolist()) != list(range(d)):
         raise ValueError("perm must be a permutation of range(d)")
+    sh = None if simhash is None else _f32(simhash)
+    nb = 0 if sh is None else sh.shape[0]
     rc = _load().oracle_search(_p(base), n, d, _p(graph), graph.shape[1], int(entry), L, m, _p(A),
                                _p(B), metric, _p(queries), nq, _p(karr), _p(efarr), ks,
                                int(pool), float(eps), mode, float(tau), 1 if precision == 32 else 0,
-                               int(lowp), _p(perm_arr), nt, _p(ids), _p(dist), _p(dist64),
-                               _p(cnt), _p(frag), _p(status))
+                               int(lowp), _p(perm_arr), _p(sh), nb, nt, _p(ids), _p(dist),
+                               _p(dist64), _p(cnt), _p(frag), _p(status))
     if rc:
         raise ValueError("bad search arguments")
     return dict(ids=ids, dist=dist, dist64=dist64, counters=cnt, fragile=frag, status=status)
+
+
+def simhash_bits(v, C):
+    """Sign bits [v . c_i >= 0] of the rows of C, as a uint64 word array."""
+    v, C = _f32(v), _f32(C)
+    nb = C.shape[0]
+    bits = np.zeros((nb + 63) // 64, np.uint64)
+    _load().oracle_simhash_bits(_p(v), v.shape[0], _p(C), nb, _p(bits))
+    return bits
 
 
 def dimension_permutation(base, graph, L):

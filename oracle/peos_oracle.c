@@ -32,6 +32,7 @@
 #define OR_ANGULAR 1
 #define OR_MODE_PEOS 0
 #define OR_MODE_EXHAUSTIVE 1
+#define OR_MODE_SIMHASH 2
 
 /* counters, per query */
 enum {
@@ -519,6 +520,62 @@ static int routing_test_lowp(const test_params* tp, const edge_rec* er, const do
 }
 
 /* ------------------------------------------------------------------ */
+/* SimHash test (Sec. 3, "SimHash Test", with the residual-edge remedy) */
+/* ------------------------------------------------------------------ */
+/*
+ * Sign bits of nb random projections, decided in single precision with one
+ * fixed order (an fmaf chain over the coordinates in increasing order):
+ * bit i = [v . c_i >= 0].  bits receives (nb + 63) / 64 words.
+ */
+static void simhash_bits_fp32(const float* v, int d, const float* C, int nb, uint64_t* bits)
+{
+    for (int w = 0; w < (nb + 63) / 64; ++w) bits[w] = 0;
+    for (int i = 0; i < nb; ++i) {
+        float p = 0.0f;
+        for (int k = 0; k < d; ++k) p = fmaf(v[k], C[(size_t)i * d + k], p);
+        if (p >= 0.0f) bits[i >> 6] |= 1ull << (i & 63);
+    }
+}
+
+/*
+ * The test on e = u - v: A_r as in the PEOs test; A_r >= 1 fails, A_r <= 0
+ * passes; otherwise the angle threshold is theta_r = arccos(A_r) (d_u < delta
+ * iff the angle of e and q is below it), the collision count of nb sign
+ * projections of e and q is Binomial(nb, 1 - theta/pi), and Hoeffding's
+ * inequality gives the threshold that a boundary edge (theta = theta_r)
+ * exceeds with probability >= 1 - eps:
+ *   pass iff #Col >= nb (1 - theta_r / pi) - sqrt(nb ln(1/eps) / 2).
+ */
+static int routing_test_simhash(const test_params* tp, double norm_e, int col, int nb,
+                                double num, double qnorm, double eps, int* kind, int* flags,
+                                int v_is_p)
+{
+    const double tau = tp->tau;
+    const int exact0 = v_is_p && tp->metric == OR_ANGULAR;
+    if (norm_e == 0.0) {
+        *kind = 0;
+        if (!exact0 && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
+        return num < 0.0;
+    }
+    const double A = num / (qnorm * norm_e);
+    if (fabs(A - 1.0) < tau) *flags |= F_A1;
+    if (!exact0 && fabs(A) < tau) *flags |= F_A0;
+    if (A >= 1.0) { *kind = 1; return 0; }
+    if (A <= 0.0) { *kind = 2; return 1; }
+    *kind = 3;
+    const double pi = 3.14159265358979323846;
+    const double T = nb * (1.0 - acos(A) / pi) - sqrt(nb * log(1.0 / eps) / 2.0);
+    if (fabs((double)col - T) < 1e-3) *flags |= F_HT;
+    return (double)col >= T;
+}
+
+/* Public: sign bits (for the pins). */
+void oracle_simhash_bits(const float* v, int d, const float* C, int nb, uint64_t* bits)
+{
+    simhash_bits_fp32(v, d, C, nb, bits);
+}
+
+/* ------------------------------------------------------------------ */
 /* Optional dimension permutation (appendix "Dimension Permutation")   */
 /* ------------------------------------------------------------------ */
 /*
@@ -679,6 +736,8 @@ typedef struct {
     int64_t n, q0, q1;
     int d, R, L, m, metric, mode, entry, kstride, pool, fp32, lowp;
     const int32_t* perm; /* dimension permutation of the test, or NULL */
+    const float* simhash; /* nb x d sign-projection vectors (SimHash mode) */
+    int nb;
     double eps, tau;
     int64_t* out_ids;
     double* out_dist;
@@ -745,6 +804,8 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         qperm = (float*)malloc(sizeof(float) * (size_t)d);
         for (int k = 0; k < d; ++k) qperm[k] = q[j->perm[k]];
     }
+    uint64_t qsig[4] = {0, 0, 0, 0};
+    if (j->mode == OR_MODE_SIMHASH) simhash_bits_fp32(q, d, j->simhash, j->nb, qsig);
     if (j->mode == OR_MODE_PEOS) {
         oracle_query_table(qperm ? qperm : q, d, j->L, j->m, j->A, j->B, table);
         if (j->lowp & LP_FP16)
@@ -776,7 +837,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         const double delta = full ? R[efq - 1].dist : INFINITY;
         const int32_t p = full ? R[efq - 1].id : -1;
         double vq = 0.0, r = 0.0;
-        if (full && j->mode == OR_MODE_PEOS) {
+        if (full && j->mode != OR_MODE_EXHAUSTIVE) {
             const float* xp = j->base + (size_t)p * d;
             vq = dot64(xv, q, d);
             if (j->metric == OR_L2) r = 0.5 * dot64(xp, xp, d) - dot64(xp, q, d);
@@ -790,7 +851,32 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             if (visited[u]) { cnt[C_VISITED_SKIPS]++; continue; }
             const float* xu = j->base + (size_t)u * d;
             int pass = 1;
-            if (full && j->mode == OR_MODE_PEOS) {
+            if (full && j->mode == OR_MODE_SIMHASH) {
+                /* e = u - v, |e| and g_e in double; signature in single */
+                double ne2 = 0.0, nu2 = 0.0, nv2 = 0.0;
+                float* e = fw1 + d;
+                for (int k = 0; k < d; ++k) {
+                    e[k] = xu[k] - xv[k];
+                    const double t = (double)xu[k] - (double)xv[k];
+                    ne2 += t * t;
+                    nu2 += (double)xu[k] * xu[k];
+                    nv2 += (double)xv[k] * xv[k];
+                }
+                uint64_t es[4];
+                simhash_bits_fp32(e, d, j->simhash, j->nb, es);
+                int diff = 0;
+                for (int w = 0; w < (j->nb + 63) / 64; ++w) diff += __builtin_popcountll(es[w] ^ qsig[w]);
+                double num;
+                if (j->metric == OR_L2) num = 0.5 * nu2 - r - vq;
+                else num = -r - vq;
+                (void)nv2;
+                int kind;
+                pass = routing_test_simhash(tp, sqrt(ne2), j->nb - diff, j->nb, num, qnorm, j->eps,
+                                            &kind, &flags, v == p);
+                cnt[C_TESTS]++;
+                cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
+                if (pass) cnt[C_PASSES]++;
+            } else if (full && j->mode == OR_MODE_PEOS) {
                 if (j->perm) {
                     float* xvp = fw1 + d;
                     float* xup = fw2 + d;
@@ -942,20 +1028,23 @@ static void* search_worker(void* arg)
  * final result list with full-precision single-precision distances before
  * the first k are taken.  perm (optional, d entries): the dimension
  * permutation of the test -- edge records and the table are taken on the
- * permuted coordinates, distances on the original ones.
+ * permuted coordinates, distances on the original ones.  mode
+ * OR_MODE_SIMHASH takes the SimHash test (routing_test_simhash) with the nb
+ * sign-projection vectors simhash (nb x d) instead of the PEOs test.
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,
                   int L, int m, const float* A, const float* B, int metric, const float* queries,
                   int64_t nq, const int32_t* k, const int32_t* ef, int kstride, int pool,
                   double eps, int mode, double tau, int fp32, int lowp, const int32_t* perm,
-                  int nthreads, int64_t* out_ids,
+                  const float* simhash, int nb, int nthreads, int64_t* out_ids,
                   double* out_dist, double* out_dist64, int64_t* counters, int32_t* fragile,
                   int32_t* status)
 {
     if (n <= 0 || d <= 0 || R <= 0 || entry < 0 || entry >= n) return -1;
     if (mode == OR_MODE_PEOS && (L <= 0 || d % L || L > 255 || m < 2 || 2 * m > 256)) return -1;
-    if (mode == OR_MODE_PEOS && !(eps > 0.0 && eps <= 0.5)) return -1;
+    if (mode != OR_MODE_EXHAUSTIVE && !(eps > 0.0 && eps <= 0.5)) return -1;
+    if (mode == OR_MODE_SIMHASH && (!simhash || nb < 1 || nb > 256)) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     if (nthreads > nq) nthreads = (int)(nq > 0 ? nq : 1);
@@ -964,8 +1053,8 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
                                nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
-                               pool, fp32 || lowp, lowp, perm, eps, tau, out_ids, out_dist,
-                               out_dist64, counters, fragile, status};
+                               pool, fp32 || lowp, lowp, perm, simhash, nb, eps, tau, out_ids,
+                               out_dist, out_dist64, counters, fragile, status};
         pthread_create(&th[t], NULL, search_worker, &jobs[t]);
     }
     for (int t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);

@@ -477,3 +477,22 @@ def test_permuted_index_matches_oracle(aniso, pool):
     res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, 10)
     assert not res["bad"], res["bad"][:5]
     assert res["checked"] >= 0.8 * len(q)
+
+
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_rceos_is_the_L1_case(pool_mul):
+    """The reverse-CEOs test is PEOs with L = 1 (one subspace: w_reg = 1,
+    w_res = 0, a single extreme-order code): same kernel, exact parity."""
+    w = W.TINY.with_sizes(n=2000, nq=80)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.make_directions(1, 64, w.d, 31)
+    idx = P.peos_build_tables(T(x), T(g), entry, 1, 64, T(A), T(B), w.metric)
+    ids, d, st = P.search(idx, T(q), w.k, w.ef, eps=w.eps, pool=pool_mul * w.ef)
+    torch.cuda.synchronize()
+    ref = O.search(x, g, entry, q, w.k, w.ef, 1, 64, A, B, w.metric, w.eps,
+                   pool=pool_mul * w.ef, precision=32)
+    res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, w.k)
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(q)
+    assert st.cpu().numpy()[:, 6].sum() > 0  # H-vs-T tests did run
