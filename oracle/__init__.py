@@ -71,7 +71,7 @@ def _load():
         lib.oracle_build_tables.restype = i32
         lib.oracle_query_table.argtypes = [P, i32, i32, i32, P, P, P]
         lib.oracle_query_table.restype = None
-        lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, i32, P]
+        lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, i32, P, i32, P]
         lib.oracle_test_edge.restype = i32
         lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
                                       i32, i32, f64, i32, f64, i32, i32, P, P, i32, i32, P, P, P, P,
@@ -171,14 +171,17 @@ def query_table(q, L, m, A, B):
     return out
 
 
-def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps, lowp=0):
+def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps, lowp=0, simhash=None):
     """One routing test of edge (v, u) against furthest result p.
     Returns (pass, A_r, H, T, kind) with kind 0 zero edge / 1 A>=1 / 2 A<=0 / 3 H-vs-T.
-    lowp = LP_FP16: the precision-form test (half-rounded scalars and table)."""
+    lowp = LP_FP16: the precision-form test (half-rounded scalars and table).
+    simhash (nb, d): the SimHash test; H is then the collision count."""
     xv, xu, xp, q, A, B = map(_f32, (xv, xu, xp, q, A, B))
     out = np.zeros(4, np.float64)
+    sh = None if simhash is None else _f32(simhash)
     ok = _load().oracle_test_edge(_p(xv), _p(xu), _p(xp), _p(q), q.shape[0], L, m, _p(A), _p(B),
-                                  metric, float(eps), int(lowp), _p(out))
+                                  metric, float(eps), int(lowp), _p(sh),
+                                  0 if sh is None else sh.shape[0], _p(out))
     return bool(ok), out[0], out[1], out[2], int(out[3])
 
 

@@ -1063,10 +1063,11 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
 
 /* Public: one routing test, for the pins.  Returns pass (1/0); out = {A, H, T, kind}.
  * lowp & LP_FP16: the precision-form test (routing_test_lowp) with dist_v and
- * delta the single-precision distances of v and p. */
+ * delta the single-precision distances of v and p.  simhash (nb x d): the
+ * SimHash test instead; H is then the collision count. */
 int oracle_test_edge(const float* xv, const float* xu, const float* xp, const float* q, int d,
                      int L, int m, const float* A, const float* B, int metric, double eps,
-                     int lowp, double* out)
+                     int lowp, const float* simhash, int nb, double* out)
 {
     float* fw1 = (float*)malloc(sizeof(float) * d);
     float* fw2 = (float*)malloc(sizeof(float) * d);
@@ -1083,7 +1084,20 @@ int oracle_test_edge(const float* xv, const float* xu, const float* xp, const fl
     double a, h, t;
     int kind, flags = 0;
     int pass;
-    if (lowp & LP_FP16) {
+    if (simhash) {
+        float* e = (float*)malloc(sizeof(float) * d);
+        for (int k = 0; k < d; ++k) e[k] = xu[k] - xv[k];
+        uint64_t es[4], qs[4];
+        simhash_bits_fp32(e, d, simhash, nb, es);
+        simhash_bits_fp32(q, d, simhash, nb, qs);
+        int diff = 0;
+        for (int w = 0; w < (nb + 63) / 64; ++w) diff += __builtin_popcountll(es[w] ^ qs[w]);
+        free(e);
+        a = er.norm_e > 0.0 ? num / (qnorm * er.norm_e) : NAN;
+        h = nb - diff;
+        t = NAN;
+        pass = routing_test_simhash(&tp, er.norm_e, nb - diff, nb, num, qnorm, eps, &kind, &flags, 0);
+    } else if (lowp & LP_FP16) {
         for (int i = 0; i < (L + 1) * m; ++i) table[i] = oracle_round_half(table[i]);
         const float iq = 1.0f / qnorm32(q, d);
         const double dv = dist32(xv, q, d, metric, iq, 0), dp = dist32(xp, q, d, metric, iq, 0);

@@ -905,3 +905,72 @@ def test_permuted_test_equals_permuted_directions():
     assert same.mean() > 0.8
     assert np.array_equal(a["ids"][same], b["ids"][same])
     assert np.array_equal(a["counters"][same], b["counters"][same])
+
+
+# ---------------------------------------------------------------------------
+# SimHash test (Sec. 3 "SimHash Test", residual-edge remedy)
+# ---------------------------------------------------------------------------
+def test_simhash_collision_rate_is_one_minus_angle_over_pi():
+    """The lemma: a random Gaussian direction separates two vectors at angle
+    theta with probability theta/pi."""
+    rng = np.random.default_rng(2)
+    d = 48
+    u = rng.normal(size=d)
+    for theta in (0.3, 1.0, 2.0):
+        w = rng.normal(size=d)
+        w -= w.dot(u) / u.dot(u) * u
+        q = np.cos(theta) * u / np.linalg.norm(u) + np.sin(theta) * w / np.linalg.norm(w)
+        cols = []
+        for rep in range(300):
+            C = rng.normal(size=(64, d)).astype(np.float32)
+            bu = O.simhash_bits(u, C)[0]
+            bq = O.simhash_bits(q, C)[0]
+            cols.append(64 - bin(int(bu) ^ int(bq)).count("1"))
+        frac = np.mean(cols) / 64
+        assert abs(frac - (1 - theta / np.pi)) < 4 * np.sqrt(0.25 / (64 * 300))
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.2])
+def test_simhash_test_guarantee(eps):
+    """Edges with cos(e, q) above A_r (so d_u < delta) pass with probability
+    at least 1 - eps (Hoeffding's bound is conservative), and edges at
+    cos(e, q) far below A_r mostly fail."""
+    rng = np.random.default_rng(8)
+    d, nb = 32, 64
+    A_, B_ = W.make_directions(4, 16, d, 5)
+    good = bad = ngood = nbad = 0
+    for _ in range(3000):
+        C = rng.normal(size=(nb, d)).astype(np.float32)
+        xv, xp, q = (rng.normal(size=d).astype(np.float32) for _ in range(3))
+        xu = (xv + rng.normal(size=d)).astype(np.float32)
+        p, A, col, T, kind = O.test_edge(xv, xu, xp, q, 4, 16, A_, B_, W.L2, eps, simhash=C)
+        if kind != 3:
+            continue
+        e = xu.astype(np.float64) - xv
+        cos = e.dot(q) / np.linalg.norm(e) / np.linalg.norm(q)
+        if cos > A:
+            ngood += 1
+            good += p
+        elif cos < A - 0.5:
+            nbad += 1
+            bad += p
+    assert ngood > 60 and good / ngood >= 1 - eps
+    assert nbad > 60 and bad / nbad < 0.5
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+def test_simhash_vanishing_eps_reproduces_exhaustive(metric):
+    """As eps -> 0 the Hoeffding margin exceeds nb, only the exact A_r >= 1
+    rule prunes, and the search returns the exhaustive search's results."""
+    w = W.TINY.with_sizes(n=1500, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    C = np.random.default_rng(3).normal(size=(64, w.d)).astype(np.float32)
+    a = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 1e-300, mode=O.MODE_SIMHASH,
+                 simhash=C)
+    b = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, mode=O.MODE_EXHAUSTIVE)
+    assert np.array_equal(a["ids"], b["ids"])
+    assert a["counters"][:, 9].sum() <= b["counters"][:, 9].sum()
