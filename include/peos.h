@@ -53,6 +53,14 @@ extern "C" {
  * i.e. Alg. 1 with RoutingTest returning true. */
 #define PEOS_MODE_PEOS 0
 #define PEOS_MODE_EXHAUSTIVE 1
+/* SIMHASH: the SimHash test of Sec. 3 ("SimHash Test") on the residual edge
+ * e = u - v instead of the PEOs test: A_r as in step (6); A_r >= 1 fails,
+ * A_r <= 0 passes; otherwise u passes iff the number of the 64 sign
+ * projections on which e and q agree is at least
+ * 64 (1 - arccos(A_r)/pi) - sqrt(64 ln(1/eps) / 2) (Hoeffding's bound on the
+ * Binomial collision count at the boundary angle).  Needs an index built with
+ * PEOS_FLAG_SIMHASH. */
+#define PEOS_MODE_SIMHASH 2
 /* index flags: the precision form (storage only; arithmetic stays single
  * precision).
  * PEOS_FLAG_BF16_BASE: index_mem also holds a bfloat16 copy of the base
@@ -66,6 +74,10 @@ extern "C" {
  *   (dist_v - delta)/|e| (angular), the same quantity as the full form's. */
 #define PEOS_FLAG_BF16_BASE 1
 #define PEOS_FLAG_FP16 2
+/* PEOS_FLAG_SIMHASH: the records also hold, per edge, the 64 sign bits
+ * [e . c_i >= 0] of the residual edge against the 64 vectors of
+ * peos_build_options.simhash_dirs (for PEOS_MODE_SIMHASH). */
+#define PEOS_FLAG_SIMHASH 4
 
 /* per-query status bits written to stats[.. + PEOS_STAT_STATUS] */
 #define PEOS_STATUS_ZERO_QUERY 1    /* |q| = 0 or not finite: outputs padded  */
@@ -111,6 +123,8 @@ typedef struct {
     int64_t code_bytes;     /* bytes of codes per edge */
     int64_t scalar_bytes;   /* bytes of scalars per edge (16, or 8 with halves) */
     int64_t bf16_offset;    /* bytes, within index_mem; 0 without the copy */
+    int64_t simhash_offset; /* bytes, within a record: 8 bytes per edge (bit i =
+                               sign i), 0 without PEOS_FLAG_SIMHASH */
 } peos_layout;
 
 /*
@@ -170,20 +184,28 @@ int peos_dimension_permutation(const float* base, int64_t n, int32_t d, const in
                                int32_t R, int32_t L, int32_t* perm, void* ws, size_t ws_bytes,
                                void* stream);
 /*
- * peos_build_tables_permuted -- peos_build_tables with the dimension
- * permutation perm (device, d int32, a permutation of 0..d-1; kept by the
- * index, must stay valid until peos_free): steps (1)-(3) and the projection
- * tables of step (5) take coordinate k of every vector from original
- * coordinate perm[k]; distances and everything else use the original
- * coordinates (the permutation changes neither the graph nor the guarantee).
- * perm = NULL is peos_build_tables.
+ * peos_build_tables_ex -- peos_build_tables with options (opt may be NULL):
+ *   perm          device, d int32, a permutation of 0..d-1, or NULL: steps
+ *                 (1)-(3) and the projection tables of step (5) take
+ *                 coordinate k of every vector from original coordinate
+ *                 perm[k]; distances and everything else use the original
+ *                 coordinates (the permutation changes neither the graph nor
+ *                 the guarantee).  Kept by the index: must stay valid until
+ *                 peos_free.  Not with PEOS_FLAG_SIMHASH.
+ *   simhash_dirs  device, 64 x d float, required by PEOS_FLAG_SIMHASH: the
+ *                 sign-projection vectors of the SimHash test (kept by the
+ *                 index: the search projects each query on them).
+ * Errors as peos_build_tables.
  */
-int peos_build_tables_permuted(const float* base, int64_t n, int32_t d, const int32_t* graph,
-                               int32_t R, int32_t entry, int32_t L, int32_t m,
-                               const float* dirs_a, const float* dirs_b, int32_t metric,
-                               int32_t flags, const int32_t* perm, void* index_mem,
-                               size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
-                               peos_index** out);
+typedef struct {
+    const int32_t* perm;
+    const float* simhash_dirs;
+} peos_build_options;
+int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t* graph, int32_t R,
+                         int32_t entry, int32_t L, int32_t m, const float* dirs_a,
+                         const float* dirs_b, int32_t metric, int32_t flags,
+                         const peos_build_options* opt, void* index_mem, size_t index_bytes,
+                         void* ws, size_t ws_bytes, void* stream, peos_index** out);
 /* Fill *out (host) with the record layout of an index.  Errors: PEOS_EINVAL. */
 int peos_index_layout(const peos_index* index, peos_layout* out);
 
@@ -232,7 +254,7 @@ int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int
  *            entries, at most 8192.
  *   eps      error bound epsilon of probabilistic routing (Def. 3.2), in
  *            (0, 0.5]; ignored by EXHAUSTIVE.
- *   mode     PEOS_MODE_*.
+ *   mode     PEOS_MODE_* (SIMHASH needs PEOS_FLAG_SIMHASH).
  *   ids      out, nq x kstride int64: first k results ordered by (distance,
  *            id), then -1.
  *   dists    out, nq x kstride float: their distances (squared l2, or

@@ -27,8 +27,10 @@ PEOS_METRIC_L2 = 0
 PEOS_METRIC_ANGULAR = 1
 PEOS_MODE_PEOS = 0
 PEOS_MODE_EXHAUSTIVE = 1
+PEOS_MODE_SIMHASH = 2
 PEOS_FLAG_BF16_BASE = 1
 PEOS_FLAG_FP16 = 2
+PEOS_FLAG_SIMHASH = 4
 PEOS_NSTATS = 12
 STATS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0", "test_h",
          "test_zero", "passes", "ndist", "inserted", "status")
@@ -49,7 +51,12 @@ class peos_layout(ctypes.Structure):
                 ("flags", ctypes.c_int32), ("entry", ctypes.c_int32),
                 ("node_stride", ctypes.c_int64), ("codes_offset", ctypes.c_int64),
                 ("scalars_offset", ctypes.c_int64), ("code_bytes", ctypes.c_int64),
-                ("scalar_bytes", ctypes.c_int64), ("bf16_offset", ctypes.c_int64)]
+                ("scalar_bytes", ctypes.c_int64), ("bf16_offset", ctypes.c_int64),
+                ("simhash_offset", ctypes.c_int64)]
+
+
+class peos_build_options(ctypes.Structure):
+    _fields_ = [("perm", ctypes.c_void_p), ("simhash_dirs", ctypes.c_void_p)]
 
 
 class peos_serve_config(ctypes.Structure):
@@ -79,8 +86,9 @@ def lib():
         L.peos_build_tables.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, i32, P, sz,
                                         P, sz, P, ctypes.POINTER(P)]
         L.peos_index_layout.argtypes = [P, ctypes.POINTER(peos_layout)]
-        L.peos_build_tables_permuted.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32,
-                                                 i32, P, P, sz, P, sz, P, ctypes.POINTER(P)]
+        L.peos_build_tables_ex.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, i32,
+                                           ctypes.POINTER(peos_build_options), P, sz, P, sz, P,
+                                           ctypes.POINTER(P)]
         L.peos_dimension_permutation_ws_bytes.argtypes = [i32, Psz]
         L.peos_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P, sz, P]
         L.peos_free.argtypes = [P]
@@ -107,7 +115,7 @@ def lib():
         L.peos_strerror.restype = ctypes.c_char_p
         L.peos_last_error.restype = ctypes.c_char_p
         for name in ("peos_index_bytes", "peos_build_tables", "peos_index_layout",
-                     "peos_build_tables_permuted", "peos_dimension_permutation_ws_bytes",
+                     "peos_build_tables_ex", "peos_dimension_permutation_ws_bytes",
                      "peos_dimension_permutation",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
                      "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
@@ -170,23 +178,26 @@ class PeosIndex:
 
 
 def peos_build_tables(base, graph, entry, L, m, dirs_a, dirs_b, metric, flags=0, stream=None,
-                      perm=None):
+                      perm=None, simhash_dirs=None):
     """Build the edge records.  base (n, d) float32, graph (n, R) int32,
     dirs_a (L, m, d/L) float32, dirs_b (m, d) float32, all on the device.
-    perm: optional int32 device tensor (d), the test's dimension permutation
-    (peos_build_tables_permuted)."""
+    perm: optional int32 device tensor (d), the test's dimension permutation;
+    simhash_dirs: (64, d) float32 device tensor, with PEOS_FLAG_SIMHASH
+    (peos_build_tables_ex)."""
     n, d = base.shape
     R = graph.shape[1]
     ib, wb = peos_index_bytes(n, d, R, L, m, flags)
     mem = torch.empty(ib, dtype=torch.uint8, device=base.device)
     ws = torch.empty(wb, dtype=torch.uint8, device=base.device)
     h = ctypes.c_void_p()
-    _check("peos_build_tables_permuted",
-           lib().peos_build_tables_permuted(_ptr(base), n, d, _ptr(graph), R, int(entry), L, m,
-                                            _ptr(dirs_a), _ptr(dirs_b), metric, flags,
-                                            _ptr(perm), _ptr(mem), ib, _ptr(ws), wb,
-                                            _stream(stream), ctypes.byref(h)))
-    return PeosIndex(h, (base, graph, dirs_a, dirs_b, perm, mem))
+    opt = peos_build_options(None if perm is None else perm.data_ptr(),
+                             None if simhash_dirs is None else simhash_dirs.data_ptr())
+    _check("peos_build_tables_ex",
+           lib().peos_build_tables_ex(_ptr(base), n, d, _ptr(graph), R, int(entry), L, m,
+                                      _ptr(dirs_a), _ptr(dirs_b), metric, flags,
+                                      ctypes.byref(opt), _ptr(mem), ib, _ptr(ws), wb,
+                                      _stream(stream), ctypes.byref(h)))
+    return PeosIndex(h, (base, graph, dirs_a, dirs_b, perm, simhash_dirs, mem))
 
 
 def peos_dimension_permutation(base, graph, L, stream=None):

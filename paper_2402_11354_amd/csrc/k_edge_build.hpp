@@ -35,6 +35,8 @@ struct EdgeBuildArgs {
     int half_scalars;  // precision form: scalars as four halves per edge
     const int32_t* perm;  // optional dimension permutation: coordinate k of
                           // the test's vectors is original coordinate perm[k]
+    const float* sdirs;   // 64 x d SimHash vectors, or null
+    int64_t sig_off;      // SimHash signatures within a record
 };
 
 // LDS: xv[d] | e[4][d] | s[4][L] | row[R]
@@ -133,6 +135,32 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 codes[j * cbytes + 1 + i] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
         }
         __syncthreads();
+        // SimHash signature of e (before e is overwritten by its residual):
+        // bit i = [e . c_i >= 0], an fma chain over the coordinates in
+        // order; lane s of the edge's group computes bits s, s+16, s+32, s+48
+        if (a.sdirs) {
+            uint32_t lo = 0u, hi = 0u;
+            if (u >= 0) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = s + 16 * r;
+                    const float* cv = a.sdirs + (int64_t)i * d;
+                    float p = 0.f;
+                    for (int k = 0; k < d; ++k) p = fmaf(e[k], cv[k], p);
+                    if (p >= 0.f) {
+                        if (i < 32) lo |= 1u << i;
+                        else hi |= 1u << (i - 32);
+                    }
+                }
+            }
+#pragma unroll
+            for (int o = 8; o >= 1; o >>= 1) {
+                lo |= (uint32_t)__shfl_xor((int)lo, o, 16);
+                hi |= (uint32_t)__shfl_xor((int)hi, o, 16);
+            }
+            if (s == 0 && j < R)
+                *reinterpret_cast<uint2*>(rv + a.sig_off + 8 * j) = make_uint2(lo, hi);
+        }
         // regular part: c = sum(s_i) / L', residual in place
         float c = 0.f;
         int nz = 0;

@@ -35,7 +35,8 @@ struct SearchArgs {
     const uint16_t* base16;  // bfloat16 copy of the base (kFlagBf16Base)
     const int32_t* graph;
     const uint8_t* rec;
-    int64_t node_stride, codes_off, scal_off;
+    int32_t node_stride, codes_off, scal_off, sig_off;  // bytes (records < 2 GB apart)
+    const float* sdirs;     // 64 x d SimHash vectors (SimHash mode)
     const float* queries;
     const float* tables;
     const float* qnorms;
@@ -48,11 +49,11 @@ struct SearchArgs {
     int32_t* stats;
     uint32_t* counter;  // work counter, zero before launch
     uint32_t* spill;    // per-slot visited bitmaps
-    int64_t spill_words;
+    int32_t spill_words;
     int64_t n, nq;
     int k_all, ef_all, kstride;
     int d, R, L, m, metric, mode, entry;
-    float eta, c_eps, kappa;
+    float eta, c_eps, kappa, hoeff;
     int listcap, listslack, pool, hcap, visit_limit;
 };
 
@@ -316,6 +317,15 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = tg[t];
             }
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
+            // SimHash mode: the query's 64 sign bits, lane i projecting on c_i
+            // (an fma chain over the coordinates in order)
+            uint64_t qsig = 0;
+            if (a.mode == 2) {
+                const float* cv = a.sdirs + (int64_t)lane * d;
+                float p = 0.f;
+                for (int k = 0; k < d; ++k) p = fmaf(qg[k], cv[k], p);
+                qsig = ballot(p >= 0.f);
+            }
             if (lane == 0) Su[0] = (uint32_t)wave_uniform(ca.entry);
             wave_sync();
             distances<BF, (MAXL >= 16) && BF>(tbase, d, Su, 1, qv, a.metric, inv_qn, Sdist);
@@ -377,7 +387,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                     if (lane == 0) Li[pos] = vid | kExpanded;
                 }
                 ++st_exp;
-                const bool testing = (a.mode == 0) && full;
+                const bool testing = (a.mode == 0 || a.mode == 2) && full;
 
                 // ids, codes and scalars depend on v only: one round trip
                 int32_t u = -1;
@@ -399,11 +409,18 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                         } else {
                             sc4 = reinterpret_cast<const float4*>(rv + a.scal_off)[lane];
                         }
-                        const uint32_t* cb =
-                            reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
+                        if (a.mode == 2) {
+                            // SimHash: the edge's sign bits in place of its codes
+                            const uint2 sg2 = reinterpret_cast<const uint2*>(rv + a.sig_off)[lane];
+                            cw[0] = sg2.x;
+                            if (NCW > 1) cw[1 % NCW] = sg2.y;
+                        } else {
+                            const uint32_t* cb =
+                                reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
 #pragma unroll
-                        for (int i = 0; i < NCW; ++i)
-                            if (i < ncw) cw[i] = cb[i];
+                            for (int i = 0; i < NCW; ++i)
+                                if (i < ncw) cw[i] = cb[i];
+                        }
                     }
                 }
                 const float sg = sc4.x, se = sc4.y, sw = sc4.z, sr = sc4.w;
@@ -435,6 +452,13 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                             } else if (A <= 0.f) {
                                 kind = 2;
                                 pass = true;
+                            } else if (a.mode == 2) {
+                                // SimHash: collisions of the 64 sign bits
+                                kind = 3;
+                                const uint64_t es = ((uint64_t)cw[1 % NCW] << 32) | cw[0];
+                                const int col = 64 - popc(es ^ qsig);
+                                const float T = 64.f * (1.f - acosf(A) * 0.318309886183790672f) - a.hoeff;
+                                pass = (float)col >= T;
                             } else {
                                 kind = 3;
                                 // code byte c: direction c mod m, negative iff c >= m

@@ -23,6 +23,8 @@ struct peos_graph {
 
 struct peos_index {
     const int32_t* perm;     // dimension permutation of the test, or null
+    const float* sdirs;      // 64 x d SimHash vectors (PEOS_FLAG_SIMHASH), or null
+    int64_t sig_off;         // SimHash signatures within a record
     const float* base;
     const uint16_t* base16;  // bfloat16 traversal copy inside index_mem, or null
     const int32_t* graph;
@@ -63,20 +65,24 @@ constexpr int kNumCu = 256;
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    int64_t stride, codes_off, scal_off;
+    int64_t stride, codes_off, scal_off, sig_off;
 };
 
-constexpr int kFlagsAll = PEOS_FLAG_BF16_BASE | PEOS_FLAG_FP16;
+constexpr int kFlagsAll = PEOS_FLAG_BF16_BASE | PEOS_FLAG_FP16;  // kernel variants
+constexpr int kFlagsKnown = kFlagsAll | PEOS_FLAG_SIMHASH;
 
 // record of a node: codes [R][round_up(L+1, 4)] bytes | pad to 16 | scalars
-// [R][4] floats (halves with PEOS_FLAG_FP16) | pad to 128.  With
+// [R][4] floats (halves with PEOS_FLAG_FP16) | with PEOS_FLAG_SIMHASH, pad to
+// 16 and [R] 64-bit sign signatures | pad to 128.  With
 // PEOS_FLAG_BF16_BASE the n x d bfloat16 copy follows the records.
 Layout layout_of(int R, int L, int flags)
 {
     Layout l;
     l.codes_off = 0;
     l.scal_off = round_up((int64_t)R * round_up(L + 1, 4), 16);
-    l.stride = round_up(l.scal_off + ((flags & PEOS_FLAG_FP16) ? 8LL : 16LL) * R, 128);
+    const int64_t end = l.scal_off + ((flags & PEOS_FLAG_FP16) ? 8LL : 16LL) * R;
+    l.sig_off = (flags & PEOS_FLAG_SIMHASH) ? round_up(end, 16) : 0;
+    l.stride = round_up((flags & PEOS_FLAG_SIMHASH) ? l.sig_off + 8LL * R : end, 128);
     return l;
 }
 
@@ -313,7 +319,7 @@ int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int3
                      size_t* index_bytes, size_t* build_ws_bytes)
 {
     if (!index_bytes || !build_ws_bytes) return fail(PEOS_EINVAL, "null output pointer");
-    if (flags & ~kFlagsAll) return fail(PEOS_EINVAL, "flags=%d not supported", flags);
+    if (flags & ~kFlagsKnown) return fail(PEOS_EINVAL, "flags=%d not supported", flags);
     int rc = check_shape(n, d, R, L, m);
     if (rc) return rc;
     Layout l = layout_of(R, L, flags);
@@ -330,18 +336,20 @@ int peos_build_tables(const float* base, int64_t n, int32_t d, const int32_t* gr
                       size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
                       peos_index** out)
 {
-    return peos_build_tables_permuted(base, n, d, graph, R, entry, L, m, dirs_a, dirs_b, metric,
-                                      flags, nullptr, index_mem, index_bytes, ws, ws_bytes, stream,
-                                      out);
+    return peos_build_tables_ex(base, n, d, graph, R, entry, L, m, dirs_a, dirs_b, metric, flags,
+                                nullptr, index_mem, index_bytes, ws, ws_bytes, stream, out);
 }
 
-int peos_build_tables_permuted(const float* base, int64_t n, int32_t d, const int32_t* graph,
-                               int32_t R, int32_t entry, int32_t L, int32_t m,
-                               const float* dirs_a, const float* dirs_b, int32_t metric,
-                               int32_t flags, const int32_t* perm, void* index_mem,
-                               size_t index_bytes, void* ws, size_t ws_bytes, void* stream,
-                               peos_index** out)
+int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t* graph, int32_t R,
+                         int32_t entry, int32_t L, int32_t m, const float* dirs_a,
+                         const float* dirs_b, int32_t metric, int32_t flags,
+                         const peos_build_options* opt, void* index_mem, size_t index_bytes,
+                         void* ws, size_t ws_bytes, void* stream, peos_index** out)
 {
+    const int32_t* perm = opt ? opt->perm : nullptr;
+    const float* sdirs = opt ? opt->simhash_dirs : nullptr;
+    if ((flags & PEOS_FLAG_SIMHASH) && !sdirs) return fail(PEOS_EINVAL, "PEOS_FLAG_SIMHASH needs simhash_dirs");
+    if ((flags & PEOS_FLAG_SIMHASH) && perm) return fail(PEOS_EINVAL, "a dimension permutation does not combine with PEOS_FLAG_SIMHASH");
     if (!out) return fail(PEOS_EINVAL, "null output handle");
     *out = nullptr;
     size_t need = 0, need_ws = 0;
@@ -379,6 +387,8 @@ int peos_build_tables_permuted(const float* base, int64_t n, int32_t d, const in
     a.metric = metric;
     a.half_scalars = (flags & PEOS_FLAG_FP16) ? 1 : 0;
     a.perm = perm;
+    a.sdirs = (flags & PEOS_FLAG_SIMHASH) ? sdirs : nullptr;
+    a.sig_off = l.sig_off;
     size_t lds = sizeof(float) * (size_t)(5 * d + 4 * L) + sizeof(int32_t) * (size_t)R;
     hipLaunchKernelGGL(peos::k_edge_build, dim3((unsigned)n), dim3(64), lds, s, a);
     HIP_TRY(hipGetLastError());
@@ -395,6 +405,8 @@ int peos_build_tables_permuted(const float* base, int64_t n, int32_t d, const in
     peos_index* ix = new (std::nothrow) peos_index;
     if (!ix) return fail(PEOS_EINVAL, "out of host memory");
     ix->perm = perm;
+    ix->sdirs = (flags & PEOS_FLAG_SIMHASH) ? sdirs : nullptr;
+    ix->sig_off = l.sig_off;
     ix->base = base;
     ix->base16 = (flags & PEOS_FLAG_BF16_BASE) ? (const uint16_t*)((uint8_t*)index_mem + bf16_off) : nullptr;
     ix->bf16_off = bf16_off;
@@ -435,6 +447,7 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
     out->code_bytes = round_up(ix->L + 1, 4);
     out->scalar_bytes = (ix->flags & PEOS_FLAG_FP16) ? 8 : 16;
     out->bf16_offset = ix->bf16_off;
+    out->simhash_offset = ix->sig_off;
     return PEOS_OK;
 }
 
@@ -491,7 +504,7 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     if (plan.lds + kStaticLds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
     peos::SearchArgs a = base_args;
     a.counter = const_cast<uint32_t*>(counter);
-    a.spill_words = plan.spill_words;
+    a.spill_words = (int32_t)plan.spill_words;
     a.listcap = plan.listcap;
     a.listslack = plan.listslack;
     a.hcap = plan.hcap;
@@ -533,9 +546,11 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.base16 = ix->base16;
     a.graph = ix->graph;
     a.rec = ix->rec;
-    a.node_stride = ix->node_stride;
-    a.codes_off = ix->codes_off;
-    a.scal_off = ix->scal_off;
+    a.node_stride = (int32_t)ix->node_stride;
+    a.codes_off = (int32_t)ix->codes_off;
+    a.scal_off = (int32_t)ix->scal_off;
+    a.sig_off = (int32_t)ix->sig_off;
+    a.sdirs = ix->sdirs;
     a.queries = queries;
     a.tables = tables;
     a.qnorms = qnorms;
@@ -564,6 +579,7 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     const double eta = std::sqrt(2.0 * ix->L * std::log((double)ix->m));
     a.eta = (float)eta;
     a.c_eps = (float)norm_ppf((double)eps);
+    a.hoeff = mode == PEOS_MODE_SIMHASH ? (float)std::sqrt(64.0 * std::log(1.0 / (double)eps) / 2.0) : 0.f;
     a.kappa = (float)((double)ix->L / (double)(ix->L + 1));
     a.pool = pool;
     uint32_t* counters = (uint32_t*)((char*)ws + w.counter_off);
@@ -599,8 +615,9 @@ static int check_search_args(const peos_index* ix, const float* queries, int64_t
     if (ef_all < 1 || ef_all > kMaxEf || k_all > kMaxEf) return fail(PEOS_EINVAL, "ef_all=%d (max %d)", ef_all, kMaxEf);
     if (pool < -16 || pool > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d", pool);
     if (pool < 0 && -pool * ef_all > 2 * kMaxEf) return fail(PEOS_EINVAL, "pool=%d x ef=%d above %d", pool, ef_all, 2 * kMaxEf);
-    if (mode != PEOS_MODE_PEOS && mode != PEOS_MODE_EXHAUSTIVE) return fail(PEOS_EINVAL, "mode=%d", mode);
-    if (mode == PEOS_MODE_PEOS && !(eps > 0.f && eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g not in (0, 0.5]", (double)eps);
+    if (mode != PEOS_MODE_PEOS && mode != PEOS_MODE_EXHAUSTIVE && mode != PEOS_MODE_SIMHASH) return fail(PEOS_EINVAL, "mode=%d", mode);
+    if (mode != PEOS_MODE_EXHAUSTIVE && !(eps > 0.f && eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g not in (0, 0.5]", (double)eps);
+    if (mode == PEOS_MODE_SIMHASH && !(ix->flags & PEOS_FLAG_SIMHASH)) return fail(PEOS_EINVAL, "PEOS_MODE_SIMHASH needs an index built with PEOS_FLAG_SIMHASH");
     if (nq > 0 && (!queries || !ids || !dists || !ws)) return fail(PEOS_EINVAL, "null device pointer");
     return PEOS_OK;
 }

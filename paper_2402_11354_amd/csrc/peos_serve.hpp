@@ -203,8 +203,9 @@ int peos_serve_open(const peos_index* ix, const peos_serve_config* cfg, peos_ser
     if (c.max_pending < c.max_batch) return fail(PEOS_EINVAL, "max_pending=%d < max_batch", c.max_pending);
     if (c.pool < -16 || c.pool > 2 * kMaxEf || (c.pool < 0 && -c.pool * c.max_ef > 2 * kMaxEf))
         return fail(PEOS_EINVAL, "pool=%d", c.pool);
-    if (c.mode != PEOS_MODE_PEOS && c.mode != PEOS_MODE_EXHAUSTIVE) return fail(PEOS_EINVAL, "mode=%d", c.mode);
-    if (c.mode == PEOS_MODE_PEOS && !(c.eps > 0.f && c.eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g", (double)c.eps);
+    if (c.mode != PEOS_MODE_PEOS && c.mode != PEOS_MODE_EXHAUSTIVE && c.mode != PEOS_MODE_SIMHASH) return fail(PEOS_EINVAL, "mode=%d", c.mode);
+    if (c.mode != PEOS_MODE_EXHAUSTIVE && !(c.eps > 0.f && c.eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g", (double)c.eps);
+    if (c.mode == PEOS_MODE_SIMHASH && !(ix->flags & PEOS_FLAG_SIMHASH)) return fail(PEOS_EINVAL, "SimHash mode needs PEOS_FLAG_SIMHASH");
     if (c.launch_waves < 0 || c.launch_waves > kMaxSlots) return fail(PEOS_EINVAL, "launch_waves=%d", c.launch_waves);
     int dev;
     int rc = check_device(&dev);

@@ -496,3 +496,60 @@ def test_rceos_is_the_L1_case(pool_mul):
     assert not res["bad"], res["bad"][:5]
     assert res["checked"] >= 0.8 * len(q)
     assert st.cpu().numpy()[:, 6].sum() > 0  # H-vs-T tests did run
+
+
+# ---------------------------------------------------------------------------
+# SimHash test on the same kernel
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def simhash_case(tiny):
+    C = np.random.default_rng(41).normal(size=(64, tiny.w.d)).astype(np.float32)
+    w = tiny.w
+    idx = P.peos_build_tables(tiny.xt, tiny.gt, tiny.entry, w.L, w.m, tiny.At, tiny.Bt, w.metric,
+                              flags=P.PEOS_FLAG_SIMHASH, simhash_dirs=T(C))
+    return tiny, C, idx
+
+
+def test_simhash_signatures_match_oracle(simhash_case):
+    case, C, idx = simhash_case
+    lay = idx.layout()
+    assert lay.simhash_offset > 0
+    mem = idx._keep[-1].cpu().numpy().reshape(lay.n, lay.node_stride)
+    R = case.g.shape[1]
+    sig = mem[:, lay.simhash_offset:lay.simhash_offset + 8 * R].copy().view(np.uint64)
+    rng = np.random.default_rng(0)
+    for v in rng.choice(lay.n, 60, replace=False):
+        for j in range(R):
+            u = case.g[v, j]
+            if u < 0:
+                continue
+            ref = O.simhash_bits(case.x[u] - case.x[v], C)[0]
+            assert sig[v, j] == ref, (v, j)
+    # PEOs codes unchanged by the extra signatures
+    codes, _ = read_records(case)
+    lay0 = case.index.layout()
+    assert lay.codes_offset == lay0.codes_offset
+
+
+@pytest.mark.parametrize("pool_mul", [0, 1])
+@pytest.mark.parametrize("eps", [0.1, 0.3])
+def test_simhash_search_matches_oracle(simhash_case, pool_mul, eps):
+    case, C, idx = simhash_case
+    w = case.w
+    ids, d, st = P.search(idx, case.qt, w.k, w.ef, eps=eps, mode=P.PEOS_MODE_SIMHASH,
+                          pool=pool_mul * w.ef)
+    torch.cuda.synchronize()
+    ref = O.search(case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B,
+                   w.metric, eps, mode=O.MODE_SIMHASH, pool=pool_mul * w.ef, precision=32,
+                   simhash=C)
+    res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, w.k)
+    print(f"[gpu] simhash eps={eps} pool={pool_mul * w.ef}: checked={res['checked']} "
+          f"fragile={res['fragile']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(case.q)
+    assert st.cpu().numpy()[:, 6].sum() > 0
+
+
+def test_simhash_mode_needs_signatures(tiny):
+    with pytest.raises(P.PeosError):
+        P.search(tiny.index, tiny.qt, 10, 32, eps=0.1, mode=P.PEOS_MODE_SIMHASH)
