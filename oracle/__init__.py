@@ -27,6 +27,7 @@ import numpy as np
 
 L2 = 0
 ANGULAR = 1
+IP = 2  # maximum inner product, distance -x.q (appendix, Extension to MIPS)
 MODE_PEOS = 0
 MODE_EXHAUSTIVE = 1
 MODE_SIMHASH = 2
@@ -45,7 +46,9 @@ _lib = None
 def build(force: bool = True) -> str:
     """Compile the C part with gcc (no fp contraction, so the single-precision
     code decisions follow the stated fmaf order exactly)."""
-    if force or not os.path.exists(_LIB):
+    stale = (not os.path.exists(_LIB)
+             or os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
                                "-fPIC", "-shared", "-pthread", _SRC, "-o", tmp, "-lm"])
@@ -268,13 +271,16 @@ def dimension_permutation(base, graph, L):
 # exact k-NN (recall reference)
 # ---------------------------------------------------------------------------
 def brute_force(base, queries, k, metric):
-    """Exact top-k in float64 by (distance, id): squared l2, or 1 - x.q/|q|."""
+    """Exact top-k in float64 by (distance, id): squared l2, 1 - x.q/|q|, or
+    -x.q (inner product)."""
     xb = np.asarray(base, np.float64)
     ids_out = np.full((len(queries), k), -1, np.int64)
     d_out = np.full((len(queries), k), np.inf)
     for i, q in enumerate(np.asarray(queries, np.float64)):
         if metric == L2:
             dd = ((xb - q) ** 2).sum(1)
+        elif metric == IP:
+            dd = -(xb @ q)
         else:
             dd = 1.0 - xb @ q / np.linalg.norm(q)
         order = np.lexsort((np.arange(len(dd)), dd))[:k]

@@ -30,6 +30,7 @@
 
 #define OR_L2 0
 #define OR_ANGULAR 1
+#define OR_IP 2 /* maximum inner product: dist = -x.q (appendix, Extension to MIPS) */
 #define OR_MODE_PEOS 0
 #define OR_MODE_EXHAUSTIVE 1
 #define OR_MODE_SIMHASH 2
@@ -429,7 +430,8 @@ double oracle_threshold(double A, double w_reg, double w_res, int L, double eta,
  * Step (6) for edge e = (v, u) against the furthest result p.  num is the
  * numerator of A_r written as in the paper: |u|^2/2 - r - v.q with
  * r = |p|^2/2 - p.q for l2, and with the two squared norms removed for the
- * angular metric (= p.q - v.q, the MIPS form).  A_r = num / (|q| |e|).
+ * angular and inner-product metrics (= p.q - v.q, the form the appendix gives
+ * for MIPS, p the result of smallest inner product).  A_r = num / (|q| |e|).
  * Returns 1 = pass, 0 = fail.  kind: 0 zero-length edge, 1 A>=1, 2 A<=0,
  * 3 H-vs-T.  flags receives the fragile bits of this decision.
  */
@@ -441,9 +443,9 @@ static int routing_test(const test_params* tp, const edge_rec* er, const double*
     *outA = NAN;
     *outH = NAN;
     *outT = NAN;
-    /* the numerator is exactly 0 in any precision only for the angular
-       metric with v = p; for l2 it is then g_e */
-    const int exact0 = v_is_p && tp->metric == OR_ANGULAR;
+    /* the numerator is exactly 0 in any precision only for the angular and
+       inner-product metrics with v = p; for l2 it is then g_e */
+    const int exact0 = v_is_p && tp->metric != OR_L2;
     if (er->norm_e == 0.0) {
         *kind = 0;
         if (!exact0 && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
@@ -474,8 +476,10 @@ static int routing_test(const test_params* tp, const edge_rec* er, const double*
  * the table entries are the nearest halves of the exact table.  The
  * numerator of A_r is taken from the search's own distances, which is the
  * same quantity: |u|^2/2 - r - v.q = g_e + (dist_v - delta)/2 for squared
- * l2 (and dist_v - delta for angular), so A_r = (gp + (dist_v - delta)/2 *
- * ie) / |q|, or (dist_v - delta) * ie.  An edge whose 1/|e| is not finite
+ * l2, (dist_v - delta) |q| for angular with dist = 1 - x.q/|q|, and
+ * dist_v - delta for the inner product with dist = -x.q; so A_r = (gp +
+ * (dist_v - delta)/2 * ie) / |q|, (dist_v - delta) * ie, or (dist_v - delta)
+ * * ie / |q| respectively.  An edge whose 1/|e| is not finite
  * as a half (|e| = 0, or below the half range) is decided by the sign of the
  * numerator, as a zero-length edge.
  */
@@ -490,7 +494,7 @@ static int routing_test_lowp(const test_params* tp, const edge_rec* er, const do
     *outT = NAN;
     const double diff = tp->metric == OR_L2 ? 0.5 * (dv - delta) : (dv - delta);
     const double ie = er->norm_e > 0.0 ? oracle_round_half(1.0 / er->norm_e) : INFINITY;
-    const int exact0 = v_is_p && tp->metric == OR_ANGULAR;
+    const int exact0 = v_is_p && tp->metric != OR_L2;
     if (!isfinite(ie)) {
         *kind = 0;
         if (!v_is_p && fabs(diff) <= tau * (fabs(dv) + fabs(delta))) *flags |= F_A0;
@@ -500,7 +504,7 @@ static int routing_test_lowp(const test_params* tp, const edge_rec* er, const do
                           ? oracle_round_half(0.5 * (er->nu2 - er->nv2) / er->norm_e) : 0.0;
     const double wr = oracle_round_half(er->w_reg);
     const double sr = oracle_round_half(sqrt((double)L) * er->w_res);
-    const double A = tp->metric == OR_L2 ? (gp + diff * ie) / qnorm : diff * ie;
+    const double A = tp->metric == OR_ANGULAR ? diff * ie : (gp + diff * ie) / qnorm;
     *outA = A;
     if (fabs(A - 1.0) < tau) *flags |= F_A1;
     if (!exact0 && fabs(A) < tau) *flags |= F_A0;
@@ -551,7 +555,7 @@ static int routing_test_simhash(const test_params* tp, double norm_e, int col, i
                                 int v_is_p)
 {
     const double tau = tp->tau;
-    const int exact0 = v_is_p && tp->metric == OR_ANGULAR;
+    const int exact0 = v_is_p && tp->metric != OR_L2;
     if (norm_e == 0.0) {
         *kind = 0;
         if (!exact0 && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
@@ -678,6 +682,7 @@ static double dist64(const float* x, const float* q, double qnorm, int d, int me
         }
         return s;
     }
+    if (metric == OR_IP) return -dot64(x, q, d);
     return 1.0 - dot64(x, q, d) / qnorm;
 }
 
@@ -727,6 +732,7 @@ static float dist32(const float* x, const float* q, int d, int metric, float inv
     }
     for (int w = 16; w > 1; w /= 2)
         for (int i = 0; i < w / 2; ++i) seg[i] = seg[2 * i] + seg[2 * i + 1];
+    if (metric == OR_IP) return -seg[0];
     return metric == OR_L2 ? seg[0] : fmaf(-seg[0], inv_qn, 1.0f);
 }
 
@@ -895,6 +901,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
                        (dist_v - delta) |q| for angular -- equal to the
                        expression below on exact distances */
                     if (j->metric == OR_L2) num = 0.5 * (er.nu2 - er.nv2) + 0.5 * (dv - delta);
+                    else if (j->metric == OR_IP) num = dv - delta;
                     else num = (dv - delta) * qnorm;
                 } else if (j->metric == OR_L2) {
                     num = 0.5 * er.nu2 - r - vq;
@@ -1019,7 +1026,8 @@ static void* search_worker(void* arg)
  * distances of dist32(), the precision of the GPU kernel.  out_dist then
  * holds those values and out_dist64 (optional) the double-precision ones.
  * out_ids / out_dist: nq x kstride, first k entries of R, padded (-1, +inf).
- * Distances: squared l2, or 1 - x.q/|q| for the angular metric.
+ * Distances: squared l2, 1 - x.q/|q| for the angular metric, or -x.q for
+ * the inner product (the largest inner products first).
  * counters: nq x C_NCOUNT int64; fragile: nq flag words; status: 0 ok, -1
  * zero/non-finite query.  lowp: precision-form flags (LP_*, implies fp32):
  * LP_FP16 takes the routing test on half-rounded scalars and tables

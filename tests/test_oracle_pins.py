@@ -349,7 +349,7 @@ def test_routing_test_H_matches_table_sum():
 # ---------------------------------------------------------------------------
 # P5: A_r algebra
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 def test_A_r_literal_equals_distance_form_and_is_exact_cosine_threshold(metric):
     rng = np.random.default_rng(13 + metric)
     L, m, d = 4, 16, 32
@@ -366,6 +366,11 @@ def test_A_r_literal_equals_distance_form_and_is_exact_cosine_threshold(metric):
             dist = lambda x: ((x - q) ** 2).sum()
             num = 0.5 * (xu @ xu - xv @ xv) + 0.5 * (dist(xv) - dist(xp))
             Aref = num / (np.linalg.norm(q) * np.linalg.norm(e))
+        elif metric == W.IP:
+            # appendix (Extension to MIPS): (p.q - v.q) / (|q| |e|), p the
+            # result of smallest inner product
+            dist = lambda x: -(x @ q)
+            Aref = (xp @ q - xv @ q) / (np.linalg.norm(q) * np.linalg.norm(e))
         else:
             dist = lambda x: 1 - x @ q / np.linalg.norm(q)
             Aref = (dist(xv) - dist(xp)) / np.linalg.norm(e)
@@ -407,7 +412,7 @@ def _tiny(n=300, d=16, R=8, seed=0, metric=W.L2):
     return x, q, g, entry
 
 
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 def test_brute_force_matches_cdist(metric):
     rng = np.random.default_rng(1)
     x = rng.standard_normal((500, 12))
@@ -417,15 +422,19 @@ def test_brute_force_matches_cdist(metric):
     ids, dd = O.brute_force(x, q, 7, metric)
     if metric == W.L2:
         full = cdist(q, x, "sqeuclidean")
+    elif metric == W.IP:
+        # -x.q = (cosine distance - 1) |q| |x|
+        full = ((cdist(q, x, "cosine") - 1.0) * np.linalg.norm(q, axis=1)[:, None]
+                * np.linalg.norm(x, axis=1)[None, :])
     else:
         full = cdist(q, x, "cosine")  # 1 - cos
     for i in range(len(q)):
         order = sorted(range(len(x)), key=lambda j: (full[i, j], j))[:7]
         assert list(ids[i]) == order
-        np.testing.assert_allclose(dd[i], full[i, order], rtol=1e-12, atol=1e-12)
+        np.testing.assert_allclose(dd[i], full[i, order], rtol=1e-12, atol=1e-11)
 
 
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 @pytest.mark.parametrize("mode", [O.MODE_EXHAUSTIVE, O.MODE_PEOS])
 def test_search_with_list_larger_than_n_is_exact_knn(metric, mode):
     """With ef >= n the list never fills, no test runs, every reachable node
@@ -444,7 +453,7 @@ def test_search_with_list_larger_than_n_is_exact_knn(metric, mode):
     assert np.all(c[:, O.COUNTERS.index("tests")] == 0)
 
 
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 def test_vanishing_eps_reproduces_exhaustive_search(metric):
     """eps -> 0+ leaves only the exact prune A_r >= 1 (which implies
     dist(u) >= delta): same ids and distances as exhaustive search, fewer
@@ -472,6 +481,51 @@ def test_vanishing_eps_reproduces_exhaustive_search(metric):
     c = pe["counters"]
     assert np.all(c[:, ci("test_zero")] == 0)
     assert np.all(c[:, ci("passes")] == c[:, ci("test_h")] + c[:, ci("test_le0")])
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_inner_product_search_scales_with_the_query(precision, pool_mul):
+    """Inner product (appendix, Extension to MIPS): multiplying q by 8 (exact
+    in binary floating point) multiplies every distance p.q, v.q by 8 and |q|
+    by 8, so A_r = (p.q - v.q)/(|q||e|) and q/|q| are unchanged: the same
+    path, counters and ids, distances times 8.  A test without |q| in the
+    denominator of A_r would see 8 times larger A_r and prune differently."""
+    w = W.TINY.with_sizes(n=1500, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    kw = dict(pool=pool_mul * 32, precision=precision)
+    a = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, W.IP, 0.1, **kw)
+    b = O.search(x, g, entry, (8.0 * q).astype(np.float32), 10, 32, w.L, w.m, A, B, W.IP, 0.1,
+                 **kw)
+    assert np.array_equal(a["ids"], b["ids"])
+    assert np.array_equal(a["counters"], b["counters"])
+    np.testing.assert_array_equal(8.0 * a["dist"], b["dist"])
+    ci = O.COUNTERS.index
+    if pool_mul == 0:
+        # the unbounded queue expands nodes outside the list: real tests run
+        assert a["counters"][:, ci("test_h")].sum() > 0
+
+
+def test_inner_product_on_unit_vectors_is_angular():
+    """On unit-norm base vectors and queries, -x.q = (1 - x.q/|q|) - 1: the
+    inner-product search takes the angular search's path (same ids and
+    counters away from near ties) with distances shifted by one."""
+    w = W.TINY.with_sizes(n=1500, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    x /= np.linalg.norm(x, axis=1, keepdims=True)
+    q = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    ang = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, W.ANGULAR, 0.1)
+    ip = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, W.IP, 0.1)
+    clean = (ang["fragile"] == 0) & (ip["fragile"] == 0)
+    assert clean.sum() >= 0.5 * len(q)
+    assert np.array_equal(ang["ids"][clean], ip["ids"][clean])
+    assert np.array_equal(ang["counters"][clean], ip["counters"][clean])
+    # |q| is one only to single precision (the stored query is float32)
+    np.testing.assert_allclose(ip["dist"][clean], ang["dist"][clean] - 1.0, rtol=0, atol=1e-6)
 
 
 def _two_heap_search(x, g, entry, q, k, ef, L, m, A, B, metric, eps, mode):
@@ -656,7 +710,7 @@ def test_integer_data_ties_follow_strict_insertion(mode, pool_mul):
 # ---------------------------------------------------------------------------
 # the single-precision distance decisions (the GPU kernel's precision)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 def test_fp32_distances_within_rounding_bound(metric):
     w = W.TINY.with_sizes(n=1500, nq=40)
     x, q = W.make_base(w), W.make_queries(w)
@@ -670,13 +724,19 @@ def test_fp32_distances_within_rounding_bound(metric):
     u = 2.0 ** -24
     if metric == W.L2:
         assert np.all(np.abs(d32 - d64) <= (w.d + 2) * u * d64)
+    elif metric == W.IP:
+        # a dot product of d terms: (d + 2) u sum |x_k q_k| <= (d + 2) u |x||q|
+        scale = (np.linalg.norm(x.astype(np.float64), axis=1)[out["ids"]]
+                 * np.linalg.norm(q.astype(np.float64), axis=1)[:, None])
+        assert np.all(np.abs(d32 - d64) <= (w.d + 2) * u * scale)
+        return
     else:
         assert np.all(np.abs(d32 - d64) <= (w.d + 4) * u)
     # and far inside the 1e-5 relative tolerance of the GPU parity
     assert np.all(np.abs(d32 - d64) <= 1e-5 * np.abs(d64) + 1e-6)
 
 
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 @pytest.mark.parametrize("pool_mul", [0, 1])
 def test_fp32_decisions_equal_fp64_away_from_near_ties(metric, pool_mul):
     """Single-precision distance decisions change nothing unless two
@@ -752,7 +812,7 @@ def test_bf16_traversal_on_bf16_exact_data_equals_fp32(mode):
     assert np.array_equal(a["counters"], b["counters"])
 
 
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 def test_bf16_rerank_returns_full_precision_order(metric):
     """The bfloat16 traversal's output is re-ranked on the full base: the
     returned distances are the single-precision distances of the returned
@@ -764,6 +824,10 @@ def test_bf16_rerank_returns_full_precision_order(metric):
     u = 2.0 ** -24
     if metric == W.L2:
         assert np.all(np.abs(d - d64) <= (w.d + 2) * u * d64)
+    elif metric == W.IP:
+        scale = (np.linalg.norm(x.astype(np.float64), axis=1)[out["ids"]]
+                 * np.linalg.norm(q.astype(np.float64), axis=1)[:, None])
+        assert np.all(np.abs(d - d64) <= (w.d + 2) * u * scale)
     else:
         assert np.all(np.abs(d - d64) <= (w.d + 4) * u)
     # recall is essentially unchanged by the bfloat16 traversal
@@ -774,7 +838,7 @@ def test_bf16_rerank_returns_full_precision_order(metric):
     assert r_lo >= r_hi - 0.02
 
 
-@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR])
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
 def test_half_test_within_rounding_bound_of_exact_test(metric):
     """The precision-form test (half scalars and table) differs from the
     exact test only by the half rounding: |A' - A| and |H' - H| stay within

@@ -20,6 +20,7 @@ import numpy as np
 
 L2 = 0
 ANGULAR = 1
+IP = 2  # maximum inner product (distance -x.q)
 
 _CHUNK_ROWS = 65536  # fixed so that chunked draws are reproducible
 

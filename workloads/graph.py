@@ -37,6 +37,7 @@ import torch
 
 L2 = 0
 ANGULAR = 1
+IP = 2
 
 
 def _dev_dtype(device):
@@ -374,22 +375,22 @@ def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool
 
 
 def ground_truth(base: np.ndarray, queries: np.ndarray, k: int, metric: int, device="cpu"):
-    """Exact top-k ids and distances (squared l2, or 1 - x.q/|q| for angular),
-    ordered by (distance, id)."""
+    """Exact top-k ids and distances (squared l2, 1 - x.q/|q| for angular,
+    -x.q for the inner product), ordered by (distance, id)."""
     device, dt = _dev_dtype(device)
     x = torch.as_tensor(base).to(device=device, dtype=dt)
     q = torch.as_tensor(queries).to(device=device, dtype=dt)
     if metric == L2:
         ids, dd = knn(x, q, k)
         return ids.cpu().numpy(), dd.cpu().numpy()
-    qn = q / torch.linalg.norm(q, dim=1, keepdim=True)
+    qn = q if metric == IP else q / torch.linalg.norm(q, dim=1, keepdim=True)
     ids_all = []
     d_all = []
     for s in range(0, q.shape[0], 2048):
         sim = qn[s:s + 2048] @ x.T.contiguous()
         kk = min(k + 8, x.shape[0])
         v, i = torch.topk(sim, kk, dim=1)
-        dd = 1.0 - v
+        dd = -v if metric == IP else 1.0 - v
         o = torch.argsort(i, dim=1, stable=True)
         i, dd = torch.gather(i, 1, o), torch.gather(dd, 1, o)
         o = torch.argsort(dd, dim=1, stable=True)
@@ -406,6 +407,8 @@ def exact_distances(base: np.ndarray, queries: np.ndarray, ids: np.ndarray, metr
     q = queries.astype(np.float64)[:, None, :]
     if metric == L2:
         dd = ((xb - q) ** 2).sum(-1)
+    elif metric == IP:
+        dd = -(xb * q).sum(-1)
     else:
         dd = 1.0 - (xb * q).sum(-1) / np.linalg.norm(q, axis=-1)
     return np.where(ids >= 0, dd, np.inf)
