@@ -47,6 +47,11 @@ extern "C" {
  * "Extension to MIPS" appendix, which is exact for this distance). */
 #define PEOS_METRIC_L2 0
 #define PEOS_METRIC_ANGULAR 1
+/* IP: maximum inner product search ("Extension to MIPS" appendix), distance
+ * -x.q (results ordered by decreasing inner product; base rows of any norm).
+ * The test takes A_r = (p.q - v.q)/(|q||e|) = (dist_v - delta)/(|q||e|),
+ * p the result of smallest inner product; everything else is as for L2. */
+#define PEOS_METRIC_IP 2
 
 /* search modes.  PEOS: neighbours are screened by the routing test.
  * EXHAUSTIVE: the test is off (every unvisited neighbour gets a distance),
@@ -71,7 +76,8 @@ extern "C" {
  *   {g_e/|e|, 1/|e| (infinite for a zero-length edge), w_reg, sqrt(L) w_res}
  *   and the projection tables as halves; the test of step (6) then takes
  *   A_r = (g_e/|e| + (dist_v - delta)/2 * 1/|e|) / |q| (l2) or
- *   (dist_v - delta)/|e| (angular), the same quantity as the full form's. */
+ *   (dist_v - delta)/|e| (angular) or (dist_v - delta)/(|e||q|) (IP), the
+ *   same quantity as the full form's. */
 #define PEOS_FLAG_BF16_BASE 1
 #define PEOS_FLAG_FP16 2
 /* PEOS_FLAG_SIMHASH: the records also hold, per edge, the 64 sign bits
@@ -110,7 +116,7 @@ typedef struct peos_graph peos_graph;
  * code e[0], bytes 1..L = subspace codes e[i], then zero padding.  A code
  * byte c encodes the index j* = c mod m of the extreme projection vector and
  * its sign (negative iff c >= m).  Scalars: edge j owns 4 floats at
- * scalars_offset + 16*j: g_e = (|u|^2 - |v|^2)/2 (zero for ANGULAR), |e|,
+ * scalars_offset + 16*j: g_e = (|u|^2 - |v|^2)/2 (zero for ANGULAR and IP), |e|,
  * w_reg, sqrt(L)*w_res; with PEOS_FLAG_FP16, 4 halves at scalars_offset + 8*j
  * (see PEOS_FLAG_FP16).  With PEOS_FLAG_BF16_BASE the bfloat16 copy of the
  * base (n x d) starts at bf16_offset. */

@@ -25,6 +25,7 @@ PEOS_EDEVICE = -5
 PEOS_EBUSY = -6
 PEOS_METRIC_L2 = 0
 PEOS_METRIC_ANGULAR = 1
+PEOS_METRIC_IP = 2
 PEOS_MODE_PEOS = 0
 PEOS_MODE_EXHAUSTIVE = 1
 PEOS_MODE_SIMHASH = 2

@@ -216,7 +216,8 @@ __device__ __forceinline__ void gather_distances(const void* base, int d, const 
                 for (int j = 0; j < NP; j += 2 * h) part[pp][j] = part[pp][j] + part[pp][j + h];
             const int idx = b0 + t + pp * SPR;
             if (act[pp] && s == 0)
-                Sdist[idx] = (metric == 0) ? part[pp][0] : fmaf(-part[pp][0], inv_qn, 1.f);
+                Sdist[idx] = (metric == 0) ? part[pp][0]
+                           : (metric == 2) ? -part[pp][0] : fmaf(-part[pp][0], inv_qn, 1.f);
         }
     }
 }
@@ -437,15 +438,17 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                     int kind = -1;
                     if (cand) {
                         // full precision: sg = g_e, se = |e|; halves: sg =
-                        // g_e/|e|, se = 1/|e| (infinite for a zero edge)
+                        // g_e/|e|, se = 1/|e| (infinite for a zero edge).
+                        // sg is zero for angular and inner product; the
+                        // angular distance already carries the 1/|q|.
                         const float diff = (a.metric == 0) ? 0.5f * (dv - delta) : (dv - delta);
                         const float num = H16 ? diff : ((a.metric == 0) ? sg + diff : diff);
                         if (H16 ? !(se < INFINITY) : se == 0.f) {
                             kind = 0;
                             pass = num < 0.f;
                         } else {
-                            const float A = H16 ? ((a.metric == 0) ? fmaf(diff, se, sg) * inv_qn : diff * se)
-                                                : num * __builtin_amdgcn_rcpf((a.metric == 0 ? qn : 1.f) * se);
+                            const float A = H16 ? ((a.metric != 1) ? fmaf(diff, se, sg) * inv_qn : diff * se)
+                                                : num * __builtin_amdgcn_rcpf((a.metric != 1 ? qn : 1.f) * se);
                             if (A >= 1.f) {
                                 kind = 1;
                                 pass = false;

@@ -358,7 +358,7 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     if (!base || !graph || !dirs_a || !dirs_b || !index_mem || !ws)
         return fail(PEOS_EINVAL, "null device pointer");
     if (entry < 0 || entry >= n) return fail(PEOS_EINVAL, "entry=%d out of range", entry);
-    if (metric != PEOS_METRIC_L2 && metric != PEOS_METRIC_ANGULAR)
+    if (metric != PEOS_METRIC_L2 && metric != PEOS_METRIC_ANGULAR && metric != PEOS_METRIC_IP)
         return fail(PEOS_EINVAL, "metric=%d", metric);
     if (index_bytes < need) return fail(PEOS_ENOSPACE, "index_bytes %zu < %zu", index_bytes, need);
     if (ws_bytes < need_ws) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %zu", ws_bytes, need_ws);

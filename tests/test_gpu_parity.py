@@ -54,6 +54,17 @@ def angular():
     return Case(ANG)
 
 
+# inner product (MIPS) on Gaussian clusters: base norms spread over about
+# 10..25, graph from l2 neighbours (an input; parity does not depend on it)
+IPW = W.Workload("ip_gmm_3k_d64", 3000, 100, 64, 16, 32, 4, 16, W.IP, "gmm10", 0.1, 10, 32, 1006)
+
+
+@pytest.fixture(scope="module")
+def ip():
+    print("[gpu] building inner-product workload", flush=True)
+    return Case(IPW)
+
+
 # ---------------------------------------------------------------------------
 # steps (1)-(3): edge records
 # ---------------------------------------------------------------------------
@@ -68,7 +79,7 @@ def read_records(case):
     return codes[:, :, :L + 1], sc.reshape(n, R, 4)
 
 
-@pytest.mark.parametrize("which", ["tiny", "angular"])
+@pytest.mark.parametrize("which", ["tiny", "angular", "ip"])
 def test_edge_records_match_oracle(which, request):
     case = request.getfixturevalue(which)
     w = case.w
@@ -110,7 +121,7 @@ def test_build_rejects_bad_graph(tiny):
 # ---------------------------------------------------------------------------
 # step (5): projection tables (matrix cores)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("which", ["tiny", "angular"])
+@pytest.mark.parametrize("which", ["tiny", "angular", "ip"])
 def test_query_tables_match_oracle(which, request):
     case = request.getfixturevalue(which)
     w = case.w
@@ -154,7 +165,7 @@ def recall(case, ids, k):
     return np.mean([len(set(ids[i][:k]) & set(gt[i])) / k for i in range(len(ids))])
 
 
-@pytest.mark.parametrize("which", ["tiny", "angular"])
+@pytest.mark.parametrize("which", ["tiny", "angular", "ip"])
 @pytest.mark.parametrize("mode", [P.PEOS_MODE_PEOS, P.PEOS_MODE_EXHAUSTIVE])
 @pytest.mark.parametrize("pool_mul", [0, 1, 2])
 def test_search_matches_oracle(which, mode, pool_mul, request):
@@ -553,3 +564,15 @@ def test_simhash_search_matches_oracle(simhash_case, pool_mul, eps):
 def test_simhash_mode_needs_signatures(tiny):
     with pytest.raises(P.PeosError):
         P.search(tiny.index, tiny.qt, 10, 32, eps=0.1, mode=P.PEOS_MODE_SIMHASH)
+
+
+def test_inner_product_prunes_and_scales(ip):
+    """Inner product with the unbounded queue: the test runs (H-tests and
+    rejections happen), and a query scaled by 8 takes the same path with
+    distances times 8 (A_r carries 1/|q|)."""
+    w = ip.w
+    a = run(ip, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, 0)
+    b = run(ip, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, 0, queries=(8.0 * ip.q).astype(np.float32))
+    assert a[2][:, 6].sum() > 0 and (a[2][:, 8] < a[2][:, 3]).any()
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
+    assert np.array_equal(8.0 * a[1], b[1])

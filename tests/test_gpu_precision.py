@@ -77,6 +77,13 @@ def ang():
                            "sphere500", 0.1, 10, 32, 1007))
 
 
+@pytest.fixture(scope="module")
+def ipc():
+    print("[gpu] precision: inner-product workload", flush=True)
+    return Case(W.Workload("prec_ip_3k_d64", 3000, 100, 64, 16, 32, 4, 16, W.IP, "gmm10", 0.1, 10,
+                           32, 1009))
+
+
 def half_adjacent(got, ref):
     """got equals ref or is the adjacent half (a straddled rounding boundary)."""
     g = got.astype(np.float16)
@@ -87,7 +94,7 @@ def half_adjacent(got, ref):
     return same, same | (g == up) | (g == dn)
 
 
-@pytest.mark.parametrize("which", ["gauss", "ang"])
+@pytest.mark.parametrize("which", ["gauss", "ang", "ipc"])
 def test_precision_records(which, request):
     case = request.getfixturevalue(which)
     w = case.w
@@ -110,8 +117,8 @@ def test_precision_records(which, request):
     valid = case.g >= 0
     assert np.array_equal(codes[valid], rc[valid])
     ne, wreg, wres, ge = (rs[..., i][valid] for i in range(4))
-    if w.metric == W.ANGULAR:
-        ge = np.zeros_like(ge)  # the angular test has no g_e term
+    if w.metric != W.L2:
+        ge = np.zeros_like(ge)  # the angular and inner-product tests have no g_e term
     want = np.stack([np.where(ne > 0, ge / np.where(ne > 0, ne, 1), 0.0),
                      np.where(ne > 0, 1.0 / np.where(ne > 0, ne, 1), np.inf),
                      wreg, np.sqrt(w.L) * wres], 1)
@@ -162,7 +169,7 @@ def test_bf16_traversal_on_exact_data_equals_fp32_path(ints, mode):
     assert not res["bad"], res["bad"][:5]
 
 
-@pytest.mark.parametrize("which", ["gauss", "ang"])
+@pytest.mark.parametrize("which", ["gauss", "ang", "ipc"])
 @pytest.mark.parametrize("pool_mul", [0, 1])
 def test_bf16_traversal_matches_oracle(which, pool_mul, request):
     """bfloat16 traversal + single-precision re-rank: exact parity on
@@ -178,7 +185,7 @@ def test_bf16_traversal_matches_oracle(which, pool_mul, request):
     assert res["checked"] >= 0.8 * len(ids)
 
 
-@pytest.mark.parametrize("which", ["gauss", "ang"])
+@pytest.mark.parametrize("which", ["gauss", "ang", "ipc"])
 @pytest.mark.parametrize("flags", [P.PEOS_FLAG_FP16, P.PEOS_FLAG_FP16 | P.PEOS_FLAG_BF16_BASE])
 def test_half_form_against_oracle(which, flags, request):
     """Halves for scalars and tables: most queries identical to the oracle's
@@ -200,6 +207,8 @@ def test_half_form_against_oracle(which, flags, request):
         row = ids[i][valid[i]]
         if w.metric == W.L2:
             exact = ((xs[row] - case.q[i]) ** 2).sum(1)
+        elif w.metric == W.IP:
+            exact = -(xs[row] @ case.q[i].astype(np.float64))
         else:
             exact = 1.0 - xs[row] @ case.q[i].astype(np.float64) / np.linalg.norm(case.q[i])
         assert np.all(np.abs(d[i][valid[i]] - exact) <= 1e-5 * np.abs(exact) + 1e-6)
