@@ -36,6 +36,8 @@ COUNTERS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_l
             "test_h", "test_zero", "passes", "ndist", "inserted")
 F_HT, F_A1, F_A0, F_DELTA, F_ORDER = 1, 2, 4, 8, 16
 LP_BF16_BASE, LP_FP16 = 1, 2
+LP_COMPACT = 8  # compact records: L <= 4, w_reg = 1, w_res = 0, 8-bit scalars, quantile table
+COMPACT_LUT_BINS = 256
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "peos_oracle.c")
@@ -84,6 +86,13 @@ def _load():
         lib.oracle_simhash_bits.argtypes = [P, i32, P, i32, P]
         lib.oracle_simhash_bits.restype = None
         lib.oracle_dimension_permutation.restype = i32
+        lib.oracle_compact_lut.argtypes = [i32, i32, f64, P]
+        lib.oracle_compact_lut.restype = None
+        lib.oracle_compact_tables.argtypes = [P, i64, i32, P, i32, i32, i32, P, P, P, P]
+        lib.oracle_compact_tables.restype = i32
+        lib.oracle_compact_test.argtypes = [P, i32, i32, P, P, i32, i32, i32, P, P, i32, f64, f64,
+                                            f64, P]
+        lib.oracle_compact_test.restype = i32
         lib.oracle_round_half.argtypes = [f64]
         lib.oracle_round_half.restype = f64
         lib.oracle_round_bf16.argtypes = [ctypes.c_float]
@@ -249,6 +258,47 @@ def simhash_bits(v, C):
     bits = np.zeros((nb + 63) // 64, np.uint64)
     _load().oracle_simhash_bits(_p(v), v.shape[0], _p(C), nb, _p(bits))
     return bits
+
+
+def compact_lut(L, m, eps):
+    """Quantile table of the compact form: entry b = T(b/256) of step (6) with
+    w_reg = 1, w_res = 0, rounded down to float32 (see peos_oracle.c)."""
+    out = np.zeros(COMPACT_LUT_BINS, np.float32)
+    _load().oracle_compact_lut(int(L), int(m), float(eps), _p(out))
+    return out
+
+
+def compact_tables(base, graph, L, metric, perm=None):
+    """Compact records: hdr (n, 4) float32 {g_lo, g_step, i_lo, i_step} per
+    node; cg, ci (n, R) uint8 codes of g_e/|e| (floor) and 1/|e| (nearest;
+    255 = zero-length edge)."""
+    base = _f32(base)
+    graph = np.ascontiguousarray(graph, dtype=np.int32)
+    n, d = base.shape
+    R = graph.shape[1]
+    hdr = np.zeros((n, 4), np.float32)
+    cg = np.zeros((n, R), np.uint8)
+    ci = np.zeros((n, R), np.uint8)
+    pa = None if perm is None else np.ascontiguousarray(perm, dtype=np.int32)
+    rc = _load().oracle_compact_tables(_p(base), n, d, _p(graph), R, int(L), int(metric), _p(pa),
+                                       _p(hdr), _p(cg), _p(ci))
+    if rc:
+        raise ValueError("bad compact-table arguments")
+    return hdr, cg, ci
+
+
+def compact_test(hdr, cg, ci, codes, q, L, m, A, B, metric, eps, dv, delta):
+    """One compact-form test on decoded codes and traversal distances.
+    Returns (pass, A_r, H, T, kind)."""
+    hdr, q, A, B = _f32(hdr), _f32(q), _f32(A), _f32(B)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    out = np.zeros(4, np.float64)
+    ok = _load().oracle_compact_test(_p(hdr), int(cg), int(ci), _p(codes), _p(q), q.shape[0],
+                                     int(L), int(m), _p(A), _p(B), int(metric), float(eps),
+                                     float(dv), float(delta), _p(out))
+    if ok < 0:
+        raise ValueError("bad compact-test arguments")
+    return bool(ok), out[0], out[1], out[2], int(out[3])
 
 
 def dimension_permutation(base, graph, L):

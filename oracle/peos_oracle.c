@@ -580,6 +580,248 @@ void oracle_simhash_bits(const float* v, int d, const float* C, int nb, uint64_t
 }
 
 /* ------------------------------------------------------------------ */
+/* The compact form (experiments, "Indexing Cost" and "Scalability")   */
+/* ------------------------------------------------------------------ */
+/*
+ * For L <= 4 the paper keeps per edge only the L sub-vector codes and two
+ * one-byte scalars, and sets w_reg = 1, w_res = 0 for every edge (the
+ * residual part is small at such L).  The test then reads
+ *   H = sum_{i=1..L} sgn(e[i]) T_i[|e[i]|],
+ *   T(A) = A eta + c_eps sqrt(1 - L A^2 / (L+1))   (step (6) with w = (1, 0)),
+ * and takes T from a lookup table over A: Sec. 4.3 allows a quantile slightly
+ * below the true one, which keeps the guarantee's direction because T grows
+ * with A.
+ *
+ * Readings (the paper gives no byte format):
+ *  - the two bytes of an edge carry g_e/|e| (l2 only: it combines |u|^2 with
+ *    the node's |v|^2, the paper's "norm of u") and 1/|e| ("norm of e"), each
+ *    an affine 8-bit code against a range kept once per node as four floats
+ *    {g_lo, g_step, i_lo, i_step};
+ *  - the codes are directed so that the test's A_r never exceeds the exact
+ *    one: g_e/|e| is rounded down; 1/|e| is rounded to nearest and decoded
+ *    half a step up when dist_v - delta < 0, half a step down otherwise, so
+ *    (dist_v - delta)/|e| is never overestimated.  Code 255 of 1/|e| marks a
+ *    zero-length edge, decided by the sign of the numerator;
+ *  - the table has COMPACT_LUT_BINS bins over A in [0, 1); bin b holds
+ *    T(b / bins) rounded down to single precision, the smallest T of the bin;
+ *  - the integer codes are decided in single precision in this order:
+ *    S_i = fmaf chain of e_k^2 over block i (k ascending, the test's
+ *    coordinates), ne2 = S_1 + ... + S_L (sequential adds), ne = sqrtf(ne2);
+ *    |x|^2 = fmaf chain of x_k^2 over the original coordinates, ascending;
+ *    gp = (0.5f * (|u|^2 - |v|^2)) / ne (zero for angular and inner product);
+ *    ie = 1.0f / ne; g_lo, g_hi, i_lo, i_hi = min / max over the node's edges
+ *    with ne > 0; g_step = (g_hi - g_lo) / 255.0f, i_step = (i_hi - i_lo) /
+ *    254.0f; cg = floorf((gp - g_lo) / g_step) in [0, 255], ci = rintf((ie -
+ *    i_lo) / i_step) in [0, 254] (0 when the step is 0).
+ */
+#define LP_COMPACT 8
+#define COMPACT_LUT_BINS 256
+static double dot64(const float* a, const float* b, int d);
+#define COMPACT_ZERO_EDGE 255
+
+typedef struct {
+    float glo, gstep, ilo, istep;
+} compact_hdr;
+
+static float sqnorm32(const float* x, int d)
+{
+    float acc = 0.0f;
+    for (int k = 0; k < d; ++k) acc = fmaf(x[k], x[k], acc);
+    return acc;
+}
+
+/* gp and ie of edge (v, u) with xv_t, xu_t on the test's coordinates; returns
+   0 for a zero-length edge */
+static int compact_values(const float* xv_t, const float* xu_t, float nv2, float nu2, int d,
+                          int L, int metric, float* gp, float* ie)
+{
+    const int dp = d / L;
+    float ne2 = 0.0f;
+    for (int i = 0; i < L; ++i) {
+        float ss = 0.0f;
+        for (int t = 0; t < dp; ++t) {
+            const float e = xu_t[i * dp + t] - xv_t[i * dp + t];
+            ss = fmaf(e, e, ss);
+        }
+        ne2 = ne2 + ss;
+    }
+    const float ne = sqrtf(ne2);
+    *gp = 0.0f;
+    *ie = 0.0f;
+    if (!(ne > 0.0f)) return 0;
+    if (metric == OR_L2) *gp = (0.5f * (nu2 - nv2)) / ne;
+    *ie = 1.0f / ne;
+    return 1;
+}
+
+/* header of node v and the scalar codes of its R edges (padding edges 0);
+   wv, wu: d floats of work space each */
+static void compact_node(const float* base, int d, const int32_t* row, int R, int L, int metric,
+                         const int32_t* perm, int32_t v, float* wv, float* wu, float* gpw,
+                         float* iew, int* kindw, compact_hdr* h, uint8_t* cg, uint8_t* ci)
+{
+    const float* xv = base + (size_t)v * d;
+    const float nv2 = sqnorm32(xv, d);
+    for (int k = 0; k < d; ++k) wv[k] = perm ? xv[perm[k]] : xv[k];
+    float glo = INFINITY, ghi = -INFINITY, ilo = INFINITY, ihi = -INFINITY;
+    for (int j = 0; j < R; ++j) {
+        const int32_t u = row[j];
+        kindw[j] = 0;
+        if (u < 0) continue;
+        const float* xu = base + (size_t)u * d;
+        for (int k = 0; k < d; ++k) wu[k] = perm ? xu[perm[k]] : xu[k];
+        if (compact_values(wv, wu, nv2, sqnorm32(xu, d), d, L, metric, &gpw[j], &iew[j])) {
+            kindw[j] = 1;
+            if (gpw[j] < glo) glo = gpw[j];
+            if (gpw[j] > ghi) ghi = gpw[j];
+            if (iew[j] < ilo) ilo = iew[j];
+            if (iew[j] > ihi) ihi = iew[j];
+        } else {
+            kindw[j] = 2;
+        }
+    }
+    if (!(glo <= ghi)) glo = ghi = ilo = ihi = 0.0f; /* no edge of nonzero length */
+    h->glo = glo;
+    h->gstep = (ghi - glo) / 255.0f;
+    h->ilo = ilo;
+    h->istep = (ihi - ilo) / 254.0f;
+    for (int j = 0; j < R; ++j) {
+        cg[j] = 0;
+        ci[j] = 0;
+        if (kindw[j] == 2) ci[j] = COMPACT_ZERO_EDGE;
+        if (kindw[j] != 1) continue;
+        if (h->gstep > 0.0f) {
+            float c = floorf((gpw[j] - glo) / h->gstep);
+            cg[j] = (uint8_t)(c < 0.0f ? 0.0f : (c > 255.0f ? 255.0f : c));
+        }
+        if (h->istep > 0.0f) {
+            float c = rintf((iew[j] - ilo) / h->istep);
+            ci[j] = (uint8_t)(c < 0.0f ? 0.0f : (c > 254.0f ? 254.0f : c));
+        }
+    }
+}
+
+/* the quantile table: entry b = T(b / bins) with w_reg = 1, w_res = 0,
+   rounded down to single precision */
+void oracle_compact_lut(int L, int m, double eps, float* lut)
+{
+    const double eta = sqrt(2.0 * L * log((double)m));
+    const double c_eps = oracle_norm_ppf(eps);
+    for (int b = 0; b < COMPACT_LUT_BINS; ++b) {
+        const double A = (double)b / COMPACT_LUT_BINS;
+        const double t = oracle_threshold(A, 1.0, 0.0, L, eta, c_eps);
+        float f = (float)t;
+        if ((double)f > t) f = nextafterf(f, -INFINITY);
+        lut[b] = f;
+    }
+}
+
+/*
+ * Step (6) in the compact form, on the decoded scalars and the traversal
+ * distances dist_v, delta (A_r = (gp + diff ie) / |q| for l2 and inner
+ * product, diff ie for angular, diff = (dist_v - delta)/2 for l2 and
+ * dist_v - delta otherwise).  codes[1..L] are the sub-vector codes.
+ */
+static int routing_test_compact(const test_params* tp, const compact_hdr* h, uint8_t cg,
+                                uint8_t ci, const uint8_t* codes, const double* table,
+                                const float* lut, double dv, double delta, double qnorm,
+                                double* outA, double* outH, double* outT, int* kind, int* flags,
+                                int v_is_p)
+{
+    const double tau = tp->tau;
+    *outA = NAN;
+    *outH = NAN;
+    *outT = NAN;
+    const double diff = tp->metric == OR_L2 ? 0.5 * (dv - delta) : (dv - delta);
+    if (ci == COMPACT_ZERO_EDGE) {
+        *kind = 0;
+        if (!v_is_p && fabs(diff) <= tau * (fabs(dv) + fabs(delta))) *flags |= F_A0;
+        return diff < 0.0;
+    }
+    const double gp = tp->metric == OR_L2 ? (double)h->glo + (double)cg * (double)h->gstep : 0.0;
+    const double ie = (double)h->ilo + ((double)ci + (diff < 0.0 ? 0.5 : -0.5)) * (double)h->istep;
+    const double A = tp->metric == OR_ANGULAR ? diff * ie : (gp + diff * ie) / qnorm;
+    const int exact0 = v_is_p && tp->metric != OR_L2;
+    *outA = A;
+    if (fabs(A - 1.0) < tau) *flags |= F_A1;
+    if (!exact0 && fabs(A) < tau) *flags |= F_A0;
+    if (A >= 1.0) { *kind = 1; return 0; }
+    if (A <= 0.0) { *kind = 2; return 1; }
+    *kind = 3;
+    double H = 0.0;
+    for (int i = 1; i <= tp->L; ++i) H += lookup(table, tp->m, i, codes[i]);
+    const double x = A * COMPACT_LUT_BINS;
+    int b = (int)floor(x);
+    if (b > COMPACT_LUT_BINS - 1) b = COMPACT_LUT_BINS - 1;
+    /* A within single-precision rounding of a bin edge: the GPU evaluates A
+       with about eight roundings of 2^-24 relative to the magnitude of the
+       terms of its numerator (the decodes, the product, the sum, 1/|q|), so
+       a margin of 2^-20 of that magnitude covers it; inside it the two
+       precisions may take neighbouring bins */
+    const double amag = tp->metric == OR_ANGULAR ? fabs(diff * ie)
+                                                 : (fabs(gp) + fabs(diff * ie)) / qnorm;
+    if (fabs(x - floor(x + 0.5)) < ldexp(amag, -20) * COMPACT_LUT_BINS) *flags |= F_HT;
+    const double T = (double)lut[b];
+    *outH = H;
+    *outT = T;
+    if (fabs(H - T) < tau * (fabs(H) + fabs(T) + 1e-30)) *flags |= F_HT;
+    return H >= T;
+}
+
+/* Public: compact records of a graph.  hdr: n x 4 floats {g_lo, g_step, i_lo,
+   i_step}; cg, ci: n x R bytes.  perm optional.  Returns 0, or -1. */
+int oracle_compact_tables(const float* base, int64_t n, int d, const int32_t* graph, int R, int L,
+                          int metric, const int32_t* perm, float* hdr, uint8_t* cg, uint8_t* ci)
+{
+    if (n <= 0 || d <= 0 || R <= 0 || L <= 0 || L > 4 || d % L) return -1;
+    float* wv = (float*)malloc(sizeof(float) * (size_t)d);
+    float* wu = (float*)malloc(sizeof(float) * (size_t)d);
+    float* gpw = (float*)malloc(sizeof(float) * (size_t)R);
+    float* iew = (float*)malloc(sizeof(float) * (size_t)R);
+    int* kw = (int*)malloc(sizeof(int) * (size_t)R);
+    for (int64_t v = 0; v < n; ++v) {
+        compact_hdr h;
+        compact_node(base, d, graph + (size_t)v * R, R, L, metric, perm, (int32_t)v, wv, wu, gpw,
+                     iew, kw, &h, cg + (size_t)v * R, ci + (size_t)v * R);
+        hdr[4 * v + 0] = h.glo;
+        hdr[4 * v + 1] = h.gstep;
+        hdr[4 * v + 2] = h.ilo;
+        hdr[4 * v + 3] = h.istep;
+    }
+    free(wv);
+    free(wu);
+    free(gpw);
+    free(iew);
+    free(kw);
+    return 0;
+}
+
+/* Public: one compact test (pins).  hdr: 4 floats; codes: L+1 bytes (code 0
+   unused); dv, delta: the traversal distances.  out = {A, H, T, kind}. */
+int oracle_compact_test(const float* hdr, int cg, int ci, const uint8_t* codes, const float* q,
+                        int d, int L, int m, const float* A, const float* B, int metric,
+                        double eps, double dv, double delta, double* out)
+{
+    if (L <= 0 || L > 4 || d % L) return -1;
+    double* table = (double*)malloc(sizeof(double) * (size_t)(L + 1) * m);
+    float lut[COMPACT_LUT_BINS];
+    oracle_query_table(q, d, L, m, A, B, table);
+    oracle_compact_lut(L, m, eps, lut);
+    test_params tp = {sqrt(2.0 * L * log((double)m)), oracle_norm_ppf(eps), 1e-5, L, m, metric};
+    compact_hdr h = {hdr[0], hdr[1], hdr[2], hdr[3]};
+    double a, hh, t;
+    int kind, flags = 0;
+    int pass = routing_test_compact(&tp, &h, (uint8_t)cg, (uint8_t)ci, codes, table, lut, dv,
+                                    delta, sqrt(dot64(q, q, d)), &a, &hh, &t, &kind, &flags, 0);
+    out[0] = a;
+    out[1] = hh;
+    out[2] = t;
+    out[3] = kind;
+    free(table);
+    return pass;
+}
+
+/* ------------------------------------------------------------------ */
 /* Optional dimension permutation (appendix "Dimension Permutation")   */
 /* ------------------------------------------------------------------ */
 /*
@@ -773,8 +1015,19 @@ typedef struct {
  *  - a survivor enters the list when R was not full or its distance is
  *    < delta.
  */
+/* work space of the compact form: the node header and edge codes of the
+   node being expanded, and the quantile table */
+typedef struct {
+    compact_hdr h;
+    uint8_t *cg, *ci;
+    float *wv, *wu, *gpw, *iew;
+    int* kw;
+    float lut[COMPACT_LUT_BINS];
+} compact_ws;
+
 static void search_one(const search_job* j, int64_t qi, const test_params* tp, uint8_t* visited,
-                       rentry* R, rentry* S, double* table, float* fw1, float* fw2, double* dw)
+                       rentry* R, rentry* S, double* table, float* fw1, float* fw2, double* dw,
+                       compact_ws* cw)
 {
     const int d = j->d;
     const float* q = j->queries + (size_t)qi * d;
@@ -850,6 +1103,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             else r = -dot64(xp, q, d);
         }
         int ns = 0;
+        int have_hdr = 0;
         for (int e = 0; e < j->R; ++e) {
             int32_t u = j->graph[(size_t)v * j->R + e];
             if (u < 0) continue;
@@ -879,6 +1133,36 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
                 int kind;
                 pass = routing_test_simhash(tp, sqrt(ne2), j->nb - diff, j->nb, num, qnorm, j->eps,
                                             &kind, &flags, v == p);
+                cnt[C_TESTS]++;
+                cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
+                if (pass) cnt[C_PASSES]++;
+            } else if (full && j->mode == OR_MODE_PEOS && (j->lowp & LP_COMPACT)) {
+                /* compact form: the node's header and scalar codes (a build
+                   product, taken over all of v's edges), the sub-vector
+                   codes of this edge */
+                if (!have_hdr) {
+                    compact_node(j->base, d, j->graph + (size_t)v * j->R, j->R, j->L, j->metric,
+                                 j->perm, v, cw->wv, cw->wu, cw->gpw, cw->iew, cw->kw, &cw->h,
+                                 cw->cg, cw->ci);
+                    have_hdr = 1;
+                }
+                uint8_t codes[257];
+                if (j->perm) {
+                    float* xvp = fw1 + d;
+                    float* xup = fw2 + d;
+                    for (int k = 0; k < d; ++k) {
+                        xvp[k] = xv[j->perm[k]];
+                        xup[k] = xu[j->perm[k]];
+                    }
+                    edge_codes_fp32(xvp, xup, d, j->L, j->m, j->A, j->B, fw1, fw2, codes, NULL);
+                } else {
+                    edge_codes_fp32(xv, xu, d, j->L, j->m, j->A, j->B, fw1, fw2, codes, NULL);
+                }
+                double A, H, T;
+                int kind;
+                pass = routing_test_compact(tp, &cw->h, cw->cg[e], cw->ci[e], codes, table,
+                                            cw->lut, dv, delta, qnorm, &A, &H, &T, &kind, &flags,
+                                            v == p);
                 cnt[C_TESTS]++;
                 cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
                 if (pass) cnt[C_PASSES]++;
@@ -1004,8 +1288,24 @@ static void* search_worker(void* arg)
     float* fw1 = (float*)malloc(sizeof(float) * 2 * (size_t)j->d);
     float* fw2 = (float*)malloc(sizeof(float) * 2 * (size_t)j->d);
     double* dw = (double*)malloc(sizeof(double) * j->d);
+    compact_ws cw;
+    cw.cg = (uint8_t*)malloc((size_t)j->R);
+    cw.ci = (uint8_t*)malloc((size_t)j->R);
+    cw.wv = (float*)malloc(sizeof(float) * (size_t)j->d);
+    cw.wu = (float*)malloc(sizeof(float) * (size_t)j->d);
+    cw.gpw = (float*)malloc(sizeof(float) * (size_t)j->R);
+    cw.iew = (float*)malloc(sizeof(float) * (size_t)j->R);
+    cw.kw = (int*)malloc(sizeof(int) * (size_t)j->R);
+    if (j->lowp & LP_COMPACT) oracle_compact_lut(j->L, j->m, j->eps, cw.lut);
     for (int64_t qi = j->q0; qi < j->q1; ++qi)
-        search_one(j, qi, &tp, visited, R, S, table, fw1, fw2, dw);
+        search_one(j, qi, &tp, visited, R, S, table, fw1, fw2, dw, &cw);
+    free(cw.cg);
+    free(cw.ci);
+    free(cw.wv);
+    free(cw.wu);
+    free(cw.gpw);
+    free(cw.iew);
+    free(cw.kw);
     free(visited);
     free(R);
     free(S);
@@ -1053,6 +1353,7 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     if (mode == OR_MODE_PEOS && (L <= 0 || d % L || L > 255 || m < 2 || 2 * m > 256)) return -1;
     if (mode != OR_MODE_EXHAUSTIVE && !(eps > 0.0 && eps <= 0.5)) return -1;
     if (mode == OR_MODE_SIMHASH && (!simhash || nb < 1 || nb > 256)) return -1;
+    if ((lowp & LP_COMPACT) && (L > 4 || (lowp & LP_FP16) || mode == OR_MODE_SIMHASH)) return -1;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     if (nthreads > nq) nthreads = (int)(nq > 0 ? nq : 1);

@@ -1038,3 +1038,183 @@ def test_simhash_vanishing_eps_reproduces_exhaustive(metric):
     b = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, mode=O.MODE_EXHAUSTIVE)
     assert np.array_equal(a["ids"], b["ids"])
     assert a["counters"][:, 9].sum() <= b["counters"][:, 9].sum()
+
+
+# ---------------------------------------------------------------------------
+# the compact form (experiments, "Indexing Cost" and "Scalability"): L <= 4,
+# w_reg = 1, w_res = 0, 8-bit scalars, quantile table
+# ---------------------------------------------------------------------------
+def _threshold_w10(A, L, m, eps):
+    """T(A) with w_reg = 1, w_res = 0, from scipy's normal quantile."""
+    A = np.asarray(A, np.float64)
+    return stats.norm.ppf(eps, loc=A * math.sqrt(2 * L * math.log(m)),
+                          scale=np.sqrt(1.0 - L * A * A / (L + 1)))
+
+
+@pytest.mark.parametrize("L,m,eps", [(2, 16, 0.1), (4, 16, 0.2), (1, 128, 0.05), (3, 32, 0.5)])
+def test_compact_lut_is_a_conservative_step_of_the_threshold(L, m, eps):
+    """Entry b is T(b/256) rounded down to float32; for every A of bin b the
+    entry is at most T(A) (T increases with A) and falls short of it by at
+    most the rise of T over the bin."""
+    lut = O.compact_lut(L, m, eps).astype(np.float64)
+    edges = np.arange(O.COMPACT_LUT_BINS) / O.COMPACT_LUT_BINS
+    te = _threshold_w10(edges, L, m, eps)
+    assert np.all(lut <= te + 1e-12 * np.abs(te) + 1e-15)
+    assert np.all(te - lut <= 2.0 ** -22 * np.abs(te) + 1e-15)
+    A = np.random.default_rng(L).uniform(0, 1, 20000)
+    b = np.floor(A * O.COMPACT_LUT_BINS).astype(int)
+    tA = _threshold_w10(A, L, m, eps)
+    assert np.all(lut[b] <= tA + 1e-12)
+    rise = _threshold_w10((b + 1) / O.COMPACT_LUT_BINS, L, m, eps) - te[b]
+    assert np.all(tA - lut[b] <= rise + 2.0 ** -22 * np.abs(te[b]) + 1e-12)
+
+
+def _compact_case(metric, n=1500):
+    w = W.TINY.with_sizes(n=n, nq=40)
+    x, q = W.make_base(w), W.make_queries(w)
+    if metric == W.ANGULAR:
+        x /= np.linalg.norm(x, axis=1, keepdims=True)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    return w, x, q, g, entry
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
+def test_compact_codes_decode_within_their_step(metric):
+    """Decoded g_e/|e| lies in [exact - g_step, exact] and decoded 1/|e|
+    within half an i_step of the exact value (up to the single-precision
+    rounding of the values the codes are decided on); the node's ranges are
+    the min / max over its edges; a zero-length edge gets code 255."""
+    w, x, q, g, entry = _compact_case(metric)
+    # a duplicate vector makes one zero-length edge
+    u0 = int(g[0, 0])
+    x = x.copy()
+    x[u0] = x[0]
+    L = 2
+    hdr, cg, ci = O.compact_tables(x, g, L, metric)
+    assert ci[0, 0] == 255
+    xs = x.astype(np.float64)
+    u = 2.0 ** -24
+    nz = 0
+    for v in range(0, len(x), 7):
+        glo, gstep, ilo, istep = hdr[v].astype(np.float64)
+        gps, ies = [], []
+        for j, uu in enumerate(g[v]):
+            if uu < 0:
+                continue
+            e = xs[uu] - xs[v]
+            ne = np.linalg.norm(e)
+            if ne == 0:
+                assert ci[v, j] == 255
+                continue
+            nu2, nv2 = xs[uu] @ xs[uu], xs[v] @ xs[v]
+            gp = 0.5 * (nu2 - nv2) / ne if metric == W.L2 else 0.0
+            ie = 1.0 / ne
+            # single-precision evaluation error of gp and ie
+            tg = (w.d + 4) * u * (nu2 + nv2) / ne + 4 * u * abs(gp)
+            ti = (w.d + 4) * u * ie
+            gh = glo + cg[v, j] * gstep
+            ih = ilo + ci[v, j] * istep
+            assert gh <= gp + tg + 1e-6 * gstep
+            assert gp - gh <= gstep * (1 + 1e-5) + tg
+            assert abs(ih - ie) <= 0.5 * istep * (1 + 1e-5) + ti
+            gps.append(gp)
+            ies.append(ie)
+            nz += 1
+        if gps:
+            assert abs(glo - min(gps)) <= 1e-5 * max(1.0, abs(min(gps)))
+            assert abs(glo + 255 * gstep - max(gps)) <= 1e-5 * max(1.0, abs(max(gps)))
+            assert abs(ilo - min(ies)) <= 1e-5 * min(ies)
+            assert abs(ilo + 254 * istep - max(ies)) <= 1e-5 * max(ies)
+    assert nz > 1000
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
+def test_compact_test_never_overestimates_A_and_passes_what_the_exact_test_passes(metric):
+    """With the node's codes, the compact test's A_r is at most the exact
+    A_r (scalars unquantized), and the compact test passes every edge that
+    the w = (1, 0) test on exact scalars and the exact quantile passes; it
+    passes some more (the price of 8-bit scalars and the table)."""
+    rng = np.random.default_rng(31 + metric)
+    L, m, d, eps = 2, 16, 32, 0.1
+    A_, B_ = W.make_directions(L, m, d, 7)
+    graph = np.full((9, 8), -1, np.int32)
+    graph[0] = np.arange(1, 9)
+    extra = checked = 0
+    for _ in range(300):
+        pts = rng.normal(size=(9, d)) * rng.uniform(0.5, 2.0, size=(9, 1))
+        pts[1:] = pts[0] + 0.5 * (pts[1:] - pts[0])
+        q = rng.normal(size=d)
+        xp = rng.normal(size=d)
+        if metric == W.ANGULAR:
+            pts /= np.linalg.norm(pts, axis=1, keepdims=True)
+            xp /= np.linalg.norm(xp)
+        pts, q, xp = (a.astype(np.float32) for a in (pts, q, xp))
+        hdr, cg, ci = O.compact_tables(pts, graph, L, metric)
+        x64, q64, p64 = pts.astype(np.float64), q.astype(np.float64), xp.astype(np.float64)
+        if metric == W.L2:
+            dist = lambda y: ((y - q64) ** 2).sum()
+        elif metric == W.IP:
+            dist = lambda y: -(y @ q64)
+        else:
+            dist = lambda y: 1.0 - y @ q64 / np.linalg.norm(q64)
+        dv, delta = dist(x64[0]), dist(p64)
+        table = O.query_table(q, L, m, A_, B_)
+        qn = np.linalg.norm(q64)
+        for j in range(1, 9):
+            codes, _, _ = O.edge_record(pts[0], pts[j], L, m, A_, B_)
+            ok, Ac, Hc, Tc, kind = O.compact_test(hdr[0], cg[0, j - 1], ci[0, j - 1], codes, q, L,
+                                                  m, A_, B_, metric, eps, dv, delta)
+            e = x64[j] - x64[0]
+            ne = np.linalg.norm(e)
+            if metric == W.L2:
+                Aex = (0.5 * (x64[j] @ x64[j] - x64[0] @ x64[0]) + 0.5 * (dv - delta)) / (qn * ne)
+            elif metric == W.IP:
+                Aex = (dv - delta) / (qn * ne)
+            else:
+                Aex = (dv - delta) / ne
+            assert Ac <= Aex + 1e-6 * (1 + abs(Aex))
+            H = sum((-1 if c >= m else 1) * table[i, c % m] for i, c in enumerate(codes) if i >= 1)
+            if Aex >= 1:
+                ok_ex = False
+            elif Aex <= 0:
+                ok_ex = True
+            else:
+                ok_ex = H >= float(_threshold_w10(Aex, L, m, eps))
+            if kind == 3:
+                assert Hc == pytest.approx(H, rel=1e-12, abs=1e-12)
+            if ok_ex:
+                assert ok, (Aex, Ac, H, Tc)
+            extra += ok and not ok_ex
+            checked += 1
+    assert checked == 2400 and extra > 0
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
+def test_compact_vanishing_eps_reproduces_exhaustive_search(metric):
+    """eps -> 0+: every table entry goes to -infinity's side, only A_r >= 1
+    prunes, and A_r is never overestimated, so the compact search returns
+    the exhaustive search's ids and distances with fewer distances."""
+    w, x, q, g, entry = _compact_case(metric, n=1000)
+    if metric == W.L2:
+        o = q[0] - 0.01
+        x, q = (x - o).astype(np.float32), (q - o).astype(np.float32)
+        g, entry = W.build_graph(x, w.R, w.cand)
+    L = 2
+    A, B = W.make_directions(L, w.m, w.d, 9)
+    ex = O.search(x, g, entry, q, 10, 16, L, w.m, A, B, metric, 0.1, mode=O.MODE_EXHAUSTIVE,
+                  precision=32)
+    pe = O.search(x, g, entry, q, 10, 16, L, w.m, A, B, metric, 1e-300, lowp=O.LP_COMPACT)
+    assert np.array_equal(ex["ids"], pe["ids"])
+    np.testing.assert_array_equal(ex["dist"], pe["dist"])
+    ci = O.COUNTERS.index
+    assert np.all(pe["counters"][:, ci("ndist")] <= ex["counters"][:, ci("ndist")])
+    assert pe["counters"][:, ci("test_ge1")].sum() > 0
+
+
+def test_compact_form_needs_L_at_most_4():
+    w, x, q, g, entry = _compact_case(W.L2, n=300)
+    A, B = W.make_directions(8, w.m, w.d, 9)
+    with pytest.raises(ValueError):
+        O.search(x, g, entry, q, 10, 16, 8, w.m, A, B, W.L2, 0.1, lowp=O.LP_COMPACT)
+    with pytest.raises(ValueError):
+        O.compact_tables(x, g, 8, W.L2)
