@@ -91,7 +91,7 @@ def main():
     ap.add_argument("--listcap", type=int, default=0,
                     help="with --profile-only: force an LDS list of this capacity")
     ap.add_argument("--mode", default="headline",
-                    choices=("headline", "batched", "serving", "precision"),
+                    choices=("headline", "batched", "serving", "precision", "compact"),
                     help="headline: the QPS-at-recall comparison (default); batched: one "
                          "captured launch over a batch of uneven k/ef; serving: the request "
                          "loop under Poisson arrivals")
@@ -128,6 +128,8 @@ def main():
         return serving(args)
     if args.mode == "precision":
         return precision(args)
+    if args.mode == "compact":
+        return compact(args)
 
     import paper_2402_11354_amd as P
     import workloads as W
@@ -537,6 +539,72 @@ def precision(args):
         "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L,
                    "m": w.m, "eps": w.eps, "stop_rule": "hnsw (pool=ef)"},
         "results": result,
+    }), flush=True)
+
+
+def compact(args):
+    """The compact records (L = 2, w_reg = 1, w_res = 0, two 8-bit scalars per
+    edge, quantile table) against the full records at the workload's L, on the
+    same graph, under the HNSW stopping rule: QPS at recall@10 >= target over
+    an ef sweep, and the bytes of an edge record."""
+    import torch
+
+    import paper_2402_11354_amd as P
+    import workloads as W
+
+    w, x, q, g, entry, index, gt_d = _setup(args.workload, args.n, args.nq, 10)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    Lc = 2
+    Ac, Bc = W.make_directions(Lc, w.m, w.d, w.seed + 2000)
+    comp = P.peos_build_tables(index._keep[0], index._keep[1], entry, Lc, w.m, T(Ac), T(Bc),
+                               w.metric, flags=P.PEOS_FLAG_COMPACT)
+    qt = T(q)
+    nq = w.nq
+    efs = [int(e) for e in args.efs.split(",")]
+    ws = torch.empty(P.peos_search_ws_bytes(index, nq, max(efs), max(efs)), dtype=torch.uint8,
+                     device=dev)
+    rows = {}
+    runs = [("full_L%d" % w.L, index, P.PEOS_MODE_PEOS, e) for e in (0.1, 0.2)]
+    runs += [("compact_L%d" % Lc, comp, P.PEOS_MODE_PEOS, e) for e in (0.1, 0.2)]
+    runs += [("exhaustive", index, P.PEOS_MODE_EXHAUSTIVE, 0.1)]
+    for label, ix, mode, eps in runs:
+        key = label if mode == P.PEOS_MODE_EXHAUSTIVE else f"{label}_eps{eps}"
+        pts = []
+        for ef in efs:
+            ids, dd, st = P.search(ix, qt, 10, ef, eps=eps, mode=mode, pool=ef, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                P.search(ix, qt, 10, ef, eps=eps, mode=mode, pool=ef, ws=ws)
+            torch.cuda.synchronize()
+            qps = nq * args.steps / (time.perf_counter() - t0)
+            rec = float(_recall(x, q, ids.cpu().numpy(), gt_d, 10, w.metric).mean())
+            s_ = st.cpu().numpy()
+            pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
+                            ndist=round(float(s_[:, 9].mean()), 1),
+                            tests=round(float(s_[:, 3].mean()), 1)))
+            log(f"compact {key} ef={ef}: recall={rec:.4f} qps={qps:.0f}")
+            if rec >= args.target + 0.02:
+                break
+        ok = [p_ for p_ in pts if p_["recall"] >= args.target]
+        rows[key] = dict(points=pts, at_target=(max(ok, key=lambda p_: p_["qps"]) if ok else None))
+    best = lambda pre: max((r["at_target"] for k_, r in rows.items()
+                            if k_.startswith(pre) and r["at_target"]),
+                           key=lambda p_: p_["qps"], default=None)
+    c, f, e = best("compact"), best("full"), best("exhaustive")
+    lay_c, lay_f = comp.layout(), index.layout()
+    print(json.dumps({
+        "metric": "QPS at recall@10>=0.95, compact records vs full records (same graph)",
+        "value": c["qps"] if c else None, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 (8-bit edge scalars)",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "m": w.m,
+                   "L_full": w.L, "L_compact": Lc, "stop_rule": "hnsw (pool=ef)"},
+        "record_bytes_per_node": {"full": lay_f.node_stride, "compact": lay_c.node_stride},
+        "at_target": {"compact": c, "full": f, "exhaustive": e},
+        "runs": rows,
     }), flush=True)
 
 

@@ -84,6 +84,21 @@ extern "C" {
  * [e . c_i >= 0] of the residual edge against the 64 vectors of
  * peos_build_options.simhash_dirs (for PEOS_MODE_SIMHASH). */
 #define PEOS_FLAG_SIMHASH 4
+/* PEOS_FLAG_COMPACT: the compact records of the experiments ("Indexing Cost",
+ * "Scalability"): for L <= 4, w_reg = 1 and w_res = 0 for every edge (no
+ * residual code), and two one-byte scalars per edge against ranges kept once
+ * per node.  Record of node v: {g_lo, g_step, i_lo, i_step} (4 floats), then
+ * 4 code bytes per edge (byte i-1 = e[i]), then 2 bytes per edge: cg =
+ * floor((g_e/|e| - g_lo)/g_step) and ci = rint((1/|e| - i_lo)/i_step), with
+ * ci = 255 for a zero-length edge (g_e/|e| is 0 for ANGULAR and IP).  The test
+ * decodes g = g_lo + cg g_step and 1/|e| = i_lo + (ci +- 1/2) i_step, the
+ * half step taken so that (dist_v - delta)/|e| is not overestimated, so its
+ * A_r is at most the exact one; H = sum_i sgn(e[i]) T_i[|e[i]|]; T is read
+ * from a table of 256 bins over A_r in [0, 1), bin b holding T(b/256) of
+ * step (6) with w = (1, 0), rounded down (the smallest T of the bin: T grows
+ * with A_r, so the quantile is never above the true one, as Sec. 4.3 allows).
+ * Needs L <= 4; does not combine with PEOS_FLAG_FP16 or PEOS_FLAG_SIMHASH. */
+#define PEOS_FLAG_COMPACT 8
 
 /* per-query status bits written to stats[.. + PEOS_STAT_STATUS] */
 #define PEOS_STATUS_ZERO_QUERY 1    /* |q| = 0 or not finite: outputs padded  */
@@ -118,7 +133,9 @@ typedef struct peos_graph peos_graph;
  * its sign (negative iff c >= m).  Scalars: edge j owns 4 floats at
  * scalars_offset + 16*j: g_e = (|u|^2 - |v|^2)/2 (zero for ANGULAR and IP), |e|,
  * w_reg, sqrt(L)*w_res; with PEOS_FLAG_FP16, 4 halves at scalars_offset + 8*j
- * (see PEOS_FLAG_FP16).  With PEOS_FLAG_BF16_BASE the bfloat16 copy of the
+ * (see PEOS_FLAG_FP16).  With PEOS_FLAG_COMPACT the record starts with the
+ * node header at offset 0, code_bytes = 4 and scalar_bytes = 2 (see
+ * PEOS_FLAG_COMPACT).  With PEOS_FLAG_BF16_BASE the bfloat16 copy of the
  * base (n x d) starts at bf16_offset. */
 typedef struct {
     int64_t n;
@@ -138,11 +155,13 @@ typedef struct {
  * Implements: storage of PEOS steps (1)-(3) results per edge (Sec. 4.3,
  * "Implementation of PEOs": codes and scalars are precomputed at build time).
  * n, d, R, L, m: base size, dimension, max out-degree, subspaces, projection
- * vectors per subspace.  flags: 0, or PEOS_FLAG_* (the precision form).
+ * vectors per subspace.  flags: 0, or PEOS_FLAG_* (the precision form, the
+ * SimHash signatures, the compact records).
  * Outputs (host pointers): index_bytes = bytes of index_mem;
  * build_ws_bytes = bytes of the build workspace.  Pure, no device work.
  * Errors: PEOS_EINVAL if n < 1, d < 1, R < 1, L < 1, d % L != 0, d/L % 4 != 0,
- * m < 16, m % 16 != 0, 2*m > 256, an unknown flag, or a null output pointer.
+ * m < 16, m % 16 != 0, 2*m > 256, an unknown flag, PEOS_FLAG_COMPACT with
+ * L > 4 or with PEOS_FLAG_FP16 / PEOS_FLAG_SIMHASH, or a null output pointer.
  */
 int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int32_t flags,
                      size_t* index_bytes, size_t* build_ws_bytes);

@@ -32,6 +32,7 @@ PEOS_MODE_SIMHASH = 2
 PEOS_FLAG_BF16_BASE = 1
 PEOS_FLAG_FP16 = 2
 PEOS_FLAG_SIMHASH = 4
+PEOS_FLAG_COMPACT = 8
 PEOS_NSTATS = 12
 STATS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0", "test_h",
          "test_zero", "passes", "ndist", "inserted", "status")

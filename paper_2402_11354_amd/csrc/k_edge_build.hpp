@@ -16,6 +16,20 @@
 //   c = (s_1 + ... + s_L) / L' (L' = nonzero blocks, sequential adds);
 //   e_res_k = fma(-(c / s_i), e_k, e_k); p_0j = fma chain over all k.
 // A code byte is j* + m * [sign < 0].
+//
+// Compact records (L <= 4; the experiments' compact form keeps w_reg = 1,
+// w_res = 0 and two one-byte scalars per edge): the record starts with the
+// node header {g_lo, g_step, i_lo, i_step}, then 4 code bytes per edge (byte
+// i-1 = e[i]), then 2 scalar bytes per edge: cg = floor((gp - g_lo)/g_step)
+// and ci = rint((ie - i_lo)/i_step) (255: zero-length edge), with gp =
+// g_e/|e| (l2; 0 otherwise) and ie = 1/|e| in single precision:
+//   ne2 = S_1 + ... + S_L (S_i the block's fma chain), ne = sqrt(ne2),
+//   |x|^2 = fma chain over the original coordinates in order,
+//   gp = (0.5 (|u|^2 - |v|^2)) / ne, ie = 1 / ne,
+//   g_lo..g_hi, i_lo..i_hi over the node's edges of nonzero length,
+//   g_step = (g_hi - g_lo)/255, i_step = (i_hi - i_lo)/254.
+// The rounding directions make the search's A_r a lower bound of the exact
+// one (g rounded down; 1/|e| decoded half a step towards the safe side).
 #pragma once
 
 #include "peos_device.hpp"
@@ -37,9 +51,12 @@ struct EdgeBuildArgs {
                           // the test's vectors is original coordinate perm[k]
     const float* sdirs;   // 64 x d SimHash vectors, or null
     int64_t sig_off;      // SimHash signatures within a record
+    int compact;          // compact records (see above)
 };
 
-// LDS: xv[d] | e[4][d] | s[4][L] | row[R]
+constexpr int kCompactZeroEdge = 255;
+
+// LDS: xv[d] | e[4][d] | s[4][L] | row[R] | compact: gp[R] | ie[R] | kind[R]
 __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
 {
 #pragma clang fp contract(off)
@@ -52,7 +69,11 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
     float* ebuf = xv + d;
     float* sblk = ebuf + 4 * d;
     int32_t* row = reinterpret_cast<int32_t*>(sblk + 4 * L);
+    float* cgp = reinterpret_cast<float*>(row + R);
+    float* cie = cgp + R;
+    int32_t* ckd = reinterpret_cast<int32_t*>(cie + R);
     const int lane = lane_id();
+    const bool compact = a.compact != 0;
     const int g = lane >> 4;   // edge slot within the wave
     const int s = lane & 15;   // lane within the edge's group
 
@@ -64,6 +85,11 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
         nv2 = fmaf(x, x, nv2);
     }
     nv2 = wave_sum(nv2);
+    // compact records: |v|^2 as one fma chain in coordinate order
+    float nv2c = 0.f;
+    if (compact) {
+        for (int k = 0; k < d; ++k) nv2c = fmaf(xvg[k], xvg[k], nv2c);
+    }
     for (int j = lane; j < R; j += kWave) row[j] = a.graph[v * R + j];
     __syncthreads();
 
@@ -78,7 +104,10 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
 
     uint8_t* rv = a.rec + v * a.node_stride;
     uint8_t* codes = rv + a.codes_off;
-    const int cbytes = (L + 4) & ~3;  // round_up(L + 1, 4)
+    // full records: round_up(L + 1, 4) code bytes per edge, byte 0 the
+    // residual code; compact: 4 bytes, byte i-1 = e[i]
+    const int cbytes = compact ? 4 : ((L + 4) & ~3);
+    const int cfirst = compact ? 0 : 1;
     float* scal = reinterpret_cast<float*>(rv + a.scal_off);
 
     for (int j0 = 0; j0 < R; j0 += 4) {
@@ -110,6 +139,34 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 sb[i] = sqrtf(ss);
             }
         }
+        // compact scalars in the order stated above (one lane per edge)
+        if (compact && s == 0 && j < R) {
+            int kd = 0;
+            float gp = 0.f, ie = 0.f;
+            if (u >= 0) {
+                float ne2c = 0.f;
+                for (int i = 0; i < L; ++i) {
+                    float ss = 0.f;
+                    for (int t = 0; t < dp; ++t) ss = fmaf(e[i * dp + t], e[i * dp + t], ss);
+                    ne2c = ne2c + ss;
+                }
+                const float ne = sqrtf(ne2c);
+                kd = 2;
+                if (ne > 0.f) {
+                    kd = 1;
+                    if (a.metric == 0) {
+                        const float* xu = a.base + (int64_t)u * d;
+                        float nu2c = 0.f;
+                        for (int k = 0; k < d; ++k) nu2c = fmaf(xu[k], xu[k], nu2c);
+                        gp = (0.5f * (nu2c - nv2c)) / ne;
+                    }
+                    ie = 1.f / ne;
+                }
+            }
+            cgp[j] = gp;
+            cie[j] = ie;
+            ckd[j] = kd;
+        }
         // subspace codes
         for (int i = 0; i < L; ++i) {
             float best = -1.f, bp = 0.f;
@@ -132,7 +189,13 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
                 if (ob > best || (ob == best && oj < bj)) { best = ob; bj = oj; bp = op; }
             }
             if (s == 0 && j < R)
-                codes[j * cbytes + 1 + i] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+                codes[j * cbytes + cfirst + i] = (u >= 0) ? (uint8_t)(bj + (bp < 0.f ? m : 0)) : 0;
+        }
+        if (compact) {
+            if (s == 0 && j < R)
+                for (int pz = L; pz < 4; ++pz) codes[j * cbytes + pz] = 0;
+            __syncthreads();
+            continue;
         }
         __syncthreads();
         // SimHash signature of e (before e is overwritten by its residual):
@@ -240,6 +303,36 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
             }
         }
         __syncthreads();
+    }
+    if (!compact) return;
+    // compact: node ranges (min / max are exact in any order) and the codes
+    __syncthreads();
+    float glo = INFINITY, ghi = -INFINITY, ilo = INFINITY, ihi = -INFINITY;
+    for (int j = 0; j < R; ++j) {
+        if (ckd[j] != 1) continue;
+        glo = fminf(glo, cgp[j]);
+        ghi = fmaxf(ghi, cgp[j]);
+        ilo = fminf(ilo, cie[j]);
+        ihi = fmaxf(ihi, cie[j]);
+    }
+    if (!(glo <= ghi)) glo = ghi = ilo = ihi = 0.f;  // no edge of nonzero length
+    const float gstep = (ghi - glo) / 255.f;
+    const float istep = (ihi - ilo) / 254.f;
+    if (lane == 0) *reinterpret_cast<float4*>(rv) = make_float4(glo, gstep, ilo, istep);
+    for (int j = lane; j < R; j += kWave) {
+        uint32_t cg = 0u, ci = 0u;
+        if (ckd[j] == 2) ci = kCompactZeroEdge;
+        if (ckd[j] == 1) {
+            if (gstep > 0.f) {
+                const float c = floorf((cgp[j] - glo) / gstep);
+                cg = (uint32_t)(c < 0.f ? 0.f : (c > 255.f ? 255.f : c));
+            }
+            if (istep > 0.f) {
+                const float c = rintf((cie[j] - ilo) / istep);
+                ci = (uint32_t)(c < 0.f ? 0.f : (c > 254.f ? 254.f : c));
+            }
+        }
+        reinterpret_cast<uint16_t*>(rv + a.scal_off)[j] = (uint16_t)(cg | (ci << 8));
     }
 }
 

@@ -29,6 +29,8 @@ namespace peos {
 // base; halves for the edge scalars and the projection tables
 constexpr int kFlagBf16Base = 1;
 constexpr int kFlagFp16 = 2;
+constexpr int kFlagCompact = 8;
+constexpr int kCompactLutBins = 256;
 
 struct SearchArgs {
     const float* base;
@@ -36,7 +38,8 @@ struct SearchArgs {
     const int32_t* graph;
     const uint8_t* rec;
     int32_t node_stride, codes_off, scal_off, sig_off;  // bytes (records < 2 GB apart)
-    const float* sdirs;     // 64 x d SimHash vectors (SimHash mode)
+    const float* aux;       // SimHash mode: 64 x d sign vectors; compact
+                            // records: the quantile table (kCompactLutBins)
     const float* queries;
     const float* tables;
     const float* qnorms;
@@ -252,6 +255,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
 {
     constexpr bool BF = (FLAGS & kFlagBf16Base) != 0;
     constexpr bool H16 = (FLAGS & kFlagFp16) != 0;
+    constexpr bool CP = (FLAGS & kFlagCompact) != 0;
     const void* tbase = BF ? (const void*)a.base16 : (const void*)a.base;
     extern __shared__ __align__(16) unsigned char sm[];
     const int lane = lane_id();
@@ -322,7 +326,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             // (an fma chain over the coordinates in order)
             uint64_t qsig = 0;
             if (a.mode == 2) {
-                const float* cv = a.sdirs + (int64_t)lane * d;
+                const float* cv = a.aux + (int64_t)lane * d;
                 float p = 0.f;
                 for (int k = 0; k < d; ++k) p = fmaf(qg[k], cv[k], p);
                 qsig = ballot(p >= 0.f);
@@ -396,9 +400,17 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 uint32_t cw[NCW];
 #pragma unroll
                 for (int i = 0; i < NCW; ++i) cw[i] = 0u;
+                uint32_t csc = 0u;  // compact: the two scalar codes of the edge
                 if (lane < R) {
                     u = a.graph[(int64_t)vid * R + lane];
-                    if (testing) {
+                    if (testing && CP) {
+                        // node header {g_lo, g_step, i_lo, i_step}, 4 code
+                        // bytes and 2 scalar bytes of the edge
+                        const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
+                        sc4 = *reinterpret_cast<const float4*>(rv);
+                        cw[0] = reinterpret_cast<const uint32_t*>(rv + a.codes_off)[lane];
+                        csc = reinterpret_cast<const uint16_t*>(rv + a.scal_off)[lane];
+                    } else if (testing) {
                         const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
                         if (H16) {
                             // halves: g_e/|e|, 1/|e|, w_reg, sqrt(L) w_res
@@ -436,7 +448,42 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 bool pass = cand;
                 if (testing) {
                     int kind = -1;
-                    if (cand) {
+                    if (cand && CP) {
+                        // compact records: w_reg = 1, w_res = 0, decoded
+                        // scalars (A_r a lower bound of the exact one), the
+                        // quantile from the table (its bin's smallest T)
+                        const float diff = (a.metric == 0) ? 0.5f * (dv - delta) : (dv - delta);
+                        const uint32_t ci = csc >> 8;
+                        if (ci == 255u) {
+                            kind = 0;
+                            pass = diff < 0.f;
+                        } else {
+                            const float gp = (a.metric == 0) ? fmaf((float)(csc & 0xFFu), sc4.y, sc4.x) : 0.f;
+                            const float ie = fmaf((float)ci + (diff < 0.f ? 0.5f : -0.5f), sc4.w, sc4.z);
+                            const float A = (a.metric != 1) ? fmaf(diff, ie, gp) * inv_qn : diff * ie;
+                            if (A >= 1.f) {
+                                kind = 1;
+                                pass = false;
+                            } else if (A <= 0.f) {
+                                kind = 2;
+                                pass = true;
+                            } else {
+                                kind = 3;
+                                float h = 0.f;
+#pragma unroll
+                                for (int i = 1; i <= 4; ++i)
+                                    if (i <= L) {
+                                        const uint32_t c = (cw[0] >> ((i - 1) * 8)) & 0xFFu;
+                                        const bool neg = c >= (uint32_t)m;
+                                        const float t = tab[i * m + (int)(neg ? c - m : c)];
+                                        h += neg ? -t : t;
+                                    }
+                                int b = (int)(A * (float)kCompactLutBins);
+                                b = b < kCompactLutBins - 1 ? b : kCompactLutBins - 1;
+                                pass = h >= a.aux[b];
+                            }
+                        }
+                    } else if (cand) {
                         // full precision: sg = g_e, se = |e|; halves: sg =
                         // g_e/|e|, se = 1/|e| (infinite for a zero edge).
                         // sg is zero for angular and inner product; the
@@ -794,6 +841,21 @@ __global__ void k_zero_u32(uint32_t* p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0u;
+}
+
+// The quantile table of the compact form: entry b = T(b / bins) of step (6)
+// with w_reg = 1, w_res = 0, in double precision and rounded down to single
+// (the smallest T of its bin, since T grows with A).
+__global__ __launch_bounds__(256) void k_compact_lut(float* lut, double eta, double c_eps, int L)
+{
+#pragma clang fp contract(off)
+    const int b = (int)threadIdx.x;
+    if (b >= kCompactLutBins) return;
+    const double A = (double)b / kCompactLutBins;
+    const double t = A * eta + c_eps * sqrt(1.0 - (double)L * A * A / (double)(L + 1));
+    float f = (float)t;
+    if ((double)f > t) f = nextafterf(f, -INFINITY);
+    lut[b] = f;
 }
 
 }  // namespace peos

@@ -68,8 +68,9 @@ struct Layout {
     int64_t stride, codes_off, scal_off, sig_off;
 };
 
-constexpr int kFlagsAll = PEOS_FLAG_BF16_BASE | PEOS_FLAG_FP16;  // kernel variants
+constexpr int kFlagsAll = PEOS_FLAG_BF16_BASE | PEOS_FLAG_FP16 | PEOS_FLAG_COMPACT;  // kernel variants
 constexpr int kFlagsKnown = kFlagsAll | PEOS_FLAG_SIMHASH;
+static_assert(PEOS_FLAG_COMPACT == peos::kFlagCompact, "flag values of the kernel variants");
 
 // record of a node: codes [R][round_up(L+1, 4)] bytes | pad to 16 | scalars
 // [R][4] floats (halves with PEOS_FLAG_FP16) | with PEOS_FLAG_SIMHASH, pad to
@@ -78,6 +79,14 @@ constexpr int kFlagsKnown = kFlagsAll | PEOS_FLAG_SIMHASH;
 Layout layout_of(int R, int L, int flags)
 {
     Layout l;
+    if (flags & PEOS_FLAG_COMPACT) {
+        // node header (16 bytes) | 4 code bytes per edge | 2 scalar bytes per edge
+        l.codes_off = 16;
+        l.scal_off = 16 + 4LL * R;
+        l.sig_off = 0;
+        l.stride = round_up(l.scal_off + 2LL * R, 128);
+        return l;
+    }
     l.codes_off = 0;
     l.scal_off = round_up((int64_t)R * round_up(L + 1, 4), 16);
     const int64_t end = l.scal_off + ((flags & PEOS_FLAG_FP16) ? 8LL : 16LL) * R;
@@ -165,7 +174,11 @@ int ensure_kernel_attrs(int dev)
     (const void*)peos::k_search<ML, 0, RG>, (const void*)peos::k_search<ML, 1, RG>,          \
         (const void*)peos::k_search<ML, 2, RG>, (const void*)peos::k_search<ML, 3, RG>
         const void* fns[] = {PEOS_FNS(8, false),  PEOS_FNS(16, false), PEOS_FNS(32, false),
-                             PEOS_FNS(8, true),   PEOS_FNS(16, true),  PEOS_FNS(32, true)};
+                             PEOS_FNS(8, true),   PEOS_FNS(16, true),  PEOS_FNS(32, true),
+                             (const void*)peos::k_search<8, 8, false>,
+                             (const void*)peos::k_search<8, 9, false>,
+                             (const void*)peos::k_search<8, 8, true>,
+                             (const void*)peos::k_search<8, 9, true>};
 #undef PEOS_FNS
         for (const void* f : fns)
             HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
@@ -244,7 +257,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
 // workspace: work counters (one per ef class) and class ranges | per-slot
 // visited bitmaps | tables | norms | query order of the class split
 struct WsLayout {
-    int64_t counter_off, ranges_off, spill_off, tables_off, qnorm_off, qperm_off, total;
+    int64_t counter_off, ranges_off, lut_off, spill_off, tables_off, qnorm_off, qperm_off, total;
 };
 
 WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
@@ -254,7 +267,8 @@ WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
     if (slots < 1) slots = 1;
     w.counter_off = 0;
     w.ranges_off = 64;
-    w.spill_off = 256;
+    w.lut_off = 256;  // quantile table of the compact form
+    w.spill_off = w.lut_off + 4 * peos::kCompactLutBins;
     w.tables_off = round_up(w.spill_off + slots * spill_words * 4, 256);
     w.qnorm_off = round_up(w.tables_off + nq * (int64_t)(ix->L + 1) * ix->m * 4, 256);
     w.qperm_off = round_up(w.qnorm_off + nq * 4, 256);
@@ -320,6 +334,10 @@ int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int3
 {
     if (!index_bytes || !build_ws_bytes) return fail(PEOS_EINVAL, "null output pointer");
     if (flags & ~kFlagsKnown) return fail(PEOS_EINVAL, "flags=%d not supported", flags);
+    if ((flags & PEOS_FLAG_COMPACT) && L > 4)
+        return fail(PEOS_EINVAL, "PEOS_FLAG_COMPACT needs L <= 4 (L=%d)", L);
+    if ((flags & PEOS_FLAG_COMPACT) && (flags & (PEOS_FLAG_FP16 | PEOS_FLAG_SIMHASH)))
+        return fail(PEOS_EINVAL, "PEOS_FLAG_COMPACT does not combine with PEOS_FLAG_FP16 or PEOS_FLAG_SIMHASH");
     int rc = check_shape(n, d, R, L, m);
     if (rc) return rc;
     Layout l = layout_of(R, L, flags);
@@ -389,7 +407,8 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     a.perm = perm;
     a.sdirs = (flags & PEOS_FLAG_SIMHASH) ? sdirs : nullptr;
     a.sig_off = l.sig_off;
-    size_t lds = sizeof(float) * (size_t)(5 * d + 4 * L) + sizeof(int32_t) * (size_t)R;
+    a.compact = (flags & PEOS_FLAG_COMPACT) ? 1 : 0;
+    size_t lds = sizeof(float) * (size_t)(5 * d + 4 * L) + sizeof(int32_t) * (size_t)R * 4;
     hipLaunchKernelGGL(peos::k_edge_build, dim3((unsigned)n), dim3(64), lds, s, a);
     HIP_TRY(hipGetLastError());
     const int64_t bf16_off = (flags & PEOS_FLAG_BF16_BASE) ? round_up(n * l.stride, 256) : 0;
@@ -444,8 +463,9 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
     out->node_stride = ix->node_stride;
     out->codes_offset = ix->codes_off;
     out->scalars_offset = ix->scal_off;
-    out->code_bytes = round_up(ix->L + 1, 4);
-    out->scalar_bytes = (ix->flags & PEOS_FLAG_FP16) ? 8 : 16;
+    const bool compact = (ix->flags & PEOS_FLAG_COMPACT) != 0;
+    out->code_bytes = compact ? 4 : round_up(ix->L + 1, 4);
+    out->scalar_bytes = compact ? 2 : ((ix->flags & PEOS_FLAG_FP16) ? 8 : 16);
     out->bf16_offset = ix->bf16_off;
     out->simhash_offset = ix->sig_off;
     return PEOS_OK;
@@ -521,7 +541,14 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     }
 #define PEOS_LAUNCH(ML)                                                                           \
     if (regl) { PEOS_LAUNCH2(ML, true) } else { PEOS_LAUNCH2(ML, false) }
-    if (ix->L <= 8) { PEOS_LAUNCH(8) }
+    // compact records (L <= 4): their own variants of the L <= 8 kernel
+    if (ix->flags & PEOS_FLAG_COMPACT) {
+        const bool bf = (ix->flags & PEOS_FLAG_BF16_BASE) != 0;
+        if (regl && bf) hipLaunchKernelGGL((peos::k_search<8, 9, true>), grid, dim3(64), lds, s, a);
+        else if (regl) hipLaunchKernelGGL((peos::k_search<8, 8, true>), grid, dim3(64), lds, s, a);
+        else if (bf) hipLaunchKernelGGL((peos::k_search<8, 9, false>), grid, dim3(64), lds, s, a);
+        else hipLaunchKernelGGL((peos::k_search<8, 8, false>), grid, dim3(64), lds, s, a);
+    } else if (ix->L <= 8) { PEOS_LAUNCH(8) }
     else if (ix->L <= 16) { PEOS_LAUNCH(16) }
     else { PEOS_LAUNCH(32) }
 #undef PEOS_LAUNCH
@@ -550,7 +577,7 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.codes_off = (int32_t)ix->codes_off;
     a.scal_off = (int32_t)ix->scal_off;
     a.sig_off = (int32_t)ix->sig_off;
-    a.sdirs = ix->sdirs;
+    a.aux = ix->sdirs;
     a.queries = queries;
     a.tables = tables;
     a.qnorms = qnorms;
@@ -586,6 +613,12 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     const bool per_query = k != nullptr || ef != nullptr;
     const int nclass = ef ? num_classes(efmax) : 1;
     hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, counters, peos::kMaxClasses);
+    if ((ix->flags & PEOS_FLAG_COMPACT) && mode == PEOS_MODE_PEOS) {
+        float* lut = (float*)((char*)ws + w.lut_off);
+        hipLaunchKernelGGL(peos::k_compact_lut, dim3(1), dim3(peos::kCompactLutBins), 0, s, lut,
+                           eta, norm_ppf((double)eps), (int)ix->L);
+        a.aux = lut;
+    }
     if (nclass == 1) return launch_search(ix, a, nq, efmax, pool, per_query, -1, counters, slots_cap, s);
     // per-query list sizes: one launch per ef class, each with the LDS plan
     // of its own largest list (small lists are not held to the largest one's
