@@ -79,8 +79,11 @@ def _load():
         lib.oracle_test_edge.argtypes = [P, P, P, P, i32, i32, i32, P, P, i32, f64, i32, P, i32, P]
         lib.oracle_test_edge.restype = i32
         lib.oracle_search.argtypes = [P, i64, i32, P, i32, i32, i32, i32, P, P, i32, P, i64, P, P,
-                                      i32, i32, f64, i32, f64, i32, i32, P, P, i32, i32, P, P, P, P,
-                                      P, P]
+                                      i32, i32, f64, i32, f64, i32, i32, P, P, i32, P, i32, P, P, P,
+                                      P, P, P]
+        lib.oracle_descend.argtypes = [P, i64, i32, i32, P, P, P, i64, i32, i32, P, i64, i32, i32,
+                                       f64, P, P, P]
+        lib.oracle_descend.restype = i32
         lib.oracle_search.restype = i32
         lib.oracle_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P]
         lib.oracle_simhash_bits.argtypes = [P, i32, P, i32, P]
@@ -202,7 +205,7 @@ def test_edge(xv, xu, xp, q, L, m, A, B, metric, eps, lowp=0, simhash=None):
 # ---------------------------------------------------------------------------
 def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MODE_PEOS,
            tau=1e-5, nthreads=None, kstride=None, pool=0, precision=64, lowp=0, perm=None,
-           simhash=None):
+           simhash=None, entries=None):
     """Batched search.  k, ef: scalars or per-query arrays (ef := max(ef, k)).
     pool: capacity of the candidate list; 0 = unbounded (Alg. 1 as printed),
     0 < pool <= ef = the HNSW stopping rule, pool < 0 = |pool| x each
@@ -216,6 +219,7 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     perm: optional dimension permutation (d ints) of the test: edge records
     and tables on permuted coordinates, distances on the original ones.
     simhash: (nb, d) sign-projection vectors, required by MODE_SIMHASH.
+    entries: optional per-query entry nodes (from descend) instead of entry.
     Returns dict(ids (nq, kstride) int64, dist (as decided), dist64 float64,
     counters (nq, 11) int64, fragile (nq,) int32 flag words, status (nq,) int32)."""
     if precision not in (32, 64):
@@ -241,14 +245,41 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
         raise ValueError("perm must be a permutation of range(d)")
     sh = None if simhash is None else _f32(simhash)
     nb = 0 if sh is None else sh.shape[0]
+    ent = None if entries is None else np.ascontiguousarray(entries, dtype=np.int32)
+    if ent is not None and (ent.shape != (nq,) or ent.min(initial=0) < 0 or ent.max(initial=0) >= n):
+        raise ValueError("entries must hold one base id per query")
     rc = _load().oracle_search(_p(base), n, d, _p(graph), graph.shape[1], int(entry), L, m, _p(A),
                                _p(B), metric, _p(queries), nq, _p(karr), _p(efarr), ks,
                                int(pool), float(eps), mode, float(tau), 1 if precision == 32 else 0,
-                               int(lowp), _p(perm_arr), _p(sh), nb, nt, _p(ids), _p(dist),
+                               int(lowp), _p(perm_arr), _p(sh), nb, _p(ent), nt, _p(ids),
+                               _p(dist),
                                _p(dist64), _p(cnt), _p(frag), _p(status))
     if rc:
         raise ValueError("bad search arguments")
     return dict(ids=ids, dist=dist, dist64=dist64, counters=cnt, fragile=frag, status=status)
+
+
+def descend(base, layers, queries, metric, precision=32, lowp=0, tau=1e-5):
+    """Greedy descent through upper layers to each query's entry node (see
+    oracle_descend in peos_oracle.c).  layers: dict with node (rows,), adj
+    (rows, Ru), down (rows,), top.  Returns (entries (nq,) int32, ndist (nq,)
+    int64, fragile (nq,) int32)."""
+    base, queries = _f32(base), _f32(queries)
+    node = np.ascontiguousarray(layers["node"], dtype=np.int32)
+    adj = np.ascontiguousarray(layers["adj"], dtype=np.int32)
+    down = np.ascontiguousarray(layers["down"], dtype=np.int32)
+    n, d = base.shape
+    nq = queries.shape[0]
+    ent = np.zeros(nq, np.int32)
+    nd = np.zeros(nq, np.int64)
+    frag = np.zeros(nq, np.int32)
+    rc = _load().oracle_descend(_p(base), n, d, int(metric), _p(node), _p(adj), _p(down),
+                                node.shape[0], adj.shape[1], int(layers["top"]), _p(queries), nq,
+                                1 if precision == 32 else 0, int(lowp), float(tau), _p(ent),
+                                _p(nd), _p(frag))
+    if rc:
+        raise ValueError("bad descent arguments")
+    return ent, nd, frag
 
 
 def simhash_bits(v, C):

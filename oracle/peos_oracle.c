@@ -986,6 +986,7 @@ typedef struct {
     const int32_t* perm; /* dimension permutation of the test, or NULL */
     const float* simhash; /* nb x d sign-projection vectors (SimHash mode) */
     int nb;
+    const int32_t* entries; /* per-query entry node (upper-layer descent), or NULL */
     double eps, tau;
     int64_t* out_ids;
     double* out_dist;
@@ -1073,12 +1074,13 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
 
     memset(visited, 0, (size_t)j->n);
     int size = 0;
-    const float* x0 = j->base + (size_t)j->entry * d;
+    const int32_t v0 = j->entries ? j->entries[qi] : j->entry;
+    const float* x0 = j->base + (size_t)v0 * d;
     R[0].dist = DIST(x0);
-    R[0].id = j->entry;
+    R[0].id = v0;
     R[0].expanded = 0;
     size = 1;
-    visited[j->entry] = 1;
+    visited[v0] = 1;
     cnt[C_NDIST]++;
 
     edge_rec er;
@@ -1316,6 +1318,79 @@ static void* search_worker(void* arg)
     return NULL;
 }
 
+/* ------------------------------------------------------------------ */
+/* Entry descent through upper layers (the HNSW graphs of Sec. 6)      */
+/* ------------------------------------------------------------------ */
+/*
+ * The paper runs PEOs on HNSW (and NSSG) graphs and searches the base layer
+ * from an entry node (Alg. 1, v0).  In HNSW that entry comes from a greedy
+ * walk down sparser upper layers: in each layer, from the current node, look
+ * at all its neighbours in that layer and move to the closest one (distance,
+ * then id) while it is closer than the current node; then continue from the
+ * same node one layer below.  The node reached in the lowest upper layer is
+ * v0.
+ * Layout: the rows of all upper layers together; node[r] = base id of row
+ * r; adj[r * Ru + j] = rows of its neighbours in the same layer (-1 = none);
+ * down[r] = row of the same node one layer below (-1 in the lowest upper
+ * layer); top = starting row.  Distances are the search's (dist32 in the
+ * GPU's precision, with the bfloat16 base under LP_BF16_BASE, else dist64).
+ * out_entry[q] = v0; out_ndist[q] = distances computed (the start included);
+ * fragile[q] |= F_ORDER when two compared distances are within tau.
+ */
+static double descend_dist(const float* x, const float* q, double qnorm, float inv_qn32, int d,
+                           int metric, int fp32, int lowp)
+{
+    return fp32 ? (double)dist32(x, q, d, metric, inv_qn32, lowp & LP_BF16_BASE)
+                : dist64(x, q, qnorm, d, metric);
+}
+
+int oracle_descend(const float* base, int64_t n, int d, int metric, const int32_t* node,
+                   const int32_t* adj, const int32_t* down, int64_t rows, int Ru, int top,
+                   const float* queries, int64_t nq, int fp32, int lowp, double tau,
+                   int32_t* out_entry, int64_t* out_ndist, int32_t* fragile)
+{
+    if (n <= 0 || d <= 0 || rows <= 0 || Ru <= 0 || top < 0 || top >= rows) return -1;
+    fp32 = fp32 || lowp;
+    for (int64_t qi = 0; qi < nq; ++qi) {
+        const float* q = queries + (size_t)qi * d;
+        const double qnorm = sqrt(dot64(q, q, d));
+        const float inv_qn32 = 1.0f / qnorm32(q, d);
+        int flags = 0;
+        int64_t nd = 1;
+        int64_t cur = top;
+        double dcur = descend_dist(base + (size_t)node[cur] * d, q, qnorm, inv_qn32, d, metric,
+                                   fp32, lowp);
+        for (;;) {
+            for (;;) {
+                int64_t best = cur;
+                double bd = dcur;
+                for (int j = 0; j < Ru; ++j) {
+                    const int32_t nb = adj[(size_t)cur * Ru + j];
+                    if (nb < 0) continue;
+                    const double dd = descend_dist(base + (size_t)node[nb] * d, q, qnorm,
+                                                   inv_qn32, d, metric, fp32, lowp);
+                    ++nd;
+                    const double sc = fabs(dd) > fabs(bd) ? fabs(dd) : fabs(bd);
+                    if (dd != bd && fabs(dd - bd) < tau * sc) flags |= F_ORDER;
+                    if (dd < bd || (dd == bd && node[nb] < node[best])) {
+                        best = nb;
+                        bd = dd;
+                    }
+                }
+                if (best == cur) break;
+                cur = best;
+                dcur = bd;
+            }
+            if (down[cur] < 0) break;
+            cur = down[cur];
+        }
+        out_entry[qi] = node[cur];
+        if (out_ndist) out_ndist[qi] = nd;
+        if (fragile) fragile[qi] = flags;
+    }
+    return 0;
+}
+
 /*
  * Public: batched search.  k and ef are per-query arrays (ef := max(ef, k)).
  * pool: capacity of the candidate list (0: unbounded, Alg. 1 as printed;
@@ -1339,13 +1414,16 @@ static void* search_worker(void* arg)
  * permuted coordinates, distances on the original ones.  mode
  * OR_MODE_SIMHASH takes the SimHash test (routing_test_simhash) with the nb
  * sign-projection vectors simhash (nb x d) instead of the PEOs test.
+ * entries (optional, nq ids): each query's entry node v0 (from
+ * oracle_descend) instead of the common entry.
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int R, int entry,
                   int L, int m, const float* A, const float* B, int metric, const float* queries,
                   int64_t nq, const int32_t* k, const int32_t* ef, int kstride, int pool,
                   double eps, int mode, double tau, int fp32, int lowp, const int32_t* perm,
-                  const float* simhash, int nb, int nthreads, int64_t* out_ids,
+                  const float* simhash, int nb, const int32_t* entries, int nthreads,
+                  int64_t* out_ids,
                   double* out_dist, double* out_dist64, int64_t* counters, int32_t* fragile,
                   int32_t* status)
 {
@@ -1362,7 +1440,8 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
                                nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
-                               pool, fp32 || lowp, lowp, perm, simhash, nb, eps, tau, out_ids,
+                               pool, fp32 || lowp, lowp, perm, simhash, nb, entries, eps, tau,
+                               out_ids,
                                out_dist, out_dist64, counters, fragile, status};
         pthread_create(&th[t], NULL, search_worker, &jobs[t]);
     }

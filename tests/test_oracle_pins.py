@@ -1218,3 +1218,74 @@ def test_compact_form_needs_L_at_most_4():
         O.search(x, g, entry, q, 10, 16, 8, w.m, A, B, W.L2, 0.1, lowp=O.LP_COMPACT)
     with pytest.raises(ValueError):
         O.compact_tables(x, g, 8, W.L2)
+
+
+# ---------------------------------------------------------------------------
+# entry descent through upper layers (HNSW graphs of the experiments)
+# ---------------------------------------------------------------------------
+def _dist64(x, q, metric):
+    x64, q64 = x.astype(np.float64), q.astype(np.float64)
+    if metric == W.L2:
+        return ((x64 - q64) ** 2).sum(-1)
+    if metric == W.IP:
+        return -(x64 @ q64)
+    return 1.0 - x64 @ q64 / np.linalg.norm(q64)
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
+def test_descent_through_a_complete_layer_finds_its_nearest_node(metric):
+    """One upper layer whose rows are all linked: one greedy step reaches the
+    layer's nearest node to q (distance, then id), the brute-force answer."""
+    w, x, q, g, entry = _compact_case(metric, n=600)
+    S = np.arange(0, 600, 37)
+    k = len(S)
+    adj = np.array([[j for j in range(k) if j != i] for i in range(k)], np.int32)
+    layers = dict(node=S.astype(np.int32), adj=adj, down=np.full(k, -1, np.int32), top=3)
+    ent, nd, frag = O.descend(x, layers, q, metric, precision=64)
+    for i in range(len(q)):
+        dd = _dist64(x[S], q[i], metric)
+        best = S[np.lexsort((S, dd))[0]]
+        assert ent[i] == best
+        # the start plus one scan from it, plus one scan from the winner if it moved
+        assert nd[i] == 1 + (k - 1) * (1 if best == S[3] else 2)
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.ANGULAR, W.IP])
+def test_descent_ends_in_a_local_minimum_of_the_lowest_layer(metric):
+    """Built HNSW-style layers: the entry is no farther than its neighbours
+    in layer 1 and no farther than the top node; the layers nest."""
+    w, x, q, g, entry = _compact_case(metric, n=3000)
+    lay = W.build_upper_layers(x, R_up=8, M=8, seed=3)
+    node, adj, down, ls = lay["node"], lay["adj"], lay["down"], lay["layer_start"]
+    assert len(ls) >= 3  # at least two upper layers at this size
+    for r in range(ls[1], len(node)):  # down goes to the same node one layer lower
+        lv = np.searchsorted(ls, r, side="right") - 1
+        assert ls[lv - 1] <= down[r] < ls[lv] and node[down[r]] == node[r]
+    assert np.all(down[:ls[1]] == -1)
+    ent, nd, frag = O.descend(x, lay, q, metric, precision=64)
+    row_of = {int(node[r]): r for r in range(ls[1])}
+    for i in range(len(q)):
+        r = row_of[int(ent[i])]
+        nbs = node[adj[r][adj[r] >= 0]]
+        de = _dist64(x[ent[i]], q[i], metric)
+        assert np.all(de <= _dist64(x[nbs], q[i], metric))
+        assert de <= _dist64(x[node[lay["top"]]], q[i], metric)
+
+
+def test_descended_entry_shortens_the_search():
+    """Starting the base-layer search at the descent's node instead of the
+    medoid takes fewer expansions on average at the same results quality."""
+    w = W.TINY.with_sizes(n=6000, nq=100)
+    x, q = W.make_base(w), W.make_queries(w)
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    lay = W.build_upper_layers(x, R_up=8, M=8, seed=1)
+    ent, _, _ = O.descend(x, lay, q, w.metric, precision=32)
+    a = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, w.metric, 0.1, pool=32, precision=32)
+    b = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, w.metric, 0.1, pool=32, precision=32,
+                 entries=ent)
+    ci = O.COUNTERS.index
+    assert b["counters"][:, ci("expansions")].mean() < a["counters"][:, ci("expansions")].mean()
+    gt, _ = O.brute_force(x, q, 10, w.metric)
+    rec = lambda I: np.mean([len(set(I[i]) & set(gt[i])) for i in range(len(q))]) / 10
+    assert rec(b["ids"]) >= rec(a["ids"]) - 0.01

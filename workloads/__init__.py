@@ -190,7 +190,7 @@ def query_params(w: Workload, nq: int, seed: int = 0):
     return k.astype(np.int32), np.maximum(ef, k).astype(np.int32)
 
 
-from .graph import build_graph, ground_truth, medoid  # noqa: E402,F401
+from .graph import build_graph, build_upper_layers, ground_truth, medoid  # noqa: E402,F401
 
 
 def graph_for(w: Workload, base: np.ndarray, device="cpu", log=None):

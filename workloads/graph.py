@@ -430,3 +430,48 @@ def recall_at_k(base, queries, ids, gt_dist, k: int, metric: int, rel_tol: float
         mask[first] = True
         hit[i] &= mask & (row >= 0)
     return hit.sum(1) / float(k)
+
+
+def build_upper_layers(base: np.ndarray, R_up: int = 16, M: int = 16, seed: int = 0,
+                       device="cpu", log=None):
+    """HNSW-style upper layers for the entry descent.  Node i reaches level
+    floor(-ln(U_i) / ln M) with U_i uniform in (0, 1] (seeded); layer l >= 1
+    holds the nodes of level >= l, linked by a pruned k-NN graph of degree
+    R_up built like the base graph (a complete graph when the layer has at
+    most R_up + 1 nodes).  Rows of layer 1 come first.  Returns dict(node
+    (rows,) base ids, adj (rows, R_up) rows of the neighbours in the same
+    layer or -1, down (rows,) row of the same node one layer below or -1 in
+    layer 1, top (the starting row: the top layer's medoid), layer_start
+    (levels + 1,))."""
+    n = base.shape[0]
+    rng = np.random.default_rng([seed, 11])
+    u = 1.0 - rng.random(n)
+    level = np.floor(-np.log(u) / math.log(M)).astype(np.int64)
+    top_level = max(1, int(level.max()))
+    if level.max() < 1:
+        level[int(np.argmin(u))] = 1
+    layers = [np.nonzero(level >= lv)[0] for lv in range(1, top_level + 1)]
+    starts = np.concatenate([[0], np.cumsum([len(ids) for ids in layers])]).astype(np.int64)
+    rows = int(starts[-1])
+    node = np.concatenate(layers).astype(np.int32)
+    adj = np.full((rows, R_up), -1, np.int32)
+    down = np.full(rows, -1, np.int32)
+    top = 0
+    for lv, ids in enumerate(layers, 1):
+        off, k = int(starts[lv - 1]), len(ids)
+        if k <= R_up + 1:
+            for i in range(k):
+                others = [off + j for j in range(k) if j != i]
+                adj[off + i, :len(others)] = others
+            ent = 0
+        else:
+            g, ent = build_graph(base[ids], R_up, 2 * R_up, device=device)
+            adj[off:off + k] = np.where(g >= 0, g + off, -1)
+        if lv >= 2:
+            prev = layers[lv - 2]
+            down[off:off + k] = starts[lv - 2] + np.searchsorted(prev, ids)
+        if lv == top_level:
+            top = off + int(ent)
+        if log:
+            log(f"upper layer {lv}: {k} nodes")
+    return dict(node=node, adj=adj, down=down, top=top, layer_start=starts)
