@@ -91,7 +91,8 @@ def main():
     ap.add_argument("--listcap", type=int, default=0,
                     help="with --profile-only: force an LDS list of this capacity")
     ap.add_argument("--mode", default="headline",
-                    choices=("headline", "batched", "serving", "precision", "compact"),
+                    choices=("headline", "batched", "serving", "precision", "compact",
+                             "descent"),
                     help="headline: the QPS-at-recall comparison (default); batched: one "
                          "captured launch over a batch of uneven k/ef; serving: the request "
                          "loop under Poisson arrivals")
@@ -130,6 +131,8 @@ def main():
         return precision(args)
     if args.mode == "compact":
         return compact(args)
+    if args.mode == "descent":
+        return descent(args)
 
     import paper_2402_11354_amd as P
     import workloads as W
@@ -604,6 +607,83 @@ def compact(args):
                    "L_full": w.L, "L_compact": Lc, "stop_rule": "hnsw (pool=ef)"},
         "record_bytes_per_node": {"full": lay_f.node_stride, "compact": lay_c.node_stride},
         "at_target": {"compact": c, "full": f, "exhaustive": e},
+        "runs": rows,
+    }), flush=True)
+
+
+def descent(args):
+    """Search from the node a greedy descent through HNSW-style upper layers
+    reaches, against search from the fixed entry (the medoid), on the same
+    base graph, under the HNSW stopping rule: QPS at recall@10 >= target over
+    an ef sweep, PEOs and exhaustive, with the descent inside the timed
+    region."""
+    import torch
+
+    import paper_2402_11354_amd as P
+    import workloads as W
+
+    w, x, q, g, entry, index, gt_d = _setup(args.workload, args.n, args.nq, 10)
+    dev = torch.device("cuda:0")
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    t0 = time.time()
+    lay = W.build_upper_layers(x, R_up=16, M=16, seed=w.seed, device=dev,
+                               log=lambda m: log("layers:", m))
+    log(f"upper layers: {len(lay['layer_start']) - 1} levels, {len(lay['node'])} rows in "
+        f"{time.time() - t0:.1f}s")
+    A, B = W.directions_for(w)
+    hier = P.peos_build_tables(index._keep[0], index._keep[1], entry, w.L, w.m, T(A), T(B),
+                               w.metric)
+    P.peos_set_upper_layers(hier, dict(node=T(lay["node"]), adj=T(lay["adj"]),
+                                       down=T(lay["down"]), top=lay["top"],
+                                       layer_start=lay["layer_start"]))
+    qt = T(q)
+    nq = w.nq
+    efs = [int(e) for e in args.efs.split(",")]
+    ws = torch.empty(P.peos_search_ws_bytes(index, nq, max(efs), max(efs)), dtype=torch.uint8,
+                     device=dev)
+    rows = {}
+    runs = []
+    for label, ix in (("medoid", index), ("descent", hier)):
+        runs += [(f"{label}_peos_eps{e}", ix, P.PEOS_MODE_PEOS, e) for e in (0.1, 0.2)]
+        runs += [(f"{label}_exhaustive", ix, P.PEOS_MODE_EXHAUSTIVE, 0.1)]
+    for key, ix, mode, eps in runs:
+        pts = []
+        for ef in efs:
+            ids, dd, st = P.search(ix, qt, 10, ef, eps=eps, mode=mode, pool=ef, ws=ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                P.search(ix, qt, 10, ef, eps=eps, mode=mode, pool=ef, ws=ws)
+            torch.cuda.synchronize()
+            qps = nq * args.steps / (time.perf_counter() - t0)
+            rec = float(_recall(x, q, ids.cpu().numpy(), gt_d, 10, w.metric).mean())
+            s_ = st.cpu().numpy()
+            pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
+                            expansions=round(float(s_[:, 0].mean()), 1),
+                            ndist=round(float(s_[:, 9].mean()), 1),
+                            descent_ndist=round(float(s_[:, 12].mean()), 1)))
+            log(f"descent {key} ef={ef}: recall={rec:.4f} qps={qps:.0f} "
+                f"expansions={pts[-1]['expansions']} descent={pts[-1]['descent_ndist']}")
+            if rec >= args.target + 0.02:
+                break
+        ok = [p_ for p_ in pts if p_["recall"] >= args.target]
+        rows[key] = dict(points=pts, at_target=(max(ok, key=lambda p_: p_["qps"]) if ok else None))
+    best = lambda pre: max((r["at_target"] for k_, r in rows.items()
+                            if k_.startswith(pre) and r["at_target"]),
+                           key=lambda p_: p_["qps"], default=None)
+    res = {k_: best(k_) for k_ in ("medoid_peos", "medoid_exhaustive", "descent_peos",
+                                   "descent_exhaustive")}
+    v = res["descent_peos"]
+    print(json.dumps({
+        "metric": "QPS at recall@10>=0.95, search from the upper-layer descent vs from the medoid",
+        "value": v["qps"] if v else None, "unit": "queries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L,
+                   "m": w.m, "upper_R": 16, "upper_M": 16,
+                   "levels": len(lay["layer_start"]) - 1, "upper_rows": int(len(lay["node"])),
+                   "stop_rule": "hnsw (pool=ef)"},
+        "at_target": res,
         "runs": rows,
     }), flush=True)
 

@@ -119,7 +119,9 @@ extern "C" {
 #define PEOS_STAT_NDIST 9        /* exact distances computed (entry included)  */
 #define PEOS_STAT_INSERTED 10    /* distances that entered the candidate list  */
 #define PEOS_STAT_STATUS 11      /* PEOS_STATUS_* bits                         */
-#define PEOS_NSTATS 12
+#define PEOS_STAT_DESCENT 12     /* distances of the upper-layer descent (0
+                                    without upper layers)                      */
+#define PEOS_NSTATS 13
 
 typedef struct peos_index peos_index;
 typedef struct peos_graph peos_graph;
@@ -236,6 +238,46 @@ int peos_index_layout(const peos_index* index, peos_layout* out);
 
 /* Release a handle (host memory only; device buffers belong to the caller). */
 void peos_free(peos_index* index);
+
+/*
+ * peos_set_upper_layers -- give the index HNSW-style upper layers, so that
+ * every search starts from the node a greedy descent through them reaches
+ * instead of the fixed entry.  Implements the entry of Alg. 1 on the
+ * hierarchical graphs the experiments use (HNSW): in each upper layer, from
+ * the current node, move to the closest of its neighbours in that layer
+ * (distance, then id) while it is closer than the current node, then
+ * continue from the same node one layer below; the node reached in the
+ * lowest upper layer is v0.  The descent runs on the GPU before the search
+ * (kernel k_descend), with the search's distances; its distance count goes
+ * to PEOS_STAT_DESCENT.
+ * Layout: the rows of all upper layers together, layer 1 (the lowest upper
+ * layer) first; layer l is rows [layer_start[l-1], layer_start[l]).
+ *   node (device, rows int32)     base id of row r, in [0, n)
+ *   adj  (device, rows x R int32) rows of r's neighbours in r's own layer,
+ *                                  -1 = none; no self loop
+ *   down (device, rows int32)     row of the same node in the layer below,
+ *                                  -1 for the rows of layer 1
+ *   layer_start (host, levels + 1 int64), top = the starting row (in the
+ *   top layer).
+ * The arrays are not copied (the caller keeps them alive while the index
+ * uses them); they are checked once here (synchronously, through a host
+ * copy): ranges, same-layer adjacency, `down` onto the same node one layer
+ * lower.  layers = NULL removes the upper layers.
+ * Errors: PEOS_EINVAL (bad sizes, levels not in [1, 32], R not in [1, 64],
+ * a check above fails), PEOS_EHIP.
+ */
+typedef struct {
+    int32_t levels;
+    int32_t R;
+    int64_t rows;
+    int64_t top;
+    const int64_t* layer_start; /* host */
+    const int32_t* node;        /* device */
+    const int32_t* adj;         /* device */
+    const int32_t* down;        /* device */
+} peos_upper_layers;
+
+int peos_set_upper_layers(peos_index* index, const peos_upper_layers* layers);
 
 /*
  * peos_query_tables -- PEOs step (5): the per-query projection table, built

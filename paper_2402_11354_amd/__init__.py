@@ -33,7 +33,8 @@ PEOS_FLAG_BF16_BASE = 1
 PEOS_FLAG_FP16 = 2
 PEOS_FLAG_SIMHASH = 4
 PEOS_FLAG_COMPACT = 8
-PEOS_NSTATS = 12
+PEOS_STAT_DESCENT = 12
+PEOS_NSTATS = 13
 STATS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0", "test_h",
          "test_zero", "passes", "ndist", "inserted", "status")
 PEOS_STATUS_ZERO_QUERY = 1
@@ -59,6 +60,12 @@ class peos_layout(ctypes.Structure):
 
 class peos_build_options(ctypes.Structure):
     _fields_ = [("perm", ctypes.c_void_p), ("simhash_dirs", ctypes.c_void_p)]
+
+
+class peos_upper_layers(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("R", ctypes.c_int32), ("rows", ctypes.c_int64),
+                ("top", ctypes.c_int64), ("layer_start", ctypes.c_void_p),
+                ("node", ctypes.c_void_p), ("adj", ctypes.c_void_p), ("down", ctypes.c_void_p)]
 
 
 class peos_serve_config(ctypes.Structure):
@@ -93,6 +100,7 @@ def lib():
                                            ctypes.POINTER(P)]
         L.peos_dimension_permutation_ws_bytes.argtypes = [i32, Psz]
         L.peos_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P, sz, P]
+        L.peos_set_upper_layers.argtypes = [P, ctypes.POINTER(peos_upper_layers)]
         L.peos_free.argtypes = [P]
         L.peos_free.restype = None
         L.peos_query_tables.argtypes = [P, P, i64, P, P, P]
@@ -122,7 +130,8 @@ def lib():
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
                      "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
                      "peos_graph_create", "peos_graph_launch", "peos_serve_open",
-                     "peos_serve_submit", "peos_serve_poll", "peos_serve_counters"):
+                     "peos_serve_submit", "peos_serve_poll", "peos_serve_counters",
+                     "peos_set_upper_layers"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -200,6 +209,23 @@ def peos_build_tables(base, graph, entry, L, m, dirs_a, dirs_b, metric, flags=0,
                                       ctypes.byref(opt), _ptr(mem), ib, _ptr(ws), wb,
                                       _stream(stream), ctypes.byref(h)))
     return PeosIndex(h, (base, graph, dirs_a, dirs_b, perm, simhash_dirs, mem))
+
+
+def peos_set_upper_layers(index, layers):
+    """Upper layers for the entry descent (peos_set_upper_layers).  layers:
+    dict with node (rows,), adj (rows, R), down (rows,) int32 device tensors,
+    top (int) and layer_start (levels + 1 ints, host); None removes them.
+    The tensors are kept alive with the index."""
+    if layers is None:
+        _check("peos_set_upper_layers", lib().peos_set_upper_layers(index.handle, None))
+        index._upper = None
+        return
+    ls = np.ascontiguousarray(layers["layer_start"], dtype=np.int64)
+    node, adj, down = layers["node"], layers["adj"], layers["down"]
+    up = peos_upper_layers(len(ls) - 1, adj.shape[1], node.shape[0], int(layers["top"]),
+                           ls.ctypes.data, node.data_ptr(), adj.data_ptr(), down.data_ptr())
+    _check("peos_set_upper_layers", lib().peos_set_upper_layers(index.handle, ctypes.byref(up)))
+    index._upper = (node, adj, down)
 
 
 def peos_dimension_permutation(base, graph, L, stream=None):

@@ -52,14 +52,16 @@ struct SearchArgs {
     int32_t* stats;
     uint32_t* counter;  // work counter, zero before launch
     uint32_t* spill;    // per-slot visited bitmaps
+    const int32_t* entries;  // per-query entry nodes (upper-layer descent), or null
     int32_t spill_words;
-    int64_t n, nq;
+    int32_t n, nq;      // both below 2^31
     int k_all, ef_all, kstride;
     int d, R, L, m, metric, mode, entry;
     float eta, c_eps, kappa, hoeff;
     int listcap, listslack, pool, hcap, visit_limit;
 };
 
+constexpr int kNumStats = 13;
 constexpr int kStatusZeroQuery = 1;
 constexpr int kStatusPoolFull = 2;
 constexpr int kStatusSpill = 4;
@@ -331,11 +333,12 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 for (int k = 0; k < d; ++k) p = fmaf(qg[k], cv[k], p);
                 qsig = ballot(p >= 0.f);
             }
-            if (lane == 0) Su[0] = (uint32_t)wave_uniform(ca.entry);
+            const uint32_t v0 = (uint32_t)wave_uniform(ca.entries ? ca.entries[qi] : ca.entry);
+            if (lane == 0) Su[0] = v0;
             wave_sync();
             distances<BF, (MAXL >= 16) && BF>(tbase, d, Su, 1, qv, a.metric, inv_qn, Sdist);
             if (lane == 0) {
-                hash_insert(hash, (uint32_t)hcap, (uint32_t)wave_uniform(ca.entry));
+                hash_insert(hash, (uint32_t)hcap, v0);
             }
             wave_sync();
             // list entry `lane` (REGL)
@@ -344,11 +347,11 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             if (REGL) {
                 if (lane == 0) {
                     rd = Sdist[0];
-                    ri = (uint32_t)wave_uniform(ca.entry);
+                    ri = v0;
                 }
             } else if (lane == 0) {
                 Ld[0] = Sdist[0];
-                Li[0] = (uint32_t)wave_uniform(ca.entry);
+                Li[0] = v0;
             }
             size = 1;
             int nvis = 1;
@@ -748,7 +751,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             }
         }
         if (ca.stats && lane == 0) {
-            int32_t* o = ca.stats + qi * 12;
+            int32_t* o = ca.stats + qi * kNumStats;
             o[0] = st_exp;
             o[1] = st_edges;
             o[2] = st_skip;
@@ -761,6 +764,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             o[9] = st_ndist;
             o[10] = st_ins;
             o[11] = status;
+            if (!ca.entries) o[12] = 0;  // else the descent's count, written before
         }
         wave_sync();
     }

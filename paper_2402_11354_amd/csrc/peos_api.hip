@@ -14,6 +14,7 @@
 #include "k_edge_build.hpp"
 #include "k_query_table.hpp"
 #include "k_search.hpp"
+#include "k_descend.hpp"
 
 struct peos_graph {
     hipGraph_t graph;
@@ -35,6 +36,11 @@ struct peos_index {
     int32_t d, R, L, m, metric, flags, entry;
     int64_t node_stride, codes_off, scal_off, bf16_off;
     int device;
+    // upper layers for the entry descent (peos_set_upper_layers), or null
+    const int32_t* up_node = nullptr;
+    const int32_t* up_adj = nullptr;
+    const int32_t* up_down = nullptr;
+    int32_t up_ru = 0, up_top = 0;
 };
 
 namespace {
@@ -257,7 +263,8 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
 // workspace: work counters (one per ef class) and class ranges | per-slot
 // visited bitmaps | tables | norms | query order of the class split
 struct WsLayout {
-    int64_t counter_off, ranges_off, lut_off, spill_off, tables_off, qnorm_off, qperm_off, total;
+    int64_t counter_off, ranges_off, lut_off, spill_off, tables_off, qnorm_off, qperm_off,
+        entries_off, total;
 };
 
 WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
@@ -272,7 +279,8 @@ WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
     w.tables_off = round_up(w.spill_off + slots * spill_words * 4, 256);
     w.qnorm_off = round_up(w.tables_off + nq * (int64_t)(ix->L + 1) * ix->m * 4, 256);
     w.qperm_off = round_up(w.qnorm_off + nq * 4, 256);
-    w.total = round_up(w.qperm_off + nq * 4, 256);
+    w.entries_off = round_up(w.qperm_off + nq * 4, 256);  // entries of the descent
+    w.total = round_up(w.entries_off + nq * 4, 256);
     return w;
 }
 
@@ -473,6 +481,51 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
 
 void peos_free(peos_index* ix) { delete ix; }
 
+int peos_set_upper_layers(peos_index* ix, const peos_upper_layers* up)
+{
+    if (!ix) return fail(PEOS_EINVAL, "null index");
+    if (!up) {
+        ix->up_node = ix->up_adj = ix->up_down = nullptr;
+        return PEOS_OK;
+    }
+    if (up->levels < 1 || up->levels > 32 || up->R < 1 || up->R > 64 || up->rows < 1 ||
+        up->rows > 0x7fffffffLL || !up->layer_start || !up->node || !up->adj || !up->down)
+        return fail(PEOS_EINVAL, "levels=%d R=%d rows=%lld", up->levels, up->R, (long long)up->rows);
+    const int64_t* ls = up->layer_start;
+    if (ls[0] != 0 || ls[up->levels] != up->rows)
+        return fail(PEOS_EINVAL, "layer_start must run from 0 to rows");
+    for (int l = 0; l < up->levels; ++l)
+        if (ls[l + 1] <= ls[l]) return fail(PEOS_EINVAL, "layer %d is empty", l + 1);
+    if (up->top < ls[up->levels - 1] || up->top >= up->rows)
+        return fail(PEOS_EINVAL, "top=%lld is not a row of the top layer", (long long)up->top);
+    const int64_t rows = up->rows;
+    std::vector<int32_t> node((size_t)rows), down((size_t)rows), adj((size_t)rows * up->R);
+    HIP_TRY(hipMemcpy(node.data(), up->node, node.size() * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(down.data(), up->down, down.size() * 4, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(adj.data(), up->adj, adj.size() * 4, hipMemcpyDeviceToHost));
+    for (int l = 0; l < up->levels; ++l) {
+        for (int64_t r = ls[l]; r < ls[l + 1]; ++r) {
+            if (node[r] < 0 || node[r] >= ix->n)
+                return fail(PEOS_EINVAL, "row %lld: node %d out of range", (long long)r, node[r]);
+            for (int j = 0; j < up->R; ++j) {
+                const int32_t nb = adj[(size_t)r * up->R + j];
+                if (nb == -1) continue;
+                if (nb < ls[l] || nb >= ls[l + 1] || nb == r)
+                    return fail(PEOS_EINVAL, "row %lld: neighbour row %d outside its layer", (long long)r, nb);
+            }
+            const int32_t dn = down[r];
+            if (l == 0 ? dn != -1 : (dn < ls[l - 1] || dn >= ls[l] || node[dn] != node[r]))
+                return fail(PEOS_EINVAL, "row %lld: down=%d is not the same node one layer below", (long long)r, dn);
+        }
+    }
+    ix->up_node = up->node;
+    ix->up_adj = up->adj;
+    ix->up_down = up->down;
+    ix->up_ru = up->R;
+    ix->up_top = (int32_t)up->top;
+    return PEOS_OK;
+}
+
 int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, float* tables,
                       float* qnorms, void* stream)
 {
@@ -588,11 +641,12 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.ids = ids;
     a.dists = dists;
     a.stats = stats;
+    a.entries = nullptr;
     a.counter = nullptr;
     a.spill = (uint32_t*)((char*)ws + w.spill_off);
     a.spill_words = 0;
-    a.n = ix->n;
-    a.nq = nq;
+    a.n = (int32_t)ix->n;
+    a.nq = (int32_t)nq;
     a.k_all = k_all;
     a.ef_all = ef_all;
     a.kstride = kstride;
@@ -613,6 +667,33 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     const bool per_query = k != nullptr || ef != nullptr;
     const int nclass = ef ? num_classes(efmax) : 1;
     hipLaunchKernelGGL(peos::k_zero_u32, dim3(1), dim3(64), 0, s, counters, peos::kMaxClasses);
+    if (ix->up_node) {
+        // entry descent through the upper layers: one wave per query
+        peos::DescendArgs da;
+        da.base = ix->base;
+        da.base16 = ix->base16;
+        da.queries = queries;
+        da.qnorms = qnorms;
+        da.node = ix->up_node;
+        da.adj = ix->up_adj;
+        da.down = ix->up_down;
+        da.entries = (int32_t*)((char*)ws + w.entries_off);
+        da.stats = stats;
+        da.nq = (int32_t)nq;
+        da.d = ix->d;
+        da.ru = ix->up_ru;
+        da.top = ix->up_top;
+        da.metric = ix->metric;
+        da.max_steps = 1 << 16;
+        const unsigned blocks = (unsigned)(nq < 16384 ? nq : 16384);
+        const size_t lds = sizeof(float) * (size_t)ix->d + 3 * 64 * sizeof(float);
+        if (ix->base16)
+            hipLaunchKernelGGL(peos::k_descend<true>, dim3(blocks), dim3(64), lds, s, da);
+        else
+            hipLaunchKernelGGL(peos::k_descend<false>, dim3(blocks), dim3(64), lds, s, da);
+        HIP_TRY(hipGetLastError());
+        a.entries = da.entries;
+    }
     if ((ix->flags & PEOS_FLAG_COMPACT) && mode == PEOS_MODE_PEOS) {
         float* lut = (float*)((char*)ws + w.lut_off);
         hipLaunchKernelGGL(peos::k_compact_lut, dim3(1), dim3(peos::kCompactLutBins), 0, s, lut,

@@ -576,3 +576,64 @@ def test_inner_product_prunes_and_scales(ip):
     assert a[2][:, 6].sum() > 0 and (a[2][:, 8] < a[2][:, 3]).any()
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[2], b[2])
     assert np.array_equal(8.0 * a[1], b[1])
+
+
+# ---------------------------------------------------------------------------
+# entry descent through upper layers
+# ---------------------------------------------------------------------------
+def _with_layers(case, flags=0, R_up=8, M=8, seed=2):
+    w = case.w
+    lay = W.build_upper_layers(case.x, R_up=R_up, M=M, seed=seed)
+    ix = P.peos_build_tables(case.xt, case.gt, case.entry, w.L, w.m, case.At, case.Bt, w.metric,
+                             flags=flags)
+    P.peos_set_upper_layers(ix, dict(node=T(lay["node"]), adj=T(lay["adj"]), down=T(lay["down"]),
+                                     top=lay["top"], layer_start=lay["layer_start"]))
+    return ix, lay
+
+
+@pytest.mark.parametrize("which", ["tiny", "angular", "ip"])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+@pytest.mark.parametrize("bf16", [False, True])
+def test_descent_then_search_matches_oracle(which, pool_mul, bf16, request):
+    case = request.getfixturevalue(which)
+    w = case.w
+    ix, lay = _with_layers(case, P.PEOS_FLAG_BF16_BASE if bf16 else 0)
+    lowp = O.LP_BF16_BASE if bf16 else 0
+    ent, nd, frag = O.descend(case.x, lay, case.q, w.metric, precision=32, lowp=lowp)
+    ids, d, st = P.search(ix, case.qt, w.k, w.ef, eps=w.eps, pool=pool_mul * w.ef)
+    torch.cuda.synchronize()
+    ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+    ok = frag == 0
+    assert ok.mean() >= 0.9
+    assert np.array_equal(st[ok, P.PEOS_STAT_DESCENT], nd[ok])
+    ref = O.search(case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B,
+                   w.metric, w.eps, pool=pool_mul * w.ef, precision=32, lowp=lowp, entries=ent)
+    ref["fragile"] = ref["fragile"] | np.where(ok, 0, O.F_ORDER)
+    res = compare(ids, d, st[:, :12], ref, w.k)
+    print(f"[gpu] descent {which} pool={pool_mul * w.ef} bf16={bf16}: checked={res['checked']} "
+          f"mean descent distances {nd.mean():.1f}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+
+
+def test_descent_count_is_zero_without_layers(tiny):
+    w = tiny.w
+    ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS)
+    assert np.all(st[:, P.PEOS_STAT_DESCENT] == 0)
+
+
+def test_upper_layers_are_checked(tiny):
+    w = tiny.w
+    lay = W.build_upper_layers(tiny.x, R_up=8, M=8, seed=2)
+    ix = P.peos_build_tables(tiny.xt, tiny.gt, tiny.entry, w.L, w.m, tiny.At, tiny.Bt, w.metric)
+    ls = lay["layer_start"]
+    bad_down = lay["down"].copy()
+    bad_down[ls[1]] = [r for r in range(ls[1]) if lay["node"][r] != lay["node"][ls[1]]][0]
+    bad_adj = lay["adj"].copy()
+    bad_adj[0, 0] = ls[1]  # a row of layer 2 from layer 1
+    for node, adj, down in ((lay["node"], bad_adj, lay["down"]),
+                            (lay["node"], lay["adj"], bad_down)):
+        with pytest.raises(P.PeosError):
+            P.peos_set_upper_layers(ix, dict(node=T(node), adj=T(adj), down=T(down),
+                                             top=lay["top"], layer_start=ls))
+    P.peos_set_upper_layers(ix, None)
