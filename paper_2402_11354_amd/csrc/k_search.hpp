@@ -272,13 +272,15 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
     const int hcap = a.hcap;
     const int slack = wave_uniform(ca.listslack);  // room past the capacity during a merge
     const int listcap = wave_uniform(ca.listcap);
-    float* qv = reinterpret_cast<float*>(sm);
+    // survivor staging and the query first, at fixed offsets (no registers
+    // hold their addresses), then table | list | visited hash
+    uint32_t* Su = reinterpret_cast<uint32_t*>(sm);
+    float* Sdist = reinterpret_cast<float*>(Su + kWave);
+    float* qv = Sdist + kWave;
     float* tab = qv + d;
     float* Ld = tab + (L + 1) * m;
     uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + listcap + slack);
     uint32_t* hash = Li + listcap + slack;
-    uint32_t* Su = hash + hcap;
-    float* Sdist = reinterpret_cast<float*>(Su + kWave);
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
 
     uint32_t qbegin = 0, qend = wave_uniform((uint32_t)ca.nq);
@@ -308,8 +310,11 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
         if (REGL) cap = cap < kWave ? cap : kWave;
         const float qn = wave_uniform(ca.qnorms[qi]);
         int status = 0;
-        int st_exp = 0, st_edges = 0, st_skip = 0, st_tests = 0, st_ge1 = 0, st_le0 = 0, st_h = 0,
-            st_zero = 0, st_pass = 0, st_ndist = 0, st_ins = 0;
+        // wave-uniform counts, and per-lane counts summed over the wave at
+        // the end of the query (kept in vector registers: no scalar
+        // registers and no ballot per count in the expansion loop)
+        int st_exp = 0, st_ndist = 0, st_ins = 0;
+        int lc_edges = 0, lc_skip = 0, lc_ge1 = 0, lc_le0 = 0, lc_h = 0, lc_zero = 0, lc_pass = 0;
         int size = 0;
 
         if (qn > 0.f && qn < INFINITY) {
@@ -441,12 +446,12 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 const float sg = sc4.x, se = sc4.y, sw = sc4.z, sr = sc4.w;
                 const bool valid = u >= 0;
-                st_edges += popc(ballot(valid));
+                lc_edges += valid ? 1 : 0;
                 bool vis = false;
                 if (valid)
                     vis = spilled ? bitmap_test(bitmap, (uint32_t)u)
                                   : hash_lookup(hash, (uint32_t)hcap, (uint32_t)u);
-                st_skip += popc(ballot(vis));
+                lc_skip += vis ? 1 : 0;
                 const bool cand = valid && !vis;
                 bool pass = cand;
                 if (testing) {
@@ -532,12 +537,12 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                             }
                         }
                     }
-                    st_tests += popc(ballot(cand));
-                    st_zero += popc(ballot(kind == 0));
-                    st_ge1 += popc(ballot(kind == 1));
-                    st_le0 += popc(ballot(kind == 2));
-                    st_h += popc(ballot(kind == 3));
-                    st_pass += popc(ballot(cand && pass));
+                    // every tested edge gets exactly one kind
+                    lc_zero += kind == 0 ? 1 : 0;
+                    lc_ge1 += kind == 1 ? 1 : 0;
+                    lc_le0 += kind == 2 ? 1 : 0;
+                    lc_h += kind == 3 ? 1 : 0;
+                    lc_pass += (cand && pass) ? 1 : 0;
                 }
                 const uint64_t smask = ballot(pass);
                 const int ns = popc(smask);
@@ -750,12 +755,16 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 ca.dists[qi * kstride + t] = ok ? Ld[t] : INFINITY;
             }
         }
+        const int st_edges = wave_sum_int(lc_edges), st_skip = wave_sum_int(lc_skip);
+        const int st_ge1 = wave_sum_int(lc_ge1), st_le0 = wave_sum_int(lc_le0);
+        const int st_h = wave_sum_int(lc_h), st_zero = wave_sum_int(lc_zero);
+        const int st_pass = wave_sum_int(lc_pass);
         if (ca.stats && lane == 0) {
             int32_t* o = ca.stats + qi * kNumStats;
             o[0] = st_exp;
             o[1] = st_edges;
             o[2] = st_skip;
-            o[3] = st_tests;
+            o[3] = st_zero + st_ge1 + st_le0 + st_h;
             o[4] = st_ge1;
             o[5] = st_le0;
             o[6] = st_h;

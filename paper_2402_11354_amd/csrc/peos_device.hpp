@@ -77,6 +77,13 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+__device__ __forceinline__ int wave_sum_int(int v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
 // sum within aligned groups of G lanes (G a power of two <= 64)
 template <int G>
 __device__ __forceinline__ float group_sum(float v)
