@@ -278,7 +278,10 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
     float* Sdist = reinterpret_cast<float*>(Su + kWave);
     float* qv = Sdist + kWave;
     float* tab = qv + d;
-    float* Ld = tab + (L + 1) * m;
+    // table: entry (i, c) of code byte c in subspace i at c (MAXL+1) + i,
+    // both signs stored (2m codes), zero for L < i <= MAXL
+    constexpr int TW = MAXL + 1;
+    float* Ld = tab + 2 * m * TW;
     uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + listcap + slack);
     uint32_t* hash = Li + listcap + slack;
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
@@ -323,10 +326,18 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             for (int t = lane; t < d; t += kWave) qv[t] = qg[t];
             if (H16) {
                 const _Float16* tg = reinterpret_cast<const _Float16*>(ca.tables) + qi * (int64_t)(L + 1) * m;
-                for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = (float)tg[t];
+                for (int c = lane; c < 2 * m; c += kWave)
+                    for (int i = 0; i < TW; ++i) {
+                        const float v = i <= L ? (float)tg[i * m + (c < m ? c : c - m)] : 0.f;
+                        tab[c * TW + i] = c < m ? v : -v;
+                    }
             } else {
                 const float* tg = ca.tables + qi * (int64_t)(L + 1) * m;
-                for (int t = lane; t < (L + 1) * m; t += kWave) tab[t] = tg[t];
+                for (int c = lane; c < 2 * m; c += kWave)
+                    for (int i = 0; i < TW; ++i) {
+                        const float v = i <= L ? tg[i * m + (c < m ? c : c - m)] : 0.f;
+                        tab[c * TW + i] = c < m ? v : -v;
+                    }
             }
             for (int t = lane; t < hcap; t += kWave) hash[t] = kEmpty;
             // SimHash mode: the query's 64 sign bits, lane i projecting on c_i
@@ -479,13 +490,8 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                                 kind = 3;
                                 float h = 0.f;
 #pragma unroll
-                                for (int i = 1; i <= 4; ++i)
-                                    if (i <= L) {
-                                        const uint32_t c = (cw[0] >> ((i - 1) * 8)) & 0xFFu;
-                                        const bool neg = c >= (uint32_t)m;
-                                        const float t = tab[i * m + (int)(neg ? c - m : c)];
-                                        h += neg ? -t : t;
-                                    }
+                                for (int i = 1; i <= 4; ++i)  // zero entries past L
+                                    h += tab[(int)((cw[0] >> ((i - 1) * 8)) & 0xFFu) * TW + i];
                                 int b = (int)(A * (float)kCompactLutBins);
                                 b = b < kCompactLutBins - 1 ? b : kCompactLutBins - 1;
                                 pass = h >= a.aux[b];
@@ -519,17 +525,22 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                                 pass = (float)col >= T;
                             } else {
                                 kind = 3;
-                                // code byte c: direction c mod m, negative iff c >= m
-                                auto signed_entry = [&](int i, uint32_t c) {
-                                    const bool neg = c >= (uint32_t)m;
-                                    const float v = tab[i * m + (int)(neg ? c - m : c)];
-                                    return neg ? -v : v;
-                                };
+                                // code byte c: direction c mod m, negative iff c >= m;
+                                // the LDS table holds both signs, entry (i, c) at
+                                // c (MAXL+1) + i (one multiply per lookup, the
+                                // subspace in the instruction's offset); entries
+                                // past L are zero and the padding codes are 0, so
+                                // every lookup is issued without a branch
+                                auto signed_entry = [&](int i, uint32_t c) { return tab[(int)c * TW + i]; };
+                                // all lookups issued before the first add
+                                float tv[TW];
+#pragma unroll
+                                for (int i = 0; i <= MAXL; ++i)
+                                    tv[i] = signed_entry(i, (cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu);
                                 float h1 = 0.f;
 #pragma unroll
-                                for (int i = 1; i <= MAXL; ++i)
-                                    if (i <= L) h1 += signed_entry(i, (cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu);
-                                const float h2 = signed_entry(0, cw[0] & 0xFFu);
+                                for (int i = 1; i <= MAXL; ++i) h1 += tv[i];
+                                const float h2 = tv[0];
                                 const float H = sw * h1 + sr * h2;
                                 const float var = sw * sw + sr * sr - a.kappa * A * A;
                                 const float T = A * a.eta + a.c_eps * __builtin_amdgcn_sqrtf(var);

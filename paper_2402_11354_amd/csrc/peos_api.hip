@@ -226,7 +226,9 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     p.listcap = lc;
     // list entries first (the visited hash is sized below)
     p.listslack = (pool > 0 && pool <= efmax && !per_query) ? 0 : 64;
-    const int64_t fixed = 4LL * ix->d + 4LL * (ix->L + 1) * ix->m + 8LL * (lc + p.listslack) +
+    // the table row width of the kernel instantiation: MAXL + 1
+    const int64_t tw = (ix->L <= 8 ? 8 : (ix->L <= 16 ? 16 : 32)) + 1;
+    const int64_t fixed = 4LL * ix->d + 8LL * tw * ix->m + 8LL * (lc + p.listslack) +
                           4LL * 2 * 64;
     // visited hash: 32 slots per list entry, 2048 to 8192; for lists up to
     // 64 no more than fits the LDS share of the 16 waves per CU the kernel's
