@@ -637,3 +637,45 @@ def test_upper_layers_are_checked(tiny):
             P.peos_set_upper_layers(ix, dict(node=T(node), adj=T(adj), down=T(down),
                                              top=lay["top"], layer_start=ls))
     P.peos_set_upper_layers(ix, None)
+
+
+# ---------------------------------------------------------------------------
+# the largest shapes the boundary accepts
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_maximum_degree_subspaces_and_directions(pool_mul):
+    """R = 64 (the largest degree: one lane per edge), L = 32 (the largest
+    subspace count, d/L = 4), m = 128 (code bytes up to 255)."""
+    w = W.Workload("max_shape_2k_d128", 2000, 60, 128, 64, 96, 32, 128, W.L2, "gmm10", 0.1, 10,
+                   48, 1012)
+    case = Case(w)
+    ids, d, st = run(case, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool_mul * w.ef)
+    ref = case.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool_mul * w.ef)
+    res = compare(ids, d, st, ref, w.k)
+    print(f"[gpu] max shape pool={pool_mul * w.ef}: checked={res['checked']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+    assert st[:, 6].sum() > 0
+    codes, _ = read_records(case)
+    rc, _, _ = O.build_tables(case.x, case.g, w.L, w.m, case.A, case.B)
+    valid = case.g >= 0
+    assert np.array_equal(codes[valid], rc[valid]) and codes.max() >= 128
+
+
+@pytest.mark.parametrize("ef", [1024, 2048])
+def test_long_result_lists(tiny, ef):
+    """Result lists of 1024 and 2048 entries under the HNSW rule (the list
+    and the visited set in LDS or spilled to HBM), k = 100."""
+    w = tiny.w
+    q = tiny.q[:20]
+    ids, d, st = run(tiny, 100, ef, w.eps, P.PEOS_MODE_PEOS, ef, queries=q)
+    ref = tiny.oracle(100, ef, w.eps, P.PEOS_MODE_PEOS, ef, queries=q)
+    res = compare(ids, d, st, ref, 100)
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+
+
+def test_list_beyond_lds_is_rejected(tiny):
+    w = tiny.w
+    with pytest.raises(P.PeosError):
+        P.search(tiny.index, tiny.qt[:4], 10, 4096, eps=w.eps, pool=0)
