@@ -16,6 +16,7 @@ off.  Prints one JSON line.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -293,7 +294,20 @@ def main():
                  + 12.0 * w.k)                         # outputs
         return float(per_q.sum())
 
+    def sector_bytes(st):
+        """The same accesses rounded to whole 64-byte sectors as the kernel
+        issues them: a node's id row per expansion, the node's whole record
+        (codes and scalars of all R edges) per expansion that ran the test,
+        whole vector rows."""
+        sec = lambda b: 64.0 * math.ceil(b / 64.0)
+        per_q = (sec(4.0 * w.R) * st[:, 0]
+                 + (sec(code_bytes * w.R) + sec(16.0 * w.R)) * st[:, 13]
+                 + sec(4.0 * w.d) * st[:, 9]
+                 + sec(4.0 * w.d) + sec(4.0 * (w.L + 1) * w.m) + sec(12.0 * w.k))
+        return float(per_q.sum())
+
     pe_bytes = alg_bytes(pe["stats"])
+    pe_sector = sector_bytes(pe["stats"])
     achieved = pe_bytes / (float(search_ms.mean()) / 1e3) / 1e9
     ef, pool, eps, mode = pe["cfg"]
     traffic = traffic_record(dict(kernel="k_search", source=kernel_digest(), workload=w.name,
@@ -354,7 +368,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                      "traffic": None if traffic is None else round(traffic),
-                     "alg_bytes": round(pe_bytes)},
+                     "alg_bytes": round(pe_bytes),
+                     "sector_bytes": round(pe_sector),
+                     "sector_frac": round(pe_sector / (float(search_ms.mean()) / 1e3) / 1e9
+                                          / PEAK_HBM_GBS, 4)},
         "cpu_baseline": cpu,
         "sweep": {"peos": pts_json(pe_sweeps), "exhaustive": pts_json(ex_sweeps)},
     }

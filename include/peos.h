@@ -121,7 +121,9 @@ extern "C" {
 #define PEOS_STAT_STATUS 11      /* PEOS_STATUS_* bits                         */
 #define PEOS_STAT_DESCENT 12     /* distances of the upper-layer descent (0
                                     without upper layers)                      */
-#define PEOS_NSTATS 13
+#define PEOS_STAT_TEST_EXPANSIONS 13 /* expansions that ran the test (list
+                                    full; each loads the node's whole record) */
+#define PEOS_NSTATS 14
 
 typedef struct peos_index peos_index;
 typedef struct peos_graph peos_graph;
@@ -324,8 +326,8 @@ int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int
  *   mode     PEOS_MODE_* (SIMHASH needs PEOS_FLAG_SIMHASH).
  *   ids      out, nq x kstride int64: first k results ordered by (distance,
  *            id), then -1.
- *   dists    out, nq x kstride float: their distances (squared l2, or
- *            1 - x.q/|q|), then +inf.
+ *   dists    out, nq x kstride float: their distances (squared l2,
+ *            1 - x.q/|q|, or -x.q), then +inf.
  *   stats    out, nq x PEOS_NSTATS int32, or NULL.
  *   ws       workspace of peos_search_ws_bytes(index, nq, efmax, pool).
  * Launch: with per-query ef (ef != NULL) the batch is split on the device
@@ -337,7 +339,10 @@ int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int
  * distance-computed and visited first; delta is read once per expansion;
  * a neighbour is visited only once its distance is computed; a survivor
  * enters the list if R was not full or its distance is < delta.
- * Errors: PEOS_EINVAL, PEOS_ENOSPACE, PEOS_EHIP.
+ * Errors: PEOS_EINVAL (also when the list and visited set of the largest
+ * list size do not fit the 64 KB of LDS one workgroup may use: about ef =
+ * 3000 under the HNSW rule, 2048 with the unbounded queue), PEOS_ENOSPACE,
+ * PEOS_EHIP.
  */
 int peos_search_tables(const peos_index* index, const float* queries, const float* tables,
                        const float* qnorms, int64_t nq, const int32_t* k, const int32_t* ef,

@@ -34,7 +34,8 @@ PEOS_FLAG_FP16 = 2
 PEOS_FLAG_SIMHASH = 4
 PEOS_FLAG_COMPACT = 8
 PEOS_STAT_DESCENT = 12
-PEOS_NSTATS = 13
+PEOS_STAT_TEST_EXPANSIONS = 13
+PEOS_NSTATS = 14
 STATS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0", "test_h",
          "test_zero", "passes", "ndist", "inserted", "status")
 PEOS_STATUS_ZERO_QUERY = 1
@@ -340,7 +341,7 @@ def peos_graph_create(index, queries, k, ef, kstride, pool, eps, mode, ids, dist
 def search(index, queries, k, ef, eps=0.1, mode=PEOS_MODE_PEOS, pool=0, kstride=None,
            ws=None, stream=None):
     """Allocate outputs (and workspace if not given) and run peos_search.
-    Returns (ids int64 (nq, kstride), dists float32, stats int32 (nq, 12))."""
+    Returns (ids int64 (nq, kstride), dists float32, stats int32 (nq, PEOS_NSTATS))."""
     nq = queries.shape[0]
     kmax = int(k if not torch.is_tensor(k) else k.max())
     efmax = max(int(ef if not torch.is_tensor(ef) else ef.max()), kmax)

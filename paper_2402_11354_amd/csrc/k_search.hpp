@@ -61,7 +61,7 @@ struct SearchArgs {
     int listcap, listslack, pool, hcap, visit_limit;
 };
 
-constexpr int kNumStats = 13;
+constexpr int kNumStats = 14;
 constexpr int kStatusZeroQuery = 1;
 constexpr int kStatusPoolFull = 2;
 constexpr int kStatusSpill = 4;
@@ -316,7 +316,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
         // wave-uniform counts, and per-lane counts summed over the wave at
         // the end of the query (kept in vector registers: no scalar
         // registers and no ballot per count in the expansion loop)
-        int st_exp = 0, st_ndist = 0, st_ins = 0;
+        int st_exp = 0, st_ndist = 0, st_ins = 0, st_texp = 0;
         int lc_edges = 0, lc_skip = 0, lc_ge1 = 0, lc_le0 = 0, lc_h = 0, lc_zero = 0, lc_pass = 0;
         int size = 0;
 
@@ -412,6 +412,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 ++st_exp;
                 const bool testing = (a.mode == 0 || a.mode == 2) && full;
+                st_texp += testing ? 1 : 0;
 
                 // ids, codes and scalars depend on v only: one round trip
                 int32_t u = -1;
@@ -785,6 +786,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             o[10] = st_ins;
             o[11] = status;
             if (!ca.entries) o[12] = 0;  // else the descent's count, written before
+            o[13] = st_texp;
         }
         wave_sync();
     }
