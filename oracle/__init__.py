@@ -33,7 +33,7 @@ MODE_EXHAUSTIVE = 1
 MODE_SIMHASH = 2
 
 COUNTERS = ("expansions", "edges", "visited_skips", "tests", "test_ge1", "test_le0",
-            "test_h", "test_zero", "passes", "ndist", "inserted")
+            "test_h", "test_zero", "passes", "ndist", "inserted", "test_expansions")
 F_HT, F_A1, F_A0, F_DELTA, F_ORDER = 1, 2, 4, 8, 16
 LP_BF16_BASE, LP_FP16 = 1, 2
 LP_COMPACT = 8  # compact records: L <= 4, w_reg = 1, w_res = 0, 8-bit scalars, quantile table

@@ -48,6 +48,7 @@ enum {
     C_PASSES,         /* tests that passed                                */
     C_NDIST,          /* exact distances computed (entry included)        */
     C_INSERTED,       /* distances that entered the merge                 */
+    C_TEST_EXPANSIONS,/* expansions with R full under a routing test      */
     C_NCOUNT
 };
 
@@ -1097,6 +1098,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         const double dv = R[pos].dist;
         const double delta = full ? R[efq - 1].dist : INFINITY;
         const int32_t p = full ? R[efq - 1].id : -1;
+        if (full && j->mode != OR_MODE_EXHAUSTIVE) cnt[C_TEST_EXPANSIONS]++;
         double vq = 0.0, r = 0.0;
         if (full && j->mode != OR_MODE_EXHAUSTIVE) {
             const float* xp = j->base + (size_t)p * d;
