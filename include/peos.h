@@ -131,8 +131,9 @@ typedef struct peos_graph peos_graph;
 /* Byte layout of the per-node edge records inside index_mem (for tests and
  * tools; the search needs nothing but the handle).  Record of node v starts at
  * v * node_stride.  Codes: edge j (to graph[v*R + j]) owns code_bytes =
- * round_up(L+1, 4) bytes at codes_offset + j*code_bytes: byte 0 = residual
- * code e[0], bytes 1..L = subspace codes e[i], then zero padding.  A code
+ * round_up(B+1, 4) bytes at codes_offset + j*code_bytes, B = 8, 16 or 32 the
+ * smallest of these >= L: byte 0 = residual code e[0], bytes 1..L = subspace
+ * codes e[i], then zero padding.  A code
  * byte c encodes the index j* = c mod m of the extreme projection vector and
  * its sign (negative iff c >= m).  Scalars: edge j owns 4 floats at
  * scalars_offset + 16*j: g_e = (|u|^2 - |v|^2)/2 (zero for ANGULAR and IP), |e|,

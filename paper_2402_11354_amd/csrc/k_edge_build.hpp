@@ -104,9 +104,10 @@ __global__ __launch_bounds__(64) void k_edge_build(EdgeBuildArgs a)
 
     uint8_t* rv = a.rec + v * a.node_stride;
     uint8_t* codes = rv + a.codes_off;
-    // full records: round_up(L + 1, 4) code bytes per edge, byte 0 the
+    // full records: round_up(B + 1, 4) code bytes per edge with B the
+    // search kernel's subspace bound (8, 16 or 32; zero past L), byte 0 the
     // residual code; compact: 4 bytes, byte i-1 = e[i]
-    const int cbytes = compact ? 4 : ((L + 4) & ~3);
+    const int cbytes = compact ? 4 : (((L <= 8 ? 8 : (L <= 16 ? 16 : 32)) + 4) & ~3);
     const int cfirst = compact ? 0 : 1;
     float* scal = reinterpret_cast<float*>(rv + a.scal_off);
 

@@ -281,9 +281,13 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
     // table: entry (i, c) of code byte c in subspace i at c (MAXL+1) + i,
     // both signs stored (2m codes), zero for L < i <= MAXL
     constexpr int TW = MAXL + 1;
-    float* Ld = tab + 2 * m * TW;
-    uint32_t* Li = reinterpret_cast<uint32_t*>(Ld + listcap + slack);
-    uint32_t* hash = Li + listcap + slack;
+    // the list in LDS (none when it lives in registers: the output then
+    // stages it in the visited hash, which is dead by then)
+    const int lds_list = REGL ? 0 : listcap + slack;
+    float* Lr = tab + 2 * m * TW;
+    uint32_t* hash = reinterpret_cast<uint32_t*>(Lr) + 2 * lds_list;
+    float* Ld = REGL ? reinterpret_cast<float*>(hash) : Lr;
+    uint32_t* Li = REGL ? hash + kWave : reinterpret_cast<uint32_t*>(Lr) + lds_list;
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
 
     uint32_t qbegin = 0, qend = wave_uniform((uint32_t)ca.nq);
@@ -377,7 +381,6 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
             wave_sync();
 
             constexpr int NCW = (MAXL + 4) / 4;  // code dwords per edge (max)
-            const int ncw = (L + 4) >> 2;
             for (;;) {
                 // pop: first unexpanded entry of the list
                 int pos = -1;
@@ -449,10 +452,10 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                             if (NCW > 1) cw[1 % NCW] = sg2.y;
                         } else {
                             const uint32_t* cb =
-                                reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * ncw;
+                                reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * NCW;
 #pragma unroll
                             for (int i = 0; i < NCW; ++i)
-                                if (i < ncw) cw[i] = cb[i];
+                                cw[i] = cb[i];  // zero past the codes of L
                         }
                     }
                 }

@@ -82,6 +82,11 @@ static_assert(PEOS_FLAG_COMPACT == peos::kFlagCompact, "flag values of the kerne
 // [R][4] floats (halves with PEOS_FLAG_FP16) | with PEOS_FLAG_SIMHASH, pad to
 // 16 and [R] 64-bit sign signatures | pad to 128.  With
 // PEOS_FLAG_BF16_BASE the n x d bfloat16 copy follows the records.
+// code bytes per edge of the full records: room for the codes of the
+// search kernel's subspace bound (8, 16 or 32) plus the residual code, so a
+// lane loads its edge's codes with a fixed number of dword loads
+int64_t code_bytes_of(int L) { return round_up((L <= 8 ? 8 : (L <= 16 ? 16 : 32)) + 1, 4); }
+
 Layout layout_of(int R, int L, int flags)
 {
     Layout l;
@@ -94,7 +99,7 @@ Layout layout_of(int R, int L, int flags)
         return l;
     }
     l.codes_off = 0;
-    l.scal_off = round_up((int64_t)R * round_up(L + 1, 4), 16);
+    l.scal_off = round_up((int64_t)R * code_bytes_of(L), 16);
     const int64_t end = l.scal_off + ((flags & PEOS_FLAG_FP16) ? 8LL : 16LL) * R;
     l.sig_off = (flags & PEOS_FLAG_SIMHASH) ? round_up(end, 16) : 0;
     l.stride = round_up((flags & PEOS_FLAG_SIMHASH) ? l.sig_off + 8LL * R : end, 128);
@@ -195,6 +200,7 @@ int ensure_kernel_attrs(int dev)
 
 struct SearchPlan {
     bool list_in_lds;  // a list capacity was forced: keep the list in LDS
+    bool regl;         // the list lives in registers (no LDS list)
     int listcap, listslack, hcap, visit_limit, slots;
     int64_t lds;
     int64_t spill_words;
@@ -226,10 +232,15 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     p.listcap = lc;
     // list entries first (the visited hash is sized below)
     p.listslack = (pool > 0 && pool <= efmax && !per_query) ? 0 : 64;
+    // the list in registers when every query's capacity is its own ef
+    // (<= 64): pool = 1 with per-query lists, or pool <= ef with one list
+    // size; it then takes no LDS (the output reuses the visited hash)
+    p.regl = efmax <= 64 && pool > 0 && (per_query ? pool == 1 : pool <= efmax) &&
+             !p.list_in_lds;
     // the table row width of the kernel instantiation: MAXL + 1
     const int64_t tw = (ix->L <= 8 ? 8 : (ix->L <= 16 ? 16 : 32)) + 1;
-    const int64_t fixed = 4LL * ix->d + 8LL * tw * ix->m + 8LL * (lc + p.listslack) +
-                          4LL * 2 * 64;
+    const int64_t fixed = 4LL * ix->d + 8LL * tw * ix->m +
+                          (p.regl ? 0 : 8LL * (lc + p.listslack)) + 4LL * 2 * 64;
     // visited hash: 32 slots per list entry, 2048 to 8192; for lists up to
     // 64 no more than fits the LDS share of the 16 waves per CU the kernel's
     // registers allow (down to 1024).  A query that fills 3/4 of it moves
@@ -243,9 +254,11 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     }
     if (t.hash_cap > 0) hc = t.hash_cap;
     hc &= ~3;  // whole buckets of four slots
+    if (p.regl && hc < 2 * 64) hc = 2 * 64;  // the output staging of the register list
     p.hcap = hc;
     p.visit_limit = (3 * hc) / 4;
-    // qv | table | list (lc + slack) | hash | survivor ids and distances.
+    // survivor ids and distances | qv | table | list (lc + slack; none in
+    // registers) | hash.
     // A merge writes up to one wave of survivors past the capacity; that
     // room (slack) is needed only when entries past ef are kept (pool above
     // ef, or the unbounded queue); when the capacity is ef they are dropped.
@@ -474,7 +487,7 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
     out->codes_offset = ix->codes_off;
     out->scalars_offset = ix->scal_off;
     const bool compact = (ix->flags & PEOS_FLAG_COMPACT) != 0;
-    out->code_bytes = compact ? 4 : round_up(ix->L + 1, 4);
+    out->code_bytes = compact ? 4 : code_bytes_of(ix->L);
     out->scalar_bytes = compact ? 2 : ((ix->flags & PEOS_FLAG_FP16) ? 8 : 16);
     out->bf16_offset = ix->bf16_off;
     out->simhash_offset = ix->sig_off;
@@ -573,8 +586,7 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     SearchPlan plan = plan_search(ix, nq, efmax, pool, per_query, cls);
     // the list in registers when every query's capacity is its own ef
     // (<= 64): pool = 1 with per-query lists, or pool <= ef with one list size
-    const bool regl = efmax <= 64 && pool > 0 && (per_query ? pool == 1 : pool <= efmax) &&
-                      !plan.list_in_lds;
+    const bool regl = plan.regl;
     if (slots_cap > 0 && plan.slots > slots_cap) plan.slots = slots_cap;
     if (plan.lds + kStaticLds > 64 * 1024) return fail(PEOS_EINVAL, "list/visited capacity needs %lld bytes of LDS", (long long)plan.lds);
     peos::SearchArgs a = base_args;

@@ -34,11 +34,13 @@ def test_library_exports_every_declared_symbol():
 
 def test_index_bytes_layout():
     ib, wb = P.peos_index_bytes(1000, 128, 32, 8, 16)
-    # per node: R * round_up(L+1, 4) code bytes padded to 16, then 4 floats per
-    # edge, padded to 128
+    # per node: R * round_up(B+1, 4) code bytes (B = 8, 16, 32, the kernel's
+    # subspace bound >= L) padded to 16, then 4 floats per edge, padded to 128
     assert ib == 1000 * 896 and wb > 0
     ib, _ = P.peos_index_bytes(10, 32, 16, 4, 16)
-    assert ib == 10 * 384
+    assert ib == 10 * 512
+    ib, _ = P.peos_index_bytes(10, 96, 16, 12, 16)
+    assert ib == 10 * 640
     ib, _ = P.peos_index_bytes(10, 960, 32, 16, 16)
     assert ib == 10 * 1152
 
