@@ -209,7 +209,9 @@ def main():
             f"qps {nq * args.steps / wall:.0f}")
         st = stats.cpu().numpy()
         log(f"per query: expansions {st[:, 0].mean():.1f} tests {st[:, 3].mean():.1f} "
-            f"ndist {st[:, 9].mean():.1f}")
+            f"ndist {st[:, 9].mean():.1f} (max {st[:, 9].max()}, p99 "
+            f"{np.percentile(st[:, 9], 99):.0f}); visited set spilled to HBM in "
+            f"{(st[:, 11] & P.PEOS_STATUS_VISITED_SPILL != 0).mean() * 100:.2f}% of queries")
         log("traffic key " + json.dumps(dict(kernel="k_search", source=kernel_digest(),
                                              workload=w.name, n=w.n, nq=nq, ef=cfg[0],
                                              pool=cfg[1], eps=cfg[2], mode=cfg[3],

@@ -176,14 +176,15 @@ int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int3
  * (Sec. 4.2: orthogonal decomposition e = e_reg + e_res of e = u - v, the
  * extreme-value codes e[0..L] against the projection vectors, and the weights
  * w_reg, w_res), plus the per-edge scalars the test of step (6) needs.
- *   base    n x d float, the vectors (ANGULAR expects unit-norm rows).
+ *   base    n x d float, the vectors (ANGULAR expects unit-norm rows),
+ *           16-byte aligned (rows are read as float4).
  *   graph   n x R int32 neighbour ids, -1 = no edge; ids in [0, n), no self
  *           loops and no repeated id within a row.
  *   entry   entry node v0 of the search (Alg. 1), in [0, n).
  *   dirs_a  L x m x (d/L) float: vectors a^i_j of subspace i (step (2)).
  *   dirs_b  m x d float: full-space vectors b_j (step (2)).
  *   metric  PEOS_METRIC_*.
- *   index_mem / index_bytes  caller buffer sized by peos_index_bytes.
+ *   index_mem / index_bytes  caller buffer sized by peos_index_bytes, 16-byte aligned.
  *   ws / ws_bytes            build workspace (peos_index_bytes).
  *   out     (host) receives a handle; free it with peos_free.
  * The handle records base, graph, dirs_a, dirs_b and index_mem (not copied).
@@ -285,7 +286,7 @@ int peos_set_upper_layers(peos_index* index, const peos_upper_layers* layers);
 /*
  * peos_query_tables -- PEOs step (5): the per-query projection table, built
  * once per query (Alg. 2, "only once and used throughout the search").
- *   queries  nq x d float.
+ *   queries  nq x d float, 16-byte aligned.
  *   tables   out, nq x (L+1) x m float: row 0 = q'.b_j, row i = q'_i . a^i_j
  *            with q' = q/|q| and q'_i its i-th block (not renormalized);
  *            IEEE halves (nq x (L+1) x m x 2 bytes) if the index has

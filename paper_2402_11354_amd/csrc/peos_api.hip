@@ -398,6 +398,8 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     if (rc) return rc;
     if (!base || !graph || !dirs_a || !dirs_b || !index_mem || !ws)
         return fail(PEOS_EINVAL, "null device pointer");
+    if (((uintptr_t)base & 15u) != 0 || ((uintptr_t)index_mem & 15u) != 0)
+        return fail(PEOS_EINVAL, "base and index_mem must be 16-byte aligned");
     if (entry < 0 || entry >= n) return fail(PEOS_EINVAL, "entry=%d out of range", entry);
     if (metric != PEOS_METRIC_L2 && metric != PEOS_METRIC_ANGULAR && metric != PEOS_METRIC_IP)
         return fail(PEOS_EINVAL, "metric=%d", metric);
@@ -747,6 +749,7 @@ static int check_search_args(const peos_index* ix, const float* queries, int64_t
     if (mode != PEOS_MODE_EXHAUSTIVE && !(eps > 0.f && eps <= 0.5f)) return fail(PEOS_EINVAL, "eps=%g not in (0, 0.5]", (double)eps);
     if (mode == PEOS_MODE_SIMHASH && !(ix->flags & PEOS_FLAG_SIMHASH)) return fail(PEOS_EINVAL, "PEOS_MODE_SIMHASH needs an index built with PEOS_FLAG_SIMHASH");
     if (nq > 0 && (!queries || !ids || !dists || !ws)) return fail(PEOS_EINVAL, "null device pointer");
+    if (((uintptr_t)queries & 15u) != 0) return fail(PEOS_EINVAL, "queries must be 16-byte aligned");
     return PEOS_OK;
 }
 
