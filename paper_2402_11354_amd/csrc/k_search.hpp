@@ -66,43 +66,85 @@ constexpr int kStatusZeroQuery = 1;
 constexpr int kStatusPoolFull = 2;
 constexpr int kStatusSpill = 4;
 
-// visited set: open addressing over buckets of four slots (one 16-byte LDS
-// read per probe), linear probing over cap/4 buckets (any number: the home
-// bucket is the multiplicative hash scaled to [0, cap/4)).  A bucket fills
-// front to back and nothing is ever removed, so a lookup may stop at the
-// first bucket that still has an empty slot.
+// visited set: buckets of four slots (one 16-byte LDS read each) over
+// cap/4 buckets, two candidate buckets per key (two multiplicative hashes
+// scaled to [0, cap/4)).  An insert takes the candidate with more free
+// slots; only when both are full does it go to the first bucket after the
+// first candidate that has room (linear probing).  Buckets fill front to back
+// and nothing is ever removed, so a lookup that finds a free slot in either
+// candidate is done, and otherwise scans on from the first candidate to the
+// first bucket with a free slot.  A lookup is one round of two parallel reads
+// unless both candidates are full, which two choices keep rare at the loads
+// the search allows (no long chains as with one choice).
 __device__ __forceinline__ uint32_t hash_bucket(uint32_t u, uint32_t nb)
 {
     return (uint32_t)(((uint64_t)(u * 0x9E3779B1u) * nb) >> 32);
 }
 
+__device__ __forceinline__ uint32_t hash_bucket2(uint32_t u, uint32_t nb)
+{
+    return (uint32_t)(((uint64_t)((u ^ (u >> 15)) * 0x85EBCA6Bu) * nb) >> 32);
+}
+
+__device__ __forceinline__ int free_slots(uint4 k)
+{
+    return (k.x == kEmpty) + (k.y == kEmpty) + (k.z == kEmpty) + (k.w == kEmpty);
+}
+
+__device__ __forceinline__ bool has_key(uint4 k, uint32_t u)
+{
+    return k.x == u || k.y == u || k.z == u || k.w == u;
+}
+
 __device__ __forceinline__ bool hash_lookup(const uint32_t* h, uint32_t cap, uint32_t u)
 {
     const uint32_t nb = cap >> 2;
-    uint32_t b = hash_bucket(u, nb);
+    const uint32_t b1 = hash_bucket(u, nb), b2 = hash_bucket2(u, nb);
+    const uint4 k1 = reinterpret_cast<const uint4*>(h)[b1];
+    const uint4 k2 = reinterpret_cast<const uint4*>(h)[b2];
+    if (has_key(k1, u) || has_key(k2, u)) return true;
+    if (k1.w == kEmpty || k2.w == kEmpty) return false;
+    // both candidates full: the overflow scan from the first candidate
+    uint32_t b = b1;
     for (;;) {
-        const uint4 k = reinterpret_cast<const uint4*>(h)[b];
-        if (k.x == u || k.y == u || k.z == u || k.w == u) return true;
-        if (k.w == kEmpty) return false;
         b = (b + 1u == nb) ? 0u : b + 1u;
+        const uint4 k = reinterpret_cast<const uint4*>(h)[b];
+        if (has_key(k, u)) return true;
+        if (k.w == kEmpty) return false;
     }
 }
 
 __device__ __forceinline__ void hash_insert(uint32_t* h, uint32_t cap, uint32_t u)
 {
     const uint32_t nb = cap >> 2;
-    uint32_t b = hash_bucket(u, nb);
+    const uint32_t b1 = hash_bucket(u, nb), b2 = hash_bucket2(u, nb);
     for (;;) {
-        const uint4 k = reinterpret_cast<const uint4*>(h)[b];
-        if (k.x == u || k.y == u || k.z == u || k.w == u) return;
-        const int e = k.x == kEmpty ? 0 : k.y == kEmpty ? 1 : k.z == kEmpty ? 2 : k.w == kEmpty ? 3 : -1;
-        if (e < 0) {
-            b = (b + 1u == nb) ? 0u : b + 1u;
-            continue;
+        const uint4 k1 = reinterpret_cast<const uint4*>(h)[b1];
+        const uint4 k2 = reinterpret_cast<const uint4*>(h)[b2];
+        if (has_key(k1, u) || has_key(k2, u)) return;
+        const int f1 = free_slots(k1), f2 = free_slots(k2);
+        uint32_t b;
+        uint4 k;
+        if (f1 == 0 && f2 == 0) {
+            // overflow: the first bucket after b1 with room
+            b = b1;
+            for (;;) {
+                b = (b + 1u == nb) ? 0u : b + 1u;
+                k = reinterpret_cast<const uint4*>(h)[b];
+                if (has_key(k, u)) return;
+                if (k.w == kEmpty) break;
+            }
+        } else if (f2 > f1) {
+            b = b2;
+            k = k2;
+        } else {
+            b = b1;
+            k = k1;
         }
+        const int e = k.x == kEmpty ? 0 : k.y == kEmpty ? 1 : k.z == kEmpty ? 2 : 3;
         const uint32_t prev = atomicCAS(&h[4 * b + e], kEmpty, u);
         if (prev == kEmpty || prev == u) return;
-        // another lane took the slot: read the bucket again
+        // another lane took the slot: read the candidates again
     }
 }
 
