@@ -366,7 +366,7 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
  * peos_set_search_tuning -- override the search kernel's launch plan for all
  * later calls in this process (0 keeps the automatic choice):
  *   hash_cap   visited-hash capacity in LDS, 64..16384 entries (rounded down
- *              to a multiple of 4); a query that visits more than 3/4 of it
+ *              to a multiple of 4); a query that visits more than 7/8 of it
  *              moves its visited set to a bitmap in the workspace
  *              (PEOS_STATUS_VISITED_SPILL);
  *   listcap    candidate-list capacity in LDS (rounded up to a multiple of 64

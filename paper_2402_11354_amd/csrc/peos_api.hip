@@ -243,7 +243,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
                           (p.regl ? 0 : 8LL * (lc + p.listslack)) + 4LL * 2 * 64;
     // visited hash: 32 slots per list entry, 2048 to 8192; for lists up to
     // 64 no more than fits the LDS share of the 16 waves per CU the kernel's
-    // registers allow (down to 1024).  A query that fills 3/4 of it moves
+    // registers allow (down to 1024).  A query that fills 7/8 of it moves
     // to the HBM bitmap (probes grow quickly past that load).
     int hc = 2048;
     while (hc < 32 * efmax && hc < 8192) hc *= 2;
@@ -256,7 +256,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     hc &= ~3;  // whole buckets of four slots
     if (p.regl && hc < 2 * 64) hc = 2 * 64;  // the output staging of the register list
     p.hcap = hc;
-    p.visit_limit = (3 * hc) / 4;
+    p.visit_limit = (7 * hc) / 8;
     // survivor ids and distances | qv | table | list (lc + slack; none in
     // registers) | hash.
     // A merge writes up to one wave of survivors past the capacity; that
