@@ -607,7 +607,8 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
 
                 // visited := visited + survivors
                 if (!spilled && nvis + ns > a.visit_limit) {
-                    for (int64_t w = lane; w < a.spill_words; w += kWave) bitmap[w] = 0u;
+                    for (int w = lane; w < (a.spill_words >> 2); w += kWave)
+                        reinterpret_cast<uint4*>(bitmap)[w] = make_uint4(0u, 0u, 0u, 0u);
                     __threadfence();
                     wave_sync();
                     for (int t = lane; t < hcap; t += kWave) {

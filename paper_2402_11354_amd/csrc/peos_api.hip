@@ -198,6 +198,10 @@ int ensure_kernel_attrs(int dev)
     return PEOS_OK;
 }
 
+// words of one visited bitmap: n bits, a whole number of 16-byte blocks (so
+// a slot's bitmap is cleared with 16-byte stores)
+int64_t spill_words_of(const peos_index* ix) { return round_up((ix->n + 31) / 32, 4); }
+
 struct SearchPlan {
     bool list_in_lds;  // a list capacity was forced: keep the list in LDS
     bool regl;         // the list lives in registers (no LDS list)
@@ -271,7 +275,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     if (t.slots > 0) slots = t.slots;
     if (slots > nq) slots = nq;
     p.slots = (int)(slots > 0 ? slots : 1);
-    p.spill_words = (ix->n + 31) / 32;
+    p.spill_words = spill_words_of(ix);
     return p;
 }
 
@@ -574,7 +578,7 @@ int peos_search_ws_bytes(const peos_index* ix, int64_t nq, int32_t efmax, int32_
     if (!ix || !ws_bytes) return fail(PEOS_EINVAL, "null pointer");
     if (nq < 0 || efmax < 1 || efmax > kMaxEf || pool < -16 || pool > 2 * kMaxEf)
         return fail(PEOS_EINVAL, "nq=%lld efmax=%d pool=%d", (long long)nq, efmax, pool);
-    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    WsLayout w = ws_layout(ix, nq, spill_words_of(ix));
     *ws_bytes = (size_t)w.total;
     return PEOS_OK;
 }
@@ -633,7 +637,7 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
                        size_t ws_bytes, hipStream_t s, int slots_cap = 0)
 {
     const int efmax = ef_all > k_all ? ef_all : k_all;
-    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    WsLayout w = ws_layout(ix, nq, spill_words_of(ix));
     if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
     int rc = ensure_kernel_attrs(ix->device);
     if (rc) return rc;
@@ -775,7 +779,7 @@ int peos_search(const peos_index* ix, const float* queries, int64_t nq, const in
     int rc = check_search_args(ix, queries, nq, k_all, ef_all, kstride, pool, eps, mode, ids, dists, ws);
     if (rc) return rc;
     if (nq == 0) return PEOS_OK;
-    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    WsLayout w = ws_layout(ix, nq, spill_words_of(ix));
     if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
     float* tables = (float*)((char*)ws + w.tables_off);
     float* qnorms = (float*)((char*)ws + w.qnorm_off);
@@ -851,7 +855,7 @@ int peos_graph_create(const peos_index* ix, const float* queries, int64_t nq, co
     int rc = check_search_args(ix, queries, nq, k_all, ef_all, kstride, pool, eps, mode, ids, dists, ws);
     if (rc) return rc;
     if (nq == 0) return fail(PEOS_EINVAL, "nq = 0: nothing to capture");
-    WsLayout w = ws_layout(ix, nq, (ix->n + 31) / 32);
+    WsLayout w = ws_layout(ix, nq, spill_words_of(ix));
     if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
     rc = ensure_kernel_attrs(ix->device);
     if (rc) return rc;

@@ -165,7 +165,7 @@ int serve_dispatch(peos_server* sv)
         HIP_TRY(hipMemcpyAsync(s->d_q, s->h_q, sizeof(float) * nqb * d, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(s->d_k, s->h_k, sizeof(int32_t) * nqb, hipMemcpyHostToDevice, st));
         HIP_TRY(hipMemcpyAsync(s->d_ef, s->h_ef, sizeof(int32_t) * nqb, hipMemcpyHostToDevice, st));
-        WsLayout w = ws_layout(ix, nqb, (ix->n + 31) / 32);
+        WsLayout w = ws_layout(ix, nqb, spill_words_of(ix));
         float* tables = (float*)((char*)s->d_ws + w.tables_off);
         float* qnorms = (float*)((char*)s->d_ws + w.qnorm_off);
         int rc = peos_query_tables(ix, s->d_q, nqb, tables, qnorms, st);
@@ -213,7 +213,7 @@ int peos_serve_open(const peos_index* ix, const peos_serve_config* cfg, peos_ser
     if (dev != ix->device) return fail(PEOS_EINVAL, "current device %d is not the index's %d", dev, ix->device);
     // memory of one slot
     const int64_t B = c.max_batch, K = c.max_k, d = ix->d;
-    WsLayout w = ws_layout(ix, B, (ix->n + 31) / 32);
+    WsLayout w = ws_layout(ix, B, spill_words_of(ix));
     const int64_t o_q = 0, o_k = align256(o_q + 4 * B * d), o_ef = align256(o_k + 4 * B),
                   o_ids = align256(o_ef + 4 * B), o_dist = align256(o_ids + 8 * B * K),
                   o_ws = align256(o_dist + 4 * B * K), dbytes = o_ws + w.total;
