@@ -245,17 +245,24 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     const int64_t tw = (ix->L <= 8 ? 8 : (ix->L <= 16 ? 16 : 32)) + 1;
     const int64_t fixed = 4LL * ix->d + 8LL * tw * ix->m +
                           (p.regl ? 0 : 8LL * (lc + p.listslack)) + 4LL * 2 * 64;
-    // visited hash: 32 slots per list entry, 2048 to 8192; for lists up to
-    // 64 no more than fits the LDS share of the 16 waves per CU the kernel's
-    // registers allow (down to 1024).  A query that fills 7/8 of it moves
-    // to the HBM bitmap (probes grow quickly past that load).
-    int hc = 2048;
-    while (hc < 32 * efmax && hc < 8192) hc *= 2;
-    if (hc == 2048) {
-        int64_t fit = (kLdsPerCu / 16 - kStaticLds - fixed) / 4;
-        fit = fit < 1024 ? 1024 : fit;
-        hc = fit < hc ? (int)fit : hc;
+    // visited hash.  A query that fills 7/8 of it moves to the HBM bitmap.
+    // Residency matters more than the odd spill (measured at ef = 96 and 128:
+    // a hash of about 20 slots per list entry beats one of 32 that halves the
+    // waves per CU), so: what fits the LDS share of the 16 waves per CU the
+    // kernel's registers allow, grown to 20 slots per list entry when that is
+    // more, 1024 to 8192.  The unbounded queue (pool = 0) visits several
+    // times more nodes per list entry: 32 slots per entry, from 2048, and
+    // for lists up to 64 the 16-wave fit.
+    const int64_t fit = (kLdsPerCu / 16 - kStaticLds - fixed) / 4;
+    int hc;
+    if (pool != 0) {
+        hc = 20 * efmax > fit ? 20 * efmax : (int)fit;
+    } else {
+        hc = 2048;
+        while (hc < 32 * efmax && hc < 8192) hc *= 2;
+        if (hc == 2048 && fit < hc) hc = (int)fit;
     }
+    hc = hc < 1024 ? 1024 : (hc > 8192 ? 8192 : hc);
     if (t.hash_cap > 0) hc = t.hash_cap;
     hc &= ~3;  // whole buckets of four slots
     if (p.regl && hc < 2 * 64) hc = 2 * 64;  // the output staging of the register list
