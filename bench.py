@@ -103,7 +103,14 @@ def main():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (a kernel of known traffic for "
                          "calibrating memory counters) and exit")
+    ap.add_argument("--gather-probe", action="store_true",
+                    help="only measure random 512-byte row gathers (the library's calibration "
+                         "kernel) over arrays of 64 MB to 4 GB: the practical HBM ceiling of "
+                         "the search's access pattern")
     args = ap.parse_args()
+
+    if args.gather_probe:
+        return gather_probe()
 
     if args.copy_calibrate:
         # a plain device copy of known size, for scaling memory counters
@@ -786,6 +793,43 @@ def serving(args):
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
         "recall@10": round(hits / max(1, total), 4), "rates": per_rate,
     }), flush=True)
+
+
+def gather_probe():
+    """Random 512-byte row gathers by the library's calibration kernel (8
+    lanes per row, 16 rows in flight per wave, the search's pattern) over
+    arrays of 64 MB to 4 GB, timed with events on the launch stream: the
+    practical HBM ceiling of the search's access pattern."""
+    import torch
+
+    import paper_2402_11354_amd as P
+
+    dev = torch.device("cuda:0")
+    iters = 64
+    res = []
+    for mb in (64, 512, 4096):
+        n = (mb << 20) // 512
+        x = torch.ones((n, 128), dtype=torch.float32, device=dev)
+        for waves in (2048, 4096, 16384):
+            sink = torch.empty(waves, dtype=torch.float32, device=dev)
+            s = torch.cuda.current_stream()
+            for _ in range(2):
+                P.peos_probe_gather(x, waves, iters, sink)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            e0.record(s)
+            for _ in range(reps):
+                P.peos_probe_gather(x, waves, iters, sink)
+            e1.record(s)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = waves * iters * 16 * 512 / (ms / 1e3) / 1e9
+            res.append({"array_mb": mb, "waves": waves, "ms": round(ms, 4),
+                        "gbs": round(gbs, 1)})
+            log(f"gather probe {mb} MB, {waves} waves: {ms:.3f} ms, {gbs:.0f} GB/s")
+        del x
+    print(json.dumps({"gather_probe": res, "row_bytes": 512, "iters": iters}), flush=True)
 
 
 def cpu_baseline(x, g, entry, q, w, cfg, budget_s):

@@ -468,6 +468,19 @@ int peos_serve_counters(const peos_server* server, int64_t* out);
  * are dropped). */
 void peos_serve_close(peos_server* server);
 /* Message for a return code, and the thread-local message of the last error. */
+/*
+ * peos_probe_gather -- calibration, not part of the search: `waves` waves
+ * each gather `iters` x 16 random 512-byte rows of `rows` (n_rows x 128
+ * float, 16-byte aligned) the way the search gathers survivor rows (8 lanes
+ * per row, 16 rows in flight per wave), and write one checksum per wave to
+ * sink (waves floats).  Asynchronous on `stream`; the caller times it.  It
+ * gives the practical HBM ceiling of the search's access pattern (the
+ * roofline's denominator is the nominal 8 TB/s).
+ * Errors: PEOS_EINVAL, PEOS_EDEVICE, PEOS_EHIP.
+ */
+int peos_probe_gather(const float* rows, int64_t n_rows, int32_t waves, int32_t iters,
+                      float* sink, void* stream);
+
 const char* peos_strerror(int code);
 const char* peos_last_error(void);
 

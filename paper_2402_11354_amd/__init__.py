@@ -102,6 +102,7 @@ def lib():
         L.peos_dimension_permutation_ws_bytes.argtypes = [i32, Psz]
         L.peos_dimension_permutation.argtypes = [P, i64, i32, P, i32, i32, P, P, sz, P]
         L.peos_set_upper_layers.argtypes = [P, ctypes.POINTER(peos_upper_layers)]
+        L.peos_probe_gather.argtypes = [P, i64, i32, i32, P, P]
         L.peos_free.argtypes = [P]
         L.peos_free.restype = None
         L.peos_query_tables.argtypes = [P, P, i64, P, P, P]
@@ -132,7 +133,7 @@ def lib():
                      "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
                      "peos_graph_create", "peos_graph_launch", "peos_serve_open",
                      "peos_serve_submit", "peos_serve_poll", "peos_serve_counters",
-                     "peos_set_upper_layers"):
+                     "peos_set_upper_layers", "peos_probe_gather"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -227,6 +228,13 @@ def peos_set_upper_layers(index, layers):
                            ls.ctypes.data, node.data_ptr(), adj.data_ptr(), down.data_ptr())
     _check("peos_set_upper_layers", lib().peos_set_upper_layers(index.handle, ctypes.byref(up)))
     index._upper = (node, adj, down)
+
+
+def peos_probe_gather(rows, waves, iters, sink, stream=None):
+    """Calibration gather of random 512-byte rows (peos_probe_gather).
+    rows: (n, 128) float32 device tensor; sink: (waves,) float32."""
+    _check("peos_probe_gather", lib().peos_probe_gather(_ptr(rows), rows.shape[0], int(waves),
+                                                        int(iters), _ptr(sink), _stream(stream)))
 
 
 def peos_dimension_permutation(base, graph, L, stream=None):

@@ -320,6 +320,40 @@ int num_classes(int efmax)
 
 }  // namespace
 
+namespace peos {
+
+// Calibration: random 512-byte rows gathered the way the search gathers
+// survivor rows (8 lanes per row, 4 float4 loads each, two groups of 8 rows
+// in flight per wave), `iters` rounds per wave, row indices from a
+// multiplicative hash of (wave, round, slot) reduced to [0, n_rows).
+__global__ __launch_bounds__(64) void k_probe_gather(const float4* rows, int64_t n_rows, int iters,
+                                                     float* sink)
+{
+    const int lane = lane_id();
+    const int grp = lane >> 3, sub = lane & 7;
+    float acc = 0.f;
+    for (int it = 0; it < iters; ++it) {
+        float4 v[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const uint64_t key = ((uint64_t)blockIdx.x * 131071u + (uint64_t)it * 8191u +
+                                  (uint64_t)(h * 8 + grp)) * 0x9E3779B97F4A7C15ull;
+            const int64_t r = (int64_t)((key >> 17) % (uint64_t)n_rows);
+            const float4* row = rows + r * 32;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[h][k] = row[sub + 8 * k];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc += v[h][k].x + v[h][k].y + v[h][k].z + v[h][k].w;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) sink[blockIdx.x] = acc;
+}
+
+}  // namespace peos
+
 extern "C" {
 
 const char* peos_last_error(void) { return g_err; }
@@ -797,6 +831,21 @@ int peos_search(const peos_index* ix, const float* queries, int64_t nq, const in
 }
 
 constexpr int kEnergyBlocks = 2048;
+
+int peos_probe_gather(const float* rows, int64_t n_rows, int32_t waves, int32_t iters,
+                      float* sink, void* stream)
+{
+    if (!rows || !sink) return fail(PEOS_EINVAL, "null pointer");
+    if (n_rows < 1 || waves < 1 || iters < 1) return fail(PEOS_EINVAL, "n_rows=%lld waves=%d iters=%d", (long long)n_rows, waves, iters);
+    if (((uintptr_t)rows & 15u) != 0) return fail(PEOS_EINVAL, "rows must be 16-byte aligned");
+    int dev;
+    int rc = check_device(&dev);
+    if (rc) return rc;
+    hipLaunchKernelGGL(peos::k_probe_gather, dim3((unsigned)waves), dim3(64), 0, (hipStream_t)stream,
+                       reinterpret_cast<const float4*>(rows), n_rows, iters, sink);
+    HIP_TRY(hipGetLastError());
+    return PEOS_OK;
+}
 
 int peos_dimension_permutation_ws_bytes(int32_t d, size_t* ws_bytes)
 {
