@@ -679,3 +679,15 @@ def test_list_beyond_lds_is_rejected(tiny):
     w = tiny.w
     with pytest.raises(P.PeosError):
         P.search(tiny.index, tiny.qt[:4], 10, 4096, eps=w.eps, pool=0)
+
+
+def test_calibration_gather_reads_every_row_it_names():
+    """peos_probe_gather over an array of ones: each wave sums 64 rounds x
+    16 rows x 128 ones."""
+    x = torch.ones((4096, 128), dtype=torch.float32, device=dev())
+    sink = torch.zeros(300, dtype=torch.float32, device=dev())
+    P.peos_probe_gather(x, 300, 64, sink)
+    torch.cuda.synchronize()
+    assert torch.all(sink == 64 * 16 * 128)
+    with pytest.raises(P.PeosError):
+        P.peos_probe_gather(x[:0], 300, 64, sink)
