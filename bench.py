@@ -323,6 +323,12 @@ def main():
                                   n=w.n, nq=nq, ef=ef, pool=pool, eps=eps, mode=mode,
                                   hash_cap=pe_cap))
 
+    # the practical ceiling of the access pattern: the library's calibration
+    # gather of random 512-byte rows over an array the size of the search's
+    # working set (base vectors + edge records), on the same box, same run
+    work_bytes = int(x.nbytes) + int(index.layout().node_stride) * w.n
+    ceiling = measure_gather_ceiling(work_bytes)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(x, g, entry, q, w, pe["cfg"], args.cpu_seconds)
@@ -380,7 +386,9 @@ def main():
                      "alg_bytes": round(pe_bytes),
                      "sector_bytes": round(pe_sector),
                      "sector_frac": round(pe_sector / (float(search_ms.mean()) / 1e3) / 1e9
-                                          / PEAK_HBM_GBS, 4)},
+                                          / PEAK_HBM_GBS, 4),
+                     "gather_ceiling": ceiling,
+                     "frac_of_gather_ceiling": round(achieved / ceiling, 4) if ceiling else None},
         "cpu_baseline": cpu,
         "sweep": {"peos": pts_json(pe_sweeps), "exhaustive": pts_json(ex_sweeps)},
     }
@@ -793,6 +801,38 @@ def serving(args):
         "p50_ms": top["p50_ms"], "p99_ms": top["p99_ms"],
         "recall@10": round(hits / max(1, total), 4), "rates": per_rate,
     }), flush=True)
+
+
+def measure_gather_ceiling(array_bytes, waves=4096, iters=64, reps=5):
+    """GB/s of the calibration gather (random 512-byte rows, the search's
+    pattern) over an array of array_bytes, or None if it cannot run."""
+    import torch
+
+    import paper_2402_11354_amd as P
+
+    try:
+        dev = torch.device("cuda:0")
+        n = max(1, array_bytes // 512)
+        x = torch.ones((n, 128), dtype=torch.float32, device=dev)
+        sink = torch.empty(waves, dtype=torch.float32, device=dev)
+        s = torch.cuda.current_stream()
+        for _ in range(2):
+            P.peos_probe_gather(x, waves, iters, sink)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            P.peos_probe_gather(x, waves, iters, sink)
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        gbs = waves * iters * 16 * 512 / (ms / 1e3) / 1e9
+        log(f"gather ceiling over {array_bytes / 2**30:.2f} GiB: {gbs:.0f} GB/s")
+        del x
+        return round(gbs, 1)
+    except (RuntimeError, P.PeosError) as e:
+        log(f"gather ceiling not measured: {e}")
+        return None
 
 
 def gather_probe():
