@@ -550,49 +550,43 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                         // angular distance already carries the 1/|q|.
                         const float diff = (a.metric == 0) ? 0.5f * (dv - delta) : (dv - delta);
                         const float num = H16 ? diff : ((a.metric == 0) ? sg + diff : diff);
-                        if (H16 ? !(se < INFINITY) : se == 0.f) {
-                            kind = 0;
-                            pass = num < 0.f;
+                        const bool zero = H16 ? !(se < INFINITY) : se == 0.f;
+                        const float A = H16 ? ((a.metric != 1) ? fmaf(diff, se, sg) * inv_qn : diff * se)
+                                            : num * __builtin_amdgcn_rcpf((a.metric != 1 ? qn : 1.f) * se);
+                        // zero-length edge: the sign of the numerator; A_r >= 1
+                        // fails, A_r <= 0 passes, otherwise H against T
+                        const bool ge1 = !zero && A >= 1.f;
+                        const bool le0 = !zero && !ge1 && A <= 0.f;
+                        kind = zero ? 0 : (ge1 ? 1 : (le0 ? 2 : 3));
+                        bool hpass;
+                        if (a.mode == 2) {
+                            // SimHash: collisions of the 64 sign bits
+                            const uint64_t es = ((uint64_t)cw[1 % NCW] << 32) | cw[0];
+                            const int col = 64 - popc(es ^ qsig);
+                            hpass = kind == 3 &&
+                                    (float)col >= 64.f * (1.f - acosf(A) * 0.318309886183790672f) - a.hoeff;
                         } else {
-                            const float A = H16 ? ((a.metric != 1) ? fmaf(diff, se, sg) * inv_qn : diff * se)
-                                                : num * __builtin_amdgcn_rcpf((a.metric != 1 ? qn : 1.f) * se);
-                            if (A >= 1.f) {
-                                kind = 1;
-                                pass = false;
-                            } else if (A <= 0.f) {
-                                kind = 2;
-                                pass = true;
-                            } else if (a.mode == 2) {
-                                // SimHash: collisions of the 64 sign bits
-                                kind = 3;
-                                const uint64_t es = ((uint64_t)cw[1 % NCW] << 32) | cw[0];
-                                const int col = 64 - popc(es ^ qsig);
-                                const float T = 64.f * (1.f - acosf(A) * 0.318309886183790672f) - a.hoeff;
-                                pass = (float)col >= T;
-                            } else {
-                                kind = 3;
-                                // code byte c: direction c mod m, negative iff c >= m;
-                                // the LDS table holds both signs, entry (i, c) at
-                                // c (MAXL+1) + i (one multiply per lookup, the
-                                // subspace in the instruction's offset); entries
-                                // past L are zero and the padding codes are 0, so
-                                // every lookup is issued without a branch
-                                auto signed_entry = [&](int i, uint32_t c) { return tab[(int)c * TW + i]; };
-                                // all lookups issued before the first add
-                                float tv[TW];
+                            // code byte c: direction c mod m, negative iff c >= m;
+                            // the LDS table holds both signs, entry (i, c) at
+                            // c (MAXL+1) + i (one multiply per lookup, the
+                            // subspace in the instruction's offset); entries
+                            // past L are zero and the padding codes are 0, so
+                            // every lookup is issued without a branch, for
+                            // every lane (the few that do not need H discard it)
+                            auto signed_entry = [&](int i, uint32_t c) { return tab[(int)c * TW + i]; };
+                            float tv[TW];
 #pragma unroll
-                                for (int i = 0; i <= MAXL; ++i)
-                                    tv[i] = signed_entry(i, (cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu);
-                                float h1 = 0.f;
+                            for (int i = 0; i <= MAXL; ++i)
+                                tv[i] = signed_entry(i, (cw[i >> 2] >> ((i & 3) * 8)) & 0xFFu);
+                            float h1 = 0.f;
 #pragma unroll
-                                for (int i = 1; i <= MAXL; ++i) h1 += tv[i];
-                                const float h2 = tv[0];
-                                const float H = sw * h1 + sr * h2;
-                                const float var = sw * sw + sr * sr - a.kappa * A * A;
-                                const float T = A * a.eta + a.c_eps * __builtin_amdgcn_sqrtf(var);
-                                pass = H >= T;
-                            }
+                            for (int i = 1; i <= MAXL; ++i) h1 += tv[i];
+                            const float H = sw * h1 + sr * tv[0];
+                            const float var = sw * sw + sr * sr - a.kappa * A * A;
+                            const float T = A * a.eta + a.c_eps * __builtin_amdgcn_sqrtf(var);
+                            hpass = H >= T;
                         }
+                        pass = zero ? num < 0.f : (ge1 ? false : (le0 ? true : hpass));
                     }
                     // every tested edge gets exactly one kind
                     lc_zero += kind == 0 ? 1 : 0;
