@@ -376,18 +376,24 @@ def build_graph(base: np.ndarray, R: int, cand: int, device="cpu", reverse: bool
 
 def ground_truth(base: np.ndarray, queries: np.ndarray, k: int, metric: int, device="cpu"):
     """Exact top-k ids and distances (squared l2, 1 - x.q/|q| for angular,
-    -x.q for the inner product), ordered by (distance, id)."""
-    device, dt = _dev_dtype(device)
+    -x.q for the inner product), ordered by (distance, id), in float64 on
+    any device (the recall reference: no single-precision cancellation in
+    |q|^2 + |x|^2 - 2 q.x)."""
+    device = torch.device(device)
+    dt = torch.float64
     x = torch.as_tensor(base).to(device=device, dtype=dt)
     q = torch.as_tensor(queries).to(device=device, dtype=dt)
     if metric == L2:
-        ids, dd = knn(x, q, k)
+        # 256 query rows x 1M columns of float64 per block (2 GB)
+        ids, dd = knn(x, q, k, row_chunk=256)
         return ids.cpu().numpy(), dd.cpu().numpy()
     qn = q if metric == IP else q / torch.linalg.norm(q, dim=1, keepdim=True)
     ids_all = []
     d_all = []
-    for s in range(0, q.shape[0], 2048):
-        sim = qn[s:s + 2048] @ x.T.contiguous()
+    xt = x.T.contiguous()
+    rows = max(1, (1 << 31) // (8 * x.shape[0]))  # about 2 GB of float64 per block
+    for s in range(0, q.shape[0], rows):
+        sim = qn[s:s + rows] @ xt
         kk = min(k + 8, x.shape[0])
         v, i = torch.topk(sim, kk, dim=1)
         dd = -v if metric == IP else 1.0 - v
