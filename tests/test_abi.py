@@ -78,3 +78,25 @@ def test_null_outputs_rejected():
     rc = lib.peos_build_tables(None, 10, 32, None, 16, 0, 4, 16, None, None, 0, 0, None, 0, None,
                                0, None, ctypes.byref(h))
     assert rc == -1 and not h.value
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built HIP library the binding raises; it has no other path."""
+    monkeypatch.setattr(P, "_lib", None)
+    monkeypatch.setattr(P, "LIB_PATH", str(tmp_path / "libpeos.so"))
+    with pytest.raises(RuntimeError, match="is missing"):
+        P.lib()
+
+
+def test_product_does_not_reach_the_oracle():
+    """The package and its kernels share nothing with the oracle: no import of
+    it, no include of its sources, no path into its folder."""
+    pkg = os.path.join(ROOT, "paper_2402_11354_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if not f.endswith((".py", ".hip", ".hpp", ".h", ".c", ".cpp")):
+                continue
+            src = open(os.path.join(dirpath, f)).read()
+            assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
+            assert not re.search(r"#\s*include\s*\"[^\"]*oracle", src), f
+            assert "peos_oracle" not in src, f
