@@ -258,6 +258,52 @@ def test_edge_cases(tiny):
         P.search(tiny.index, tiny.qt, w.k, w.ef, eps=0.7)
 
 
+def test_duplicate_vectors_and_single_node(tiny):
+    """Duplicated base vectors make zero-length edges: their codes take the
+    first direction, and the test decides them by the sign of the numerator
+    alone.  A one-node index returns its entry and padding."""
+    w = tiny.w
+    rng = np.random.default_rng(11)
+    x = tiny.x.copy()
+    n = x.shape[0]
+    src = rng.choice(n, n // 5, replace=False)
+    dst = rng.choice(np.setdiff1d(np.arange(n), src), n // 5, replace=False)
+    x[dst] = x[src]
+    g, entry = W.build_graph(x, w.R, w.cand, device="cpu")
+    A, B = tiny.A, tiny.B
+    index = P.peos_build_tables(T(x), T(g), entry, w.L, w.m, tiny.At, tiny.Bt, w.metric)
+    dup = Case.__new__(Case)
+    dup.w, dup.x, dup.q, dup.g, dup.entry, dup.A, dup.B = w, x, tiny.q, g, entry, A, B
+    dup.index, dup.qt = index, tiny.qt
+    codes, sc = read_records(dup)
+    rc, rs, _ = O.build_tables(x, g, w.L, w.m, A, B)
+    valid = g >= 0
+    assert np.array_equal(codes[valid], rc[valid])
+    zero = valid & (rs[..., 0] == 0)
+    assert zero.sum() >= n // 10
+    assert np.all(sc[..., 1][zero] == 0)
+    for pool_mul in (0, 1):
+        pool = pool_mul * w.ef
+        ids, d, st = run(dup, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool)
+        ref = dup.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool)
+        assert ref["counters"][:, O.COUNTERS.index("test_zero")].sum() > 0
+        res = compare(ids, d, st, ref, w.k)
+        print(f"[gpu] duplicates pool={pool}: checked={res['checked']} fragile={res['fragile']}")
+        assert not res["bad"], res["bad"][:5]
+        # a twin at exactly the list's bound is a tie with delta, which marks
+        # the query fragile: about a fifth of these queries meet one
+        assert res["checked"] >= 0.7 * len(ids)
+    # one node, no edges
+    one = P.peos_build_tables(T(tiny.x[:1]), T(np.full((1, w.R), -1, np.int32)), 0, w.L, w.m,
+                              tiny.At, tiny.Bt, w.metric)
+    ids, d, st = P.search(one, tiny.qt[:5], w.k, w.ef)
+    torch.cuda.synchronize()
+    ids, d = ids.cpu().numpy(), d.cpu().numpy()
+    assert np.all(ids[:, 0] == 0) and np.all(ids[:, 1:] == -1) and np.all(np.isinf(d[:, 1:]))
+    ref = ((tiny.x[0].astype(np.float64) - tiny.q[:5].astype(np.float64)) ** 2).sum(1)
+    np.testing.assert_allclose(d[:, 0], ref, rtol=1e-5)
+
+
 def test_large_list(tiny):
     """ef = 256 (the largest in the sweeps) with the queue unbounded."""
     w = tiny.w
