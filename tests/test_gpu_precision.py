@@ -28,9 +28,9 @@ def T(a):
 
 
 class Case:
-    def __init__(self, w):
+    def __init__(self, w, base=None):
         self.w = w
-        self.x = W.make_base(w)
+        self.x = W.make_base(w) if base is None else base
         self.q = W.make_queries(w)
         self.g, self.entry = W.build_graph(self.x, w.R, w.cand)
         self.A, self.B = W.directions_for(w)
@@ -217,6 +217,35 @@ def test_half_form_against_oracle(which, flags, request):
     rec = lambda I: np.mean([len(set(I[i]) & set(gt[i])) / w.k for i in range(len(I))])
     print(f"[gpu] {which} flags={flags}: recall {rec(ids):.4f} vs full {rec(full[0]):.4f}")
     assert rec(ids) >= rec(full[0]) - 0.005
+
+
+@pytest.fixture(scope="module")
+def dup():
+    print("[gpu] precision: tiny workload with a fifth of its vectors duplicated", flush=True)
+    w = W.TINY
+    x = W.make_base(w)
+    rng = np.random.default_rng(11)
+    n = x.shape[0]
+    src = rng.choice(n, n // 5, replace=False)
+    dst = rng.choice(np.setdiff1d(np.arange(n), src), n // 5, replace=False)
+    x[dst] = x[src]
+    return Case(w, base=x)
+
+
+@pytest.mark.parametrize("flags", [P.PEOS_FLAG_FP16, P.PEOS_FLAG_FP16 | P.PEOS_FLAG_BF16_BASE])
+def test_half_form_zero_length_edges(dup, flags):
+    """A zero-length edge stores 1/|e| as the half infinity; the test then
+    decides it by the numerator's sign, as the oracle's precision form does."""
+    w = dup.w
+    ids, d, st = dup.run(flags, pool=w.ef)
+    ref = dup.oracle(flags, pool=w.ef)
+    assert ref["counters"][:, O.COUNTERS.index("test_zero")].sum() > 0
+    frag = ref["fragile"] != 0
+    same = np.all(ids == ref["ids"], axis=1) & np.all(d.astype(np.float64) == ref["dist"], axis=1)
+    print(f"[gpu] duplicates flags={flags}: identical {same[~frag].mean():.3f} of non-fragile")
+    assert same[~frag].mean() >= 0.9
+    zero_tests = st[:, 7].sum()
+    assert zero_tests > 0
 
 
 @pytest.fixture(scope="module")
