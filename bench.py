@@ -293,15 +293,11 @@ def main():
     P.peos_set_search_tuning(0, 0, 0)
 
     # algorithmic bytes of one search launch, from the kernel's own counters
-    code_bytes = 4 * ((w.L + 4) // 4)
+    lay = index.layout()
+    code_bytes = lay.code_bytes
 
     def alg_bytes(st):
-        per_q = (4.0 * w.R * st[:, 0]                  # neighbour ids of each expansion
-                 + (code_bytes + 16.0) * st[:, 3]      # codes + 4 fp32 scalars per tested edge
-                 + 4.0 * w.d * st[:, 9]                # exact distances
-                 + 4.0 * w.d + 4.0 * (w.L + 1) * w.m    # query vector and table
-                 + 12.0 * w.k)                         # outputs
-        return float(per_q.sum())
+        return search_alg_bytes(st, lay, w.k, pe["cfg"][0])
 
     def sector_bytes(st):
         """The same accesses rounded to whole 64-byte sectors as the kernel
@@ -395,6 +391,36 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def search_alg_bytes(st, lay, k, ef):
+    """Algorithmic bytes of one search call, summed over its queries, from the
+    kernel's own counters and the index layout: the neighbour ids of each
+    expansion, the codes and scalars of each tested edge (and the compact
+    records' node header per expansion that ran the test), one vector row per
+    exact distance (bfloat16 rows with the traversal copy, then the fp32
+    re-rank of the final list), the query and its table, the outputs, and an
+    id and a row per distance of the upper-layer descent."""
+    st = np.asarray(st, np.float64)
+    compact = bool(lay.flags & 8)
+    bf = bool(lay.flags & 1)
+    half = bool(lay.flags & 2)
+    e = 2.0 if bf else 4.0
+    per_q = (4.0 * lay.R * st[:, 0]
+             + float(lay.code_bytes + lay.scalar_bytes) * st[:, 3]
+             + (16.0 * st[:, 13] if compact else 0.0)
+             + e * lay.d * st[:, 9]
+             + 4.0 * lay.d + (2.0 if half else 4.0) * (lay.L + 1) * lay.m
+             + 12.0 * k
+             + (4.0 * lay.d * ef if bf else 0.0)
+             + (e * lay.d + 4.0) * st[:, 12])
+    return float(per_q.sum())
+
+
+def alg_rate(st, lay, k, ef, qps):
+    """Bytes per query and the rate they are moved at (TB/s; the peak is 8)."""
+    b = search_alg_bytes(st, lay, k, ef) / max(len(st), 1)
+    return dict(alg_bytes_per_query=round(b, 1), alg_TBps=round(b * qps / 1e12, 3))
+
+
 def _setup(name, n, nq, gt_k):
     """Data, graph, edge records and exact top-gt_k of a named workload."""
     import torch
@@ -482,10 +508,7 @@ def batched(args):
             sel = np.nonzero(k >= 10)[0]
             rec["recall@10 (k>=10)"] = round(float(_recall(x, q[sel], ii[sel], gt_d[sel, :10],
                                                            10, w.metric).mean()), 4)
-            code_bytes = 4 * ((w.L + 4) // 4)
-            alg = float((4.0 * w.R * st[:, 0] + (code_bytes + 16.0) * st[:, 3]
-                         + 4.0 * w.d * st[:, 9] + 4.0 * w.d + 4.0 * (w.L + 1) * w.m
-                         + 12.0 * k).sum())
+            alg = search_alg_bytes(st, index.layout(), np.asarray(k, np.float64), 0)
             r = dict(qps=round(nq * args.steps / wall, 1), ms=round(float(ms.mean()), 4),
                      p99_ms=round(float(np.percentile(ms, 99)), 4), recall=rec,
                      ndist=round(float(st[:, 9].mean()), 1),
@@ -555,7 +578,8 @@ def precision(args):
                     d64 = 1.0 - (xs[ids] * qs[:, None, :]).sum(-1) / qs.norm(dim=1)[:, None]
                 err = ((dd.double() - d64).abs() / d64.clamp(min=1e-30)).max().item()
                 pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
-                                max_rel_dist_err=err))
+                                max_rel_dist_err=err,
+                                **alg_rate(st.cpu().numpy(), ix.layout(), k, ef, qps)))
                 log(f"precision k={k} {label} ef={ef}: recall={rec:.4f} qps={qps:.0f} "
                     f"max rel err={err:.2e}")
             ok = [p_ for p_ in pts if p_["recall"] >= args.target]
@@ -620,7 +644,8 @@ def compact(args):
             s_ = st.cpu().numpy()
             pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
                             ndist=round(float(s_[:, 9].mean()), 1),
-                            tests=round(float(s_[:, 3].mean()), 1)))
+                            tests=round(float(s_[:, 3].mean()), 1),
+                            **alg_rate(s_, ix.layout(), 10, ef, qps)))
             log(f"compact {key} ef={ef}: recall={rec:.4f} qps={qps:.0f}")
             if rec >= args.target + 0.02:
                 break
@@ -695,7 +720,8 @@ def descent(args):
             pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
                             expansions=round(float(s_[:, 0].mean()), 1),
                             ndist=round(float(s_[:, 9].mean()), 1),
-                            descent_ndist=round(float(s_[:, 12].mean()), 1)))
+                            descent_ndist=round(float(s_[:, 12].mean()), 1),
+                            **alg_rate(s_, ix.layout(), 10, ef, qps)))
             log(f"descent {key} ef={ef}: recall={rec:.4f} qps={qps:.0f} "
                 f"expansions={pts[-1]['expansions']} descent={pts[-1]['descent_ndist']}")
             if rec >= args.target + 0.02:
