@@ -103,6 +103,8 @@ def main():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (a kernel of known traffic for "
                          "calibrating memory counters) and exit")
+    ap.add_argument("--prec-ef", type=int, default=0,
+                    help="precision mode: time only k = 10 at this ef (for profiler runs)")
     ap.add_argument("--gather-probe", action="store_true",
                     help="only measure random 512-byte row gathers (the library's calibration "
                          "kernel) over arrays of 64 MB to 4 GB: the practical HBM ceiling of "
@@ -555,8 +557,10 @@ def precision(args):
     xs = torch.from_numpy(x).to(dev).double()
     qs = qt.double()
     result = {}
-    for k, efs in ((10, (32, 64, 128, 192, 256, 384, 512)),
-                   (100, (128, 192, 256, 384, 512, 768, 1024))):
+    plan = ((10, (32, 64, 128, 192, 256, 384, 512)), (100, (128, 192, 256, 384, 512, 768, 1024)))
+    if args.prec_ef:
+        plan = ((10, (args.prec_ef,)),)
+    for k, efs in plan:
         ws = torch.empty(P.peos_search_ws_bytes(index, nq, max(efs), max(efs)),
                          dtype=torch.uint8, device=dev)
         rows = {}
