@@ -381,6 +381,18 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
 int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots);
 
 /*
+ * peos_set_long_rows -- allow (1, the default) or forbid (0) the search
+ * kernel's long-vector variant for all later calls in this process.  The
+ * variant is chosen for d > 512 and L > 8 with the list in LDS when at most
+ * 8 waves per CU would be resident anyway (the list and visited hash fill
+ * the LDS share of more, or the batch is at most 2048 queries): it may use
+ * the registers of two waves per SIMD and gathers 8 rows of up to 1024
+ * coordinates per round trip, in the same fixed summation order, so results
+ * do not depend on it.  Errors: PEOS_EINVAL for other values.
+ */
+int peos_set_long_rows(int32_t enable);
+
+/*
  * peos_set_class_tuning -- launch plan of one ef class of a split batch (see
  * peos_search_tables; class c holds lists of size <= 32 << c, c in [0, 8)):
  * visited-hash capacity and resident waves, 0 = automatic.  Overrides

@@ -111,6 +111,7 @@ def lib():
                                          P, P, sz, P]
         L.peos_search.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P, sz, P]
         L.peos_set_search_tuning.argtypes = [i32, i32, i32]
+        L.peos_set_long_rows.argtypes = [i32]
         L.peos_set_class_tuning.argtypes = [i32, i32, i32]
         L.peos_serve_open.argtypes = [P, ctypes.POINTER(peos_serve_config), ctypes.POINTER(P)]
         L.peos_serve_submit.argtypes = [P, P, i32, i32, i32, P, P, ctypes.POINTER(ctypes.c_uint64)]
@@ -130,7 +131,8 @@ def lib():
                      "peos_build_tables_ex", "peos_dimension_permutation_ws_bytes",
                      "peos_dimension_permutation",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
-                     "peos_search", "peos_set_search_tuning", "peos_set_class_tuning",
+                     "peos_search", "peos_set_search_tuning", "peos_set_long_rows",
+                     "peos_set_class_tuning",
                      "peos_graph_create", "peos_graph_launch", "peos_serve_open",
                      "peos_serve_submit", "peos_serve_poll", "peos_serve_counters",
                      "peos_set_upper_layers", "peos_probe_gather"):
@@ -301,6 +303,11 @@ def peos_search(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, sta
 def peos_set_search_tuning(hash_cap=0, listcap=0, slots=0):
     """Override the search launch plan (0 = automatic); see include/peos.h."""
     _check("peos_set_search_tuning", lib().peos_set_search_tuning(hash_cap, listcap, slots))
+
+
+def peos_set_long_rows(enable=True):
+    """Allow or forbid the long-vector search variant; see include/peos.h."""
+    _check("peos_set_long_rows", lib().peos_set_long_rows(1 if enable else 0))
 
 
 def peos_set_class_tuning(cls, hash_cap=0, slots=0):

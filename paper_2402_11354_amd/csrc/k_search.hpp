@@ -30,6 +30,9 @@ namespace peos {
 constexpr int kFlagBf16Base = 1;
 constexpr int kFlagFp16 = 2;
 constexpr int kFlagCompact = 8;
+// launch variant, not an index flag: long vectors at low occupancy (at most
+// two waves per SIMD, so a wave has the registers for 2 x 16 rows in flight)
+constexpr int kVariantLong = 16;
 constexpr int kCompactLutBins = 256;
 
 struct SearchArgs {
@@ -181,7 +184,11 @@ struct Chunk<true> {
     }
 };
 
-template <int G, int PER, int K, bool BF>
+// CLAMP: every lane issues all its loads (an idle slot reads row 0, a chunk
+// past the row re-reads the last one) and discards the extra terms with a
+// select, so the loads are straight-line code the compiler keeps in flight
+// together (with exec-masked loads it waits for each before the next).
+template <int G, int PER, int K, bool BF, bool CLAMP = false>
 __device__ __forceinline__ void gather_distances(const void* base, int d, const uint32_t* Su, int ns,
                                                  const float* qv, int metric, float inv_qn,
                                                  float* Sdist)
@@ -212,23 +219,25 @@ __device__ __forceinline__ void gather_distances(const void* base, int d, const 
 #pragma unroll
             for (int j = 0; j < NP; ++j) part[pp][j] = 0.f;
         }
-        for (int k0 = 0; s + G * k0 < nch; k0 += K) {
+        for (int k0 = 0; (CLAMP ? 0 : s) + G * k0 < nch; k0 += K) {
             raw xv[PER][K];
 #pragma unroll
             for (int pp = 0; pp < PER; ++pp)
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk) {
                     const int c = s + G * (k0 + kk);
-                    if (act[pp] && c < nch) xv[pp][kk] = x4[pp][c];
+                    if (CLAMP) xv[pp][kk] = x4[pp][c < nch ? c : nch - 1];
+                    else if (act[pp] && c < nch) xv[pp][kk] = x4[pp][c];
                 }
 #pragma unroll
             for (int pp = 0; pp < PER; ++pp)
 #pragma unroll
                 for (int kk = 0; kk < K; ++kk) {
                     const int c = s + G * (k0 + kk);
-                    if (act[pp] && c < nch) {
+                    const bool ok = act[pp] && c < nch;
+                    if (CLAMP || ok) {
                         const float4 x = Chunk<BF>::get(xv[pp][kk]);
-                        const float4 q = q4[c];
+                        const float4 q = q4[CLAMP ? (c < nch ? c : nch - 1) : c];
                         float acc = part[pp][kk % NP];
                         if (metric == 0) {
                             const float t0 = x.x - q.x, t1 = x.y - q.y, t2 = x.z - q.z, t3 = x.w - q.w;
@@ -242,7 +251,7 @@ __device__ __forceinline__ void gather_distances(const void* base, int d, const 
                             acc = fmaf(x.z, q.z, acc);
                             acc = fmaf(x.w, q.w, acc);
                         }
-                        part[pp][kk % NP] = acc;
+                        part[pp][kk % NP] = (CLAMP && !ok) ? part[pp][kk % NP] : acc;
                     }
                 }
         }
@@ -269,22 +278,29 @@ __device__ __forceinline__ void gather_distances(const void* base, int d, const 
     }
 }
 
-template <bool BF, bool WIDE = false>
+template <bool BF, bool WIDE = false, bool LONG = false>
 __device__ __forceinline__ void distances(const void* base, int d, const uint32_t* Su, int ns,
                                           const float* qv, int metric, float inv_qn, float* Sdist)
 {
     // 4..16 lanes per vector; each lane keeps at most 8 chunk loads in
     // flight (one round trip for up to 16 vectors of 128 coordinates).
     // Long bfloat16 vectors: 16 lanes x 16 chunks (8 bytes each) cover up to
-    // 1024 coordinates in one round trip per 4 vectors.
+    // 1024 coordinates in one round trip per 4 vectors.  The low-occupancy
+    // variant keeps two such rows per lane group in flight: one round trip
+    // per 8 vectors of up to 1024 coordinates, fp32 or bfloat16 (it is
+    // only launched for d > 512, and is correct for any d).
+    if (LONG) {
+        gather_distances<16, 2, 16, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+        return;
+    }
     if (WIDE && d > 512) {
         gather_distances<16, 1, 16, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
         return;
     }
-    if (ns <= 4) gather_distances<16, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 8) gather_distances<8, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else if (ns <= 16) gather_distances<4, 1, 8, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
-    else gather_distances<4, 2, 4, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    if (ns <= 4) gather_distances<16, 1, 8, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 8) gather_distances<8, 1, 8, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else if (ns <= 16) gather_distances<4, 1, 8, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    else gather_distances<4, 2, 4, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
 }
 
 #ifndef PEOS_SEARCH_WAVES_PER_EU
@@ -295,8 +311,10 @@ __device__ __forceinline__ void distances(const void* base, int d, const uint32_
 // the HNSW stopping rule): entry i lives in lane i's registers (rd, ri), so
 // the pop is a ballot and the merge a register scatter through LDS staging.
 template <int MAXL, int FLAGS, bool REGL>
-__global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchArgs a)
+__global__ __launch_bounds__(64, (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_PER_EU) void k_search(
+    SearchArgs a)
 {
+    constexpr bool LONG = (FLAGS & kVariantLong) != 0;
     constexpr bool BF = (FLAGS & kFlagBf16Base) != 0;
     constexpr bool H16 = (FLAGS & kFlagFp16) != 0;
     constexpr bool CP = (FLAGS & kFlagCompact) != 0;
@@ -621,7 +639,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 }
                 nvis += ns;
                 wave_sync();
-                distances<BF, (MAXL >= 16) && BF>(tbase, d, Su, ns, qv, a.metric, inv_qn, Sdist);
+                distances<BF, (MAXL >= 16) && BF, LONG>(tbase, d, Su, ns, qv, a.metric, inv_qn, Sdist);
                 st_ndist += ns;
                 wave_sync();
 
@@ -779,7 +797,7 @@ __global__ __launch_bounds__(64, PEOS_SEARCH_WAVES_PER_EU) void k_search(SearchA
                 const int cnt = nr - c0 < kWave ? nr - c0 : kWave;
                 if (lane < cnt) Su[lane] = Li[c0 + lane] & kIdMask;
                 wave_sync();
-                distances<false, false>(a.base, d, Su, cnt, qv, a.metric, inv_qn, Sdist);
+                distances<false, false, LONG>(a.base, d, Su, cnt, qv, a.metric, inv_qn, Sdist);
                 wave_sync();
                 if (lane < cnt) Ld[c0 + lane] = Sdist[lane];
                 wave_sync();

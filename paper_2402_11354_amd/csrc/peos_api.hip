@@ -167,6 +167,7 @@ double norm_ppf(double p)
 
 struct Tuning {
     int hash_cap = 0, listcap = 0, slots = 0;
+    bool no_long = false;  // never choose the long-vector variant
 };
 std::mutex g_tune_mu;
 Tuning g_tune;
@@ -184,12 +185,17 @@ int ensure_kernel_attrs(int dev)
 #define PEOS_FNS(ML, RG)                                                                      \
     (const void*)peos::k_search<ML, 0, RG>, (const void*)peos::k_search<ML, 1, RG>,          \
         (const void*)peos::k_search<ML, 2, RG>, (const void*)peos::k_search<ML, 3, RG>
+#define PEOS_FNS_LONG(ML)                                                                     \
+    (const void*)peos::k_search<ML, 16, false>, (const void*)peos::k_search<ML, 17, false>,   \
+        (const void*)peos::k_search<ML, 18, false>, (const void*)peos::k_search<ML, 19, false>
         const void* fns[] = {PEOS_FNS(8, false),  PEOS_FNS(16, false), PEOS_FNS(32, false),
                              PEOS_FNS(8, true),   PEOS_FNS(16, true),  PEOS_FNS(32, true),
                              (const void*)peos::k_search<8, 8, false>,
                              (const void*)peos::k_search<8, 9, false>,
                              (const void*)peos::k_search<8, 8, true>,
-                             (const void*)peos::k_search<8, 9, true>};
+                             (const void*)peos::k_search<8, 9, true>,
+                             PEOS_FNS_LONG(16), PEOS_FNS_LONG(32)};
+#undef PEOS_FNS_LONG
 #undef PEOS_FNS
         for (const void* f : fns)
             HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
@@ -205,6 +211,7 @@ int64_t spill_words_of(const peos_index* ix) { return round_up((ix->n + 31) / 32
 struct SearchPlan {
     bool list_in_lds;  // a list capacity was forced: keep the list in LDS
     bool regl;         // the list lives in registers (no LDS list)
+    bool long_rows;    // the low-occupancy variant for long vectors
     int listcap, listslack, hcap, visit_limit, slots;
     int64_t lds;
     int64_t spill_words;
@@ -277,6 +284,12 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     int64_t per_cu = kLdsPerCu / (p.lds + kStaticLds);
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 16) per_cu = 16;
+    // long vectors (d > 512, L > 8, list in LDS): when the LDS or the batch
+    // allows at most 8 waves per CU anyway, the variant with the registers
+    // of two waves per SIMD keeps twice the rows in flight
+    p.long_rows = ix->d > 512 && ix->L > 8 && !(ix->flags & PEOS_FLAG_COMPACT) && !p.regl &&
+                  (per_cu <= 8 || nq <= 8 * kNumCu) && !t.no_long;
+    if (p.long_rows && per_cu > 8) per_cu = 8;
     int64_t slots = per_cu * kNumCu;
     if (slots > kMaxSlots) slots = kMaxSlots;
     if (t.slots > 0) slots = t.slots;
@@ -357,6 +370,14 @@ __global__ __launch_bounds__(64) void k_probe_gather(const float4* rows, int64_t
 extern "C" {
 
 const char* peos_last_error(void) { return g_err; }
+
+int peos_set_long_rows(int32_t enable)
+{
+    if (enable != 0 && enable != 1) return fail(PEOS_EINVAL, "enable=%d", enable);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune.no_long = enable == 0;
+    return PEOS_OK;
+}
 
 int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots)
 {
@@ -653,8 +674,16 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     case 2: hipLaunchKernelGGL((peos::k_search<ML, 2, RG>), grid, dim3(64), lds, s, a); break;     \
     default: hipLaunchKernelGGL((peos::k_search<ML, 3, RG>), grid, dim3(64), lds, s, a); break;    \
     }
+#define PEOS_LAUNCH_LONG(ML)                                                                      \
+    switch (ix->flags & kFlagsAll) {                                                              \
+    case 0: hipLaunchKernelGGL((peos::k_search<ML, 16, false>), grid, dim3(64), lds, s, a); break; \
+    case 1: hipLaunchKernelGGL((peos::k_search<ML, 17, false>), grid, dim3(64), lds, s, a); break; \
+    case 2: hipLaunchKernelGGL((peos::k_search<ML, 18, false>), grid, dim3(64), lds, s, a); break; \
+    default: hipLaunchKernelGGL((peos::k_search<ML, 19, false>), grid, dim3(64), lds, s, a); break;\
+    }
 #define PEOS_LAUNCH(ML)                                                                           \
     if (regl) { PEOS_LAUNCH2(ML, true) } else { PEOS_LAUNCH2(ML, false) }
+    static_assert(peos::kVariantLong == 16, "long-vector variants are FLAGS + 16");
     // compact records (L <= 4): their own variants of the L <= 8 kernel
     if (ix->flags & PEOS_FLAG_COMPACT) {
         const bool bf = (ix->flags & PEOS_FLAG_BF16_BASE) != 0;
@@ -663,10 +692,13 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
         else if (bf) hipLaunchKernelGGL((peos::k_search<8, 9, false>), grid, dim3(64), lds, s, a);
         else hipLaunchKernelGGL((peos::k_search<8, 8, false>), grid, dim3(64), lds, s, a);
     } else if (ix->L <= 8) { PEOS_LAUNCH(8) }
+    else if (plan.long_rows && ix->L <= 16) { PEOS_LAUNCH_LONG(16) }
+    else if (plan.long_rows) { PEOS_LAUNCH_LONG(32) }
     else if (ix->L <= 16) { PEOS_LAUNCH(16) }
     else { PEOS_LAUNCH(32) }
 #undef PEOS_LAUNCH
 #undef PEOS_LAUNCH2
+#undef PEOS_LAUNCH_LONG
     HIP_TRY(hipGetLastError());
     return PEOS_OK;
 }

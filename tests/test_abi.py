@@ -100,3 +100,11 @@ def test_product_does_not_reach_the_oracle():
             assert not re.search(r"^\s*(from|import)\s+oracle\b", src, flags=re.M), f
             assert not re.search(r"#\s*include\s*\"[^\"]*oracle", src), f
             assert "peos_oracle" not in src, f
+
+
+def test_long_rows_switch_validates():
+    lib = P.lib()
+    assert lib.peos_set_long_rows(2) == P.PEOS_EINVAL
+    assert lib.peos_set_long_rows(-1) == P.PEOS_EINVAL
+    assert lib.peos_set_long_rows(0) == P.PEOS_OK
+    assert lib.peos_set_long_rows(1) == P.PEOS_OK

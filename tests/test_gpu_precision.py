@@ -270,3 +270,21 @@ def test_long_vectors_match_oracle(wide, flags, pool_mul):
     print(f"[gpu] wide flags={flags} pool={pool_mul * w.ef}: checked={res['checked']}")
     assert not res["bad"], res["bad"][:5]
     assert res["checked"] >= 0.8 * len(ids)
+
+
+@pytest.mark.parametrize("flags", [0, P.PEOS_FLAG_BF16_BASE,
+                                   P.PEOS_FLAG_BF16_BASE | P.PEOS_FLAG_FP16])
+@pytest.mark.parametrize("pool_mul", [0, 2])
+def test_long_row_variant_changes_nothing(wide, flags, pool_mul):
+    """The long-vector variant (two waves per SIMD, 8 rows per round trip) is
+    chosen here (d = 768, L = 16, list in LDS, 60 queries); forbidding it
+    gives the standard kernels.  Ids, distances and every counter agree."""
+    w = wide.w
+    a = wide.run(flags, pool=pool_mul * w.ef)
+    try:
+        P.peos_set_long_rows(False)
+        b = wide.run(flags, pool=pool_mul * w.ef)
+    finally:
+        P.peos_set_long_rows(True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
