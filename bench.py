@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--pool", default="ef")
     ap.add_argument("--eps", type=float, default=0.1)
     ap.add_argument("--hash-cap", type=int, default=0, help="with --profile-only: visited-hash capacity")
+    ap.add_argument("--slots", type=int, default=0,
+                    help="with --profile-only: resident waves of the persistent grid")
     ap.add_argument("--listcap", type=int, default=0,
                     help="with --profile-only: force an LDS list of this capacity")
     ap.add_argument("--mode", default="headline",
@@ -211,7 +213,7 @@ def main():
         return wall, step_ms, table_ms, search_ms
 
     if args.profile_only:
-        P.peos_set_search_tuning(args.hash_cap, args.listcap, 0)
+        P.peos_set_search_tuning(args.hash_cap, args.listcap, args.slots)
         cfg = (args.ef, pool_of(args.pool, args.ef), args.eps, P.PEOS_MODE_PEOS)
         wall, sms, tms, srch = timed(cfg, args.steps, args.warmup)
         log(f"profile-only {cfg}: step {sms.mean():.3f} ms search {srch.mean():.3f} ms "
