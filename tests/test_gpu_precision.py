@@ -288,3 +288,41 @@ def test_long_row_variant_changes_nothing(wide, flags, pool_mul):
         P.peos_set_long_rows(True)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def wide_ang():
+    print("[gpu] precision: long-vector angular workload (d = 768)", flush=True)
+    return Case(W.Workload("wide_sphere_2k_d768", 2000, 40, 768, 16, 32, 16, 16, W.ANGULAR,
+                           "sphere500", 0.1, 10, 32, 1009))
+
+
+@pytest.fixture(scope="module")
+def wide_ip():
+    print("[gpu] precision: long-vector inner-product workload (d = 768)", flush=True)
+    return Case(W.Workload("wide_ip_gmm_2k_d768", 2000, 40, 768, 16, 32, 16, 16, W.IP, "gmm10",
+                           0.1, 10, 32, 1010))
+
+
+@pytest.mark.parametrize("which", ["wide_ang", "wide_ip"])
+@pytest.mark.parametrize("flags", [0, P.PEOS_FLAG_BF16_BASE])
+def test_long_rows_angular_and_inner_product(which, flags, request):
+    """The long-vector variant under the other two metrics: parity with the
+    oracle, and the same results with the variant forbidden."""
+    case = request.getfixturevalue(which)
+    w = case.w
+    ids, d, st = case.run(flags, pool=0)
+    ref = case.oracle(flags, pool=0) if flags else O.search(
+        case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B, w.metric, w.eps,
+        pool=0, precision=32)
+    res = compare(ids, d, st, ref, w.k)
+    print(f"[gpu] {which} flags={flags}: checked={res['checked']} fragile={res['fragile']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+    try:
+        P.peos_set_long_rows(False)
+        other = case.run(flags, pool=0)
+    finally:
+        P.peos_set_long_rows(True)
+    for x, y in zip((ids, d, st), other):
+        assert np.array_equal(x, y)
