@@ -326,3 +326,32 @@ def test_long_rows_angular_and_inner_product(which, flags, request):
         P.peos_set_long_rows(True)
     for x, y in zip((ids, d, st), other):
         assert np.array_equal(x, y)
+
+
+def test_long_rows_simhash(wide):
+    """The SimHash test (mode 2) runs in the long-vector variant too."""
+    w = wide.w
+    C = np.random.default_rng(43).normal(size=(64, w.d)).astype(np.float32)
+    idx = P.peos_build_tables(wide.xt, wide.gt, wide.entry, w.L, w.m, wide.At, wide.Bt, w.metric,
+                              flags=P.PEOS_FLAG_SIMHASH, simhash_dirs=T(C))
+
+    def run():
+        ids, d, st = P.search(idx, wide.qt, w.k, w.ef, eps=0.1, mode=P.PEOS_MODE_SIMHASH, pool=0)
+        torch.cuda.synchronize()
+        return ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+
+    ids, d, st = run()
+    ref = O.search(wide.x, wide.g, wide.entry, wide.q, w.k, w.ef, w.L, w.m, wide.A, wide.B,
+                   w.metric, 0.1, mode=O.MODE_SIMHASH, pool=0, precision=32, simhash=C)
+    res = compare(ids, d, st, ref, w.k)
+    print(f"[gpu] wide simhash: checked={res['checked']} fragile={res['fragile']}")
+    assert not res["bad"], res["bad"][:5]
+    assert res["checked"] >= 0.8 * len(ids)
+    assert st[:, 6].sum() > 0
+    try:
+        P.peos_set_long_rows(False)
+        other = run()
+    finally:
+        P.peos_set_long_rows(True)
+    for x, y in zip((ids, d, st), other):
+        assert np.array_equal(x, y)
