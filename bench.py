@@ -105,6 +105,8 @@ def main():
     ap.add_argument("--copy-calibrate", type=int, default=0, metavar="MIB",
                     help="only run one device copy of MIB MiB (a kernel of known traffic for "
                          "calibrating memory counters) and exit")
+    ap.add_argument("--compact-L", type=int, default=2,
+                    help="compact mode: subspaces of the compact records (1..4)")
     ap.add_argument("--prec-ef", type=int, default=0,
                     help="precision mode: time only k = 10 at this ef (for profiler runs)")
     ap.add_argument("--gather-probe", action="store_true",
@@ -622,7 +624,7 @@ def compact(args):
     w, x, q, g, entry, index, gt_d = _setup(args.workload, args.n, args.nq, 10)
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
-    Lc = 2
+    Lc = args.compact_L
     Ac, Bc = W.make_directions(Lc, w.m, w.d, w.seed + 2000)
     comp = P.peos_build_tables(index._keep[0], index._keep[1], entry, Lc, w.m, T(Ac), T(Bc),
                                w.metric, flags=P.PEOS_FLAG_COMPACT)
