@@ -612,7 +612,7 @@ def precision(args):
 
 
 def compact(args):
-    """The compact records (L = 2, w_reg = 1, w_res = 0, two 8-bit scalars per
+    """The compact records (L = --compact-L, default 2; w_reg = 1, w_res = 0, two 8-bit scalars per
     edge, quantile table) against the full records at the workload's L, on the
     same graph, under the HNSW stopping rule: QPS at recall@10 >= target over
     an ef sweep, and the bytes of an edge record."""
