@@ -131,7 +131,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; sharding across GPUs is a "
+        print(json.dumps({"error": "this library runs on one GPU only; sharding across GPUs is a "
                                    "design note, not a code path", "n_gpus": args.gpus}))
         sys.exit(2)
 
