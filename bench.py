@@ -107,6 +107,8 @@ def main():
                          "calibrating memory counters) and exit")
     ap.add_argument("--compact-L", type=int, default=2,
                     help="compact mode: subspaces of the compact records (1..4)")
+    ap.add_argument("--no-long-rows", action="store_true",
+                    help="forbid the long-vector search variant (for comparisons)")
     ap.add_argument("--prec-ef", type=int, default=0,
                     help="precision mode: time only k = 10 at this ef (for profiler runs)")
     ap.add_argument("--gather-probe", action="store_true",
@@ -549,6 +551,8 @@ def precision(args):
     import paper_2402_11354_amd as P
     import workloads as W
 
+    if args.no_long_rows:
+        P.peos_set_long_rows(False)
     name = args.workload if args.workload != "sift_like_1m_d128" else "gist_like_1m_d960"
     w, x, q, g, entry, index, gt_d = _setup(name, args.n, args.nq, 100)
     dev = torch.device("cuda:0")
