@@ -212,10 +212,13 @@ def search(base, graph, entry, queries, k, ef, L, m, A, B, metric, eps, mode=MOD
     query's ef.  precision: 64 = distances in float64;
     32 = the distance decisions taken on the canonical single-precision
     distances (the GPU kernel's precision; see dist32 in peos_oracle.c).
-    lowp: precision form (implies precision 32): LP_FP16 = routing test on
-    half-rounded edge scalars and tables; LP_BF16_BASE = traversal on the
-    bfloat16-rounded base, result list re-ranked in single precision on the
-    full base (see routing_test_lowp and oracle_search in peos_oracle.c).
+    lowp: precision form (LP_FP16 and LP_BF16_BASE imply precision 32):
+    LP_FP16 = routing test on half-rounded edge scalars and tables;
+    LP_BF16_BASE = traversal on the bfloat16-rounded base, result list
+    re-ranked in single precision on the full base (see routing_test_lowp and
+    oracle_search in peos_oracle.c); LP_COMPACT = the compact records' test
+    (its scalar codes and quantile table are single-precision decisions in
+    either precision; the search distances follow `precision`).
     perm: optional dimension permutation (d ints) of the test: edge records
     and tables on permuted coordinates, distances on the original ones.
     simhash: (nb, d) sign-projection vectors, required by MODE_SIMHASH.

@@ -438,15 +438,15 @@ double oracle_threshold(double A, double w_reg, double w_res, int L, double eta,
  */
 static int routing_test(const test_params* tp, const edge_rec* er, const double* table,
                         double num, double qnorm, double* outA, double* outH, double* outT,
-                        int* kind, int* flags, int v_is_p)
+                        int* kind, int* flags, int num_exact)
 {
     const double tau = tp->tau;
     *outA = NAN;
     *outH = NAN;
     *outT = NAN;
-    /* the numerator is exactly 0 in any precision only for the angular and
-       inner-product metrics with v = p; for l2 it is then g_e */
-    const int exact0 = v_is_p && tp->metric != OR_L2;
+    /* num_exact: the sign of the numerator is the same in any precision (see
+       numerator_is_exact), so A_r near 0 is not a fragile decision */
+    const int exact0 = num_exact;
     if (er->norm_e == 0.0) {
         *kind = 0;
         if (!exact0 && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
@@ -553,10 +553,10 @@ static void simhash_bits_fp32(const float* v, int d, const float* C, int nb, uin
  */
 static int routing_test_simhash(const test_params* tp, double norm_e, int col, int nb,
                                 double num, double qnorm, double eps, int* kind, int* flags,
-                                int v_is_p)
+                                int num_exact)
 {
     const double tau = tp->tau;
-    const int exact0 = v_is_p && tp->metric != OR_L2;
+    const int exact0 = num_exact;
     if (norm_e == 0.0) {
         *kind = 0;
         if (!exact0 && fabs(num) <= tau * fabs(qnorm)) *flags |= F_A0;
@@ -1017,6 +1017,51 @@ typedef struct {
  *  - a survivor enters the list when R was not full or its distance is
  *    < delta.
  */
+/*
+ * When is the sign of the test's numerator the same in single precision as in
+ * double?  The numerator of A_r (step (6)) is, for l2, g_e + (dist_v -
+ * delta)/2 with g_e = (|u|^2 - |v|^2)/2, and for the inner product dist_v -
+ * delta.  If every coordinate of x_u, x_v, x_p and q is an integer and the
+ * squared norms and distances involved stay below 2^22, each of these terms
+ * is a sum of integer products whose every partial sum is an integer below
+ * 2^24 -- exact in single precision in any summation order -- and the
+ * numerator itself is a multiple of 1/2 below 2^23, also exact.  Its sign
+ * (the A_r <= 0 decision) then cannot depend on the precision, so a small
+ * |A_r| is not a fragile decision.  The same holds for angular and inner
+ * product when v = p (the numerator is then exactly 0 on both sides).
+ */
+static int integer_valued(const float* x, int d)
+{
+    for (int k = 0; k < d; ++k)
+        if (!(fabsf(x[k]) < 16777216.0f) || x[k] != floorf(x[k])) return 0;
+    return 1;
+}
+
+/* The same argument for a comparison of two search distances (list order,
+   d_u against delta): with q and both vectors integer-valued and squared l2
+   distances (or |inner products|) below 2^24, single precision computes both
+   exactly, so their order cannot depend on the precision. */
+static int distances_are_exact(const search_job* j, int q_int, int32_t a, int32_t b, double da,
+                               double db)
+{
+    const double lim = 16777216.0; /* 2^24 */
+    if (!q_int || (j->metric != OR_L2 && j->metric != OR_IP)) return 0;
+    if (!(fabs(da) < lim) || !(fabs(db) < lim)) return 0;
+    return integer_valued(j->base + (size_t)a * j->d, j->d) &&
+           integer_valued(j->base + (size_t)b * j->d, j->d);
+}
+
+static int numerator_is_exact(int metric, int v_is_p, int ints, double nu2, double nv2, double dv,
+                              double delta)
+{
+    const double lim = 4194304.0; /* 2^22 */
+    if (metric != OR_L2 && v_is_p) return 1;
+    if (!ints) return 0;
+    if (metric == OR_L2) return nu2 < lim && nv2 < lim && dv < lim && delta < lim;
+    if (metric == OR_IP) return fabs(dv) < lim && fabs(delta) < lim;
+    return 0;
+}
+
 /* work space of the compact form: the node header and edge codes of the
    node being expanded, and the quantile table */
 typedef struct {
@@ -1067,6 +1112,7 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
     }
     uint64_t qsig[4] = {0, 0, 0, 0};
     if (j->mode == OR_MODE_SIMHASH) simhash_bits_fp32(q, d, j->simhash, j->nb, qsig);
+    const int q_int = !j->lowp && integer_valued(q, d);
     if (j->mode == OR_MODE_PEOS) {
         oracle_query_table(qperm ? qperm : q, d, j->L, j->m, j->A, j->B, table);
         if (j->lowp & LP_FP16)
@@ -1100,11 +1146,13 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         const int32_t p = full ? R[efq - 1].id : -1;
         if (full && j->mode != OR_MODE_EXHAUSTIVE) cnt[C_TEST_EXPANSIONS]++;
         double vq = 0.0, r = 0.0;
+        int vp_int = 0; /* x_v, x_p and q integer-valued (see numerator_is_exact) */
         if (full && j->mode != OR_MODE_EXHAUSTIVE) {
             const float* xp = j->base + (size_t)p * d;
             vq = dot64(xv, q, d);
             if (j->metric == OR_L2) r = 0.5 * dot64(xp, xp, d) - dot64(xp, q, d);
             else r = -dot64(xp, q, d);
+            vp_int = q_int && integer_valued(xv, d) && integer_valued(xp, d);
         }
         int ns = 0;
         int have_hdr = 0;
@@ -1135,8 +1183,11 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
                 else num = -r - vq;
                 (void)nv2;
                 int kind;
+                const int ex = numerator_is_exact(j->metric, v == p,
+                                                  vp_int && integer_valued(xu, d), nu2, nv2, dv,
+                                                  delta);
                 pass = routing_test_simhash(tp, sqrt(ne2), j->nb - diff, j->nb, num, qnorm, j->eps,
-                                            &kind, &flags, v == p);
+                                            &kind, &flags, ex);
                 cnt[C_TESTS]++;
                 cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
                 if (pass) cnt[C_PASSES]++;
@@ -1203,7 +1254,9 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
                                              &flags, v == p);
                 else
                     pass = routing_test(tp, &er, table, num, qnorm, &A, &H, &T, &kind, &flags,
-                                        v == p);
+                                        numerator_is_exact(j->metric, v == p,
+                                                           vp_int && integer_valued(xu, d),
+                                                           er.nu2, er.nv2, dv, delta));
                 cnt[C_TESTS]++;
                 cnt[kind == 0 ? C_TEST_ZERO : kind == 1 ? C_TEST_GE1 : kind == 2 ? C_TEST_LE0 : C_TEST_H]++;
                 if (pass) cnt[C_PASSES]++;
@@ -1212,7 +1265,9 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             visited[u] = 1;
             cnt[C_NDIST]++;
             double du = DIST(xu);
-            if (!j->fp32 && full && fabs(du - delta) < j->tau * fabs(delta)) flags |= F_DELTA;
+            if (!j->fp32 && full && fabs(du - delta) < j->tau * fabs(delta) &&
+                !distances_are_exact(j, q_int, u, p, du, delta))
+                flags |= F_DELTA;
             if (!full || du < delta) {
                 S[ns].dist = du;
                 S[ns].id = u;
@@ -1226,6 +1281,28 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
         memcpy(R + size, S, sizeof(rentry) * (size_t)ns);
         int tot = size + ns;
         qsort(R, (size_t)tot, sizeof(rentry), rcmp);
+        if (!j->fp32) {
+            /* which entries stay, in which order, and which one is popped next
+               all follow the order of the merged list up to the first entry
+               the capacity drops: a query is fragile if two adjacent entries
+               of that stretch have distances within tau */
+            int kept = 0, last = tot - 1;
+            for (int i = 0; i < tot; ++i) {
+                if (i >= efq && R[i].expanded) continue;
+                if (kept >= cap) {
+                    last = i;
+                    break;
+                }
+                ++kept;
+            }
+            for (int i = 1; i <= last; ++i) {
+                double a = R[i - 1].dist, b = R[i].dist;
+                double sc = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
+                if (a != b && fabs(a - b) < j->tau * sc &&
+                    !distances_are_exact(j, q_int, R[i - 1].id, R[i].id, a, b))
+                    flags |= F_ORDER;
+            }
+        }
         int w = 0;
         for (int i = 0; i < tot; ++i) {
             if (i >= efq && R[i].expanded) continue;
@@ -1233,11 +1310,6 @@ static void search_one(const search_job* j, int64_t qi, const test_params* tp, u
             R[w++] = R[i];
         }
         size = w;
-        for (int i = 1; i < size && !j->fp32; ++i) {
-            double a = R[i - 1].dist, b = R[i].dist;
-            double sc = fabs(a) > fabs(b) ? fabs(a) : fabs(b);
-            if (a != b && fabs(a - b) < j->tau * sc) flags |= F_ORDER;
-        }
     }
     if (j->lowp & LP_BF16_BASE) {
         /* precision form: the result list (first ef entries) re-ranked by
@@ -1442,7 +1514,8 @@ int oracle_search(const float* base, int64_t n, int d, const int32_t* graph, int
     for (int t = 0; t < nthreads; ++t) {
         jobs[t] = (search_job){base, A, B, queries, graph, k, ef, n, nq * t / nthreads,
                                nq * (t + 1) / nthreads, d, R, L, m, metric, mode, entry, kstride,
-                               pool, fp32 || lowp, lowp, perm, simhash, nb, entries, eps, tau,
+                               pool, fp32 || (lowp & (LP_BF16_BASE | LP_FP16)), lowp, perm,
+                               simhash, nb, entries, eps, tau,
                                out_ids,
                                out_dist, out_dist64, counters, fragile, status};
         pthread_create(&th[t], NULL, search_worker, &jobs[t]);

@@ -751,10 +751,41 @@ def test_fp32_decisions_equal_fp64_away_from_near_ties(metric, pool_mul):
     o64 = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, precision=64, **kw)
     o32 = O.search(x, g, entry, q, 10, 32, w.L, w.m, A, B, metric, 0.1, precision=32, **kw)
     clean = (o64["fragile"] & (O.F_DELTA | O.F_ORDER)) == 0
-    assert clean.sum() >= 0.3 * len(q)
+    # observed: 69-82% of the queries clean on these workloads, and the two
+    # precisions agree on every query (clean or not)
+    assert clean.sum() >= 0.65 * len(q)
     assert np.array_equal(o64["ids"][clean], o32["ids"][clean])
     assert np.array_equal(o64["counters"][clean], o32["counters"][clean])
     np.testing.assert_allclose(o32["dist64"][clean], o64["dist"][clean], rtol=0, atol=0)
+    assert np.mean(np.all(o64["ids"] == o32["ids"], axis=1)) >= 0.97
+
+
+@pytest.mark.parametrize("metric", [W.L2, W.IP])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_integer_data_decisions_do_not_depend_on_precision(metric, pool_mul):
+    """On integer-valued vectors with squared norms and distances below 2^22
+    every distance, delta and A_r numerator is an integer (or half-integer)
+    that single precision computes exactly in any order, so the search's
+    distance decisions and the sign of A_r cannot depend on the precision:
+    none of them is flagged, and the single- and double-precision searches are
+    identical on every query (ids, distances, counters)."""
+    w = W.SIFT_LIKE.with_sizes(n=6000, nq=60)
+    x, q = W.make_base(w), W.make_queries(w)
+    assert np.all(x == np.floor(x)) and (x.astype(np.float64) ** 2).sum(1).max() < 2 ** 22
+    g, entry = W.build_graph(x, w.R, w.cand)
+    A, B = W.directions_for(w)
+    kw = dict(pool=pool_mul * 48)
+    o64 = O.search(x, g, entry, q, 10, 48, w.L, w.m, A, B, metric, 0.2, precision=64, **kw)
+    o32 = O.search(x, g, entry, q, 10, 48, w.L, w.m, A, B, metric, 0.2, precision=32, **kw)
+    assert np.all(o64["fragile"] & (O.F_DELTA | O.F_ORDER | O.F_A0) == 0)
+    assert np.array_equal(o64["ids"], o32["ids"])
+    assert np.array_equal(o64["counters"], o32["counters"])
+    assert np.array_equal(o64["dist"], o32["dist"])
+    # the same data shifted by 1/3 is not integer-valued: near ties are flagged again
+    xs, qs = x + np.float32(1 / 3), q + np.float32(1 / 3)
+    o64s = O.search(xs, g, entry, qs, 10, 48, w.L, w.m, A, B, metric, 0.2, precision=64, **kw)
+    if metric == W.L2:
+        assert np.any(o64s["fragile"] & (O.F_DELTA | O.F_ORDER))
 
 
 # ---------------------------------------------------------------------------
@@ -1203,7 +1234,8 @@ def test_compact_vanishing_eps_reproduces_exhaustive_search(metric):
     A, B = W.make_directions(L, w.m, w.d, 9)
     ex = O.search(x, g, entry, q, 10, 16, L, w.m, A, B, metric, 0.1, mode=O.MODE_EXHAUSTIVE,
                   precision=32)
-    pe = O.search(x, g, entry, q, 10, 16, L, w.m, A, B, metric, 1e-300, lowp=O.LP_COMPACT)
+    pe = O.search(x, g, entry, q, 10, 16, L, w.m, A, B, metric, 1e-300, lowp=O.LP_COMPACT,
+                  precision=32)
     assert np.array_equal(ex["ids"], pe["ids"])
     np.testing.assert_array_equal(ex["dist"], pe["dist"])
     ci = O.COUNTERS.index
