@@ -363,8 +363,15 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
                 size_t ws_bytes, void* stream);
 
 /*
- * peos_set_search_tuning -- override the search kernel's launch plan for all
- * later calls in this process (0 keeps the automatic choice):
+ * Launch plan of an index's searches.  The plan changes speed only, never a
+ * result (except through the list capacity with pool = 0, see listcap); it
+ * belongs to the index: overrides set here apply to every later search on
+ * that index (peos_search, peos_search_tables, captured graphs created
+ * afterwards, servers over it) and to no other index.  Not to be called while
+ * another thread searches the same index.
+ *
+ * peos_set_search_tuning -- overrides for every launch (0 keeps the
+ * automatic choice):
  *   hash_cap   visited-hash capacity in LDS, 64..16384 entries (rounded down
  *              to a multiple of 4); a query that visits more than 7/8 of it
  *              moves its visited set to a bitmap in the workspace
@@ -374,40 +381,48 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
  *              kernel capacity that PEOS_STATUS_POOL_FULL refers to.  Setting
  *              it also keeps the list in LDS where it would otherwise live in
  *              registers (capacity = ef <= 64);
- *   slots      resident waves of the persistent grid, 1..4096.
- * Results do not depend on the tuning except through the pool capacity.
- * Errors: PEOS_EINVAL for values out of range.
+ *   slots      resident workgroups of the persistent grid, 1..4096;
+ *   waves      wavefronts per query, 1, 2 or 4 (0 automatic: 4 or 2 when
+ *              every query of the batch can still be resident at once,
+ *              else 1).  One workgroup of that many waves searches a query:
+ *              wave 0 runs the search and all of them gather the survivor
+ *              rows, each row still reduced by one wave in the fixed order,
+ *              so results do not depend on it.
+ * Errors: PEOS_EINVAL for a null index or values out of range.
  */
-int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots);
+int peos_set_search_tuning(peos_index* index, int32_t hash_cap, int32_t listcap, int32_t slots,
+                           int32_t waves);
 
 /*
  * peos_set_long_rows -- allow (1, the default) or forbid (0) the search
- * kernel's long-vector variant for all later calls in this process.  The
+ * kernel's long-vector variant for later searches on this index.  The
  * variant is chosen for d > 512 and L > 8 with the list in LDS when at most
  * 8 waves per CU would be resident anyway (the list and visited hash fill
- * the LDS share of more, or the batch is at most 2048 queries): it may use
- * the registers of two waves per SIMD and gathers 8 rows of up to 1024
+ * the LDS share of more, or the batch is at most 8 queries per CU): it may
+ * use the registers of two waves per SIMD and gathers 8 rows of up to 1024
  * coordinates per round trip, in the same fixed summation order, so results
- * do not depend on it.  Errors: PEOS_EINVAL for other values.
+ * do not depend on it.  Errors: PEOS_EINVAL for a null index or other values.
  */
-int peos_set_long_rows(int32_t enable);
+int peos_set_long_rows(peos_index* index, int32_t enable);
 
 /*
- * peos_set_class_tuning -- launch plan of one ef class of a split batch (see
+ * peos_set_class_tuning -- overrides of one ef class of a split batch (see
  * peos_search_tables; class c holds lists of size <= 32 << c, c in [0, 8)):
- * visited-hash capacity and resident waves, 0 = automatic.  Overrides
- * peos_set_search_tuning for that class.  Results do not depend on it.
- * Errors: PEOS_EINVAL for values out of range.
+ * visited-hash capacity, resident workgroups and waves per query as in
+ * peos_set_search_tuning, 0 = automatic.  They take precedence over
+ * peos_set_search_tuning's for that class.  Errors: PEOS_EINVAL for a null
+ * index or values out of range.
  */
-int peos_set_class_tuning(int32_t cls, int32_t hash_cap, int32_t slots);
+int peos_set_class_tuning(peos_index* index, int32_t cls, int32_t hash_cap, int32_t slots,
+                          int32_t waves);
 /*
  * peos_graph_create -- capture one peos_search call (projection tables,
  * class split and search launches; no memset nodes) into an executable HIP
  * graph, so that a batch of the same shape is issued with one launch.
  * Arguments as for peos_search; every pointer is baked into the graph, so the
  * caller refills queries (and k, ef) in place between launches and reads
- * ids/dists/stats after each.  Tuning in effect at capture time is frozen in
- * the graph.  Output *out (host); release with peos_graph_destroy.
+ * ids/dists/stats after each.  The index's launch plan in effect at capture
+ * time is frozen in the graph.  Output *out (host); release with peos_graph_destroy.
  * Errors: as peos_search, PEOS_EINVAL for nq = 0, PEOS_EHIP if capture or
  * instantiation fails.
  */

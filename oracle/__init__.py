@@ -41,7 +41,8 @@ COMPACT_LUT_BINS = 256
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "peos_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# PEOS_ORACLE_LIB: another build of the same source (the sanitizer test's)
+_LIB = os.environ.get("PEOS_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

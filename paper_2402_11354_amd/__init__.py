@@ -110,9 +110,9 @@ def lib():
         L.peos_search_tables.argtypes = [P, P, P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P,
                                          P, P, sz, P]
         L.peos_search.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P, sz, P]
-        L.peos_set_search_tuning.argtypes = [i32, i32, i32]
-        L.peos_set_long_rows.argtypes = [i32]
-        L.peos_set_class_tuning.argtypes = [i32, i32, i32]
+        L.peos_set_search_tuning.argtypes = [P, i32, i32, i32, i32]
+        L.peos_set_long_rows.argtypes = [P, i32]
+        L.peos_set_class_tuning.argtypes = [P, i32, i32, i32, i32]
         L.peos_serve_open.argtypes = [P, ctypes.POINTER(peos_serve_config), ctypes.POINTER(P)]
         L.peos_serve_submit.argtypes = [P, P, i32, i32, i32, P, P, ctypes.POINTER(ctypes.c_uint64)]
         L.peos_serve_poll.argtypes = [P, i32, P, i32, ctypes.POINTER(i32)]
@@ -131,7 +131,8 @@ def lib():
                      "peos_build_tables_ex", "peos_dimension_permutation_ws_bytes",
                      "peos_dimension_permutation",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
-                     "peos_search", "peos_set_search_tuning", "peos_set_long_rows",
+                     "peos_search", "peos_set_search_tuning",
+                     "peos_set_long_rows",
                      "peos_set_class_tuning",
                      "peos_graph_create", "peos_graph_launch", "peos_serve_open",
                      "peos_serve_submit", "peos_serve_poll", "peos_serve_counters",
@@ -176,6 +177,7 @@ class PeosIndex:
     def __init__(self, handle, keep):
         self.handle = handle
         self._keep = keep
+        self.tuned_waves = 0  # waves per query the autotuner chose (0 = automatic)
 
     def layout(self):
         return peos_index_layout(self)
@@ -300,19 +302,21 @@ def peos_search(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, sta
                              _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)))
 
 
-def peos_set_search_tuning(hash_cap=0, listcap=0, slots=0):
-    """Override the search launch plan (0 = automatic); see include/peos.h."""
-    _check("peos_set_search_tuning", lib().peos_set_search_tuning(hash_cap, listcap, slots))
+def peos_set_search_tuning(index, hash_cap=0, listcap=0, slots=0, waves=0):
+    """Override the index's search launch plan (0 = automatic); see include/peos.h."""
+    _check("peos_set_search_tuning",
+           lib().peos_set_search_tuning(index.handle, hash_cap, listcap, slots, waves))
 
 
-def peos_set_long_rows(enable=True):
-    """Allow or forbid the long-vector search variant; see include/peos.h."""
-    _check("peos_set_long_rows", lib().peos_set_long_rows(1 if enable else 0))
+def peos_set_long_rows(index, enable=True):
+    """Allow or forbid the long-vector search variant on this index."""
+    _check("peos_set_long_rows", lib().peos_set_long_rows(index.handle, 1 if enable else 0))
 
 
-def peos_set_class_tuning(cls, hash_cap=0, slots=0):
-    """Launch plan of ef class cls (lists <= 32 << cls) of a split batch."""
-    _check("peos_set_class_tuning", lib().peos_set_class_tuning(cls, hash_cap, slots))
+def peos_set_class_tuning(index, cls, hash_cap=0, slots=0, waves=0):
+    """Launch plan of ef class cls (lists <= 32 << cls) of a split batch on this index."""
+    _check("peos_set_class_tuning",
+           lib().peos_set_class_tuning(index.handle, cls, hash_cap, slots, waves))
 
 
 class PeosGraph:
@@ -404,10 +408,16 @@ class Server:
         ids = np.empty((nq, k), np.int64)
         dists = np.empty((nq, k), np.float32)
         t = ctypes.c_uint64()
-        _check("peos_serve_submit",
-               lib().peos_serve_submit(self.handle, q.ctypes.data, nq, int(k), int(ef),
-                                       ids.ctypes.data, dists.ctypes.data, ctypes.byref(t)))
-        self.live[t.value] = (q, ids, dists)
+        # the buffers are held before the call: the library writes to them
+        # until the request completes
+        self._held = (q, ids, dists)
+        try:
+            _check("peos_serve_submit",
+                   lib().peos_serve_submit(self.handle, q.ctypes.data, nq, int(k), int(ef),
+                                           ids.ctypes.data, dists.ctypes.data, ctypes.byref(t)))
+            self.live[t.value] = (q, ids, dists)
+        finally:
+            self._held = None
         return t.value
 
     def poll(self, wait=False):

@@ -3,8 +3,11 @@
 The search kernel keeps each query's visited set in an LDS hash.  A larger hash
 avoids moving busy queries' visited sets to HBM but costs LDS, hence resident
 waves per CU; the best capacity depends on the graph, ef and the stopping rule.
-`tune` times peos_search with a few capacities on the caller's batch and sets
-the fastest with peos_set_search_tuning.  Results never depend on the choice
+`tune` times peos_search on the caller's batch with 1, 2 or 4 waves per query
+(more waves gather each query's rows together; they pay when the batch is too
+small to fill the chip with one wave per query) and then with a few
+capacities, and sets the fastest with peos_set_search_tuning on that index
+(the plan belongs to the index and touches no other).  Results never depend on the choice
 (only speed does).  Choices are cached per device and problem shape in a JSON
 file (PEOS_TUNE_CACHE, default ~/.cache/peos_tune.json).
 """
@@ -19,6 +22,7 @@ from . import peos_search_ws_bytes, peos_set_search_tuning, search
 
 CACHE = os.environ.get("PEOS_TUNE_CACHE", os.path.expanduser("~/.cache/peos_tune.json"))
 HASH_CAPS = (0, 1024, 1536, 1792, 2048, 3072, 4096, 8192)  # 0 = the library's default plan
+WAVES = (0, 1, 2, 4)  # waves per query; 0 = the library's automatic choice
 KEEP_DEFAULT = 0.03  # another plan must be this much faster to replace the default
 
 
@@ -47,45 +51,75 @@ def _store(cache):
         pass
 
 
-def tune(index, queries, k, ef, pool=0, eps=0.1, mode=0, caps=HASH_CAPS, reps=3, use_cache=True,
-         log=None):
-    """Pick and set the visited-hash capacity for this operating point.
-    The library's default plan (cap 0) is kept unless another capacity is at
-    least KEEP_DEFAULT faster, so that the choice is stable from run to run.
-    Returns (hash_cap, {cap: ms})."""
+def _time(index, queries, k, ef, pool, eps, mode, ws, reps):
+    """Average ms of one search call, or None when the plan does not fit."""
+    try:
+        search(index, queries, k, ef, eps=eps, mode=mode, pool=pool, ws=ws)  # warm-up
+    except RuntimeError:
+        return None  # LDS plan too large for this capacity
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        search(index, queries, k, ef, eps=eps, mode=mode, pool=pool, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _pick(times):
+    """Fastest key; the default (first key) stays unless another is at least
+    KEEP_DEFAULT faster, so that the choice is stable from run to run."""
+    keys = list(times)
+    best = min(keys, key=times.get)
+    if times[best] > (1.0 - KEEP_DEFAULT) * times[keys[0]]:
+        best = keys[0]
+    return best
+
+
+def tune(index, queries, k, ef, pool=0, eps=0.1, mode=0, caps=HASH_CAPS, waves=WAVES, reps=3,
+         use_cache=True, log=None):
+    """Pick and set the launch plan of this operating point on this index:
+    first the waves per query (the library's automatic choice, or 1, 2, 4),
+    then the visited-hash capacity at that choice.  Returns (hash_cap,
+    {cap: ms}); the chosen waves per query are in index.tuned_waves."""
     nq = queries.shape[0]
     key = _key(index, nq, k, ef, pool, mode)
     cache = _load() if use_cache else {}
     if key in cache:
         cap = int(cache[key]["hash_cap"])
-        peos_set_search_tuning(cap, 0, 0)
+        nw = int(cache[key].get("waves", 0))
+        peos_set_search_tuning(index, cap, waves=nw)
+        index.tuned_waves = nw
         return cap, cache[key].get("ms", {})
     efmax = max(ef, k)
     ws = torch.empty(peos_search_ws_bytes(index, nq, efmax, pool), dtype=torch.uint8,
                      device=queries.device)
+    wtimes = {}
+    for nw in waves:
+        peos_set_search_tuning(index, 0, waves=nw)
+        t = _time(index, queries, k, ef, pool, eps, mode, ws, reps)
+        if t is not None:
+            wtimes[nw] = t
+            if log:
+                log(f"autotune ef={ef} pool={pool} mode={mode} waves={nw}: {t:.3f} ms")
+    nw = _pick(wtimes) if wtimes else 0
     times = {}
     for cap in caps:
-        peos_set_search_tuning(cap, 0, 0)
-        try:
-            search(index, queries, k, ef, eps=eps, mode=mode, pool=pool, ws=ws)  # warm-up
-        except RuntimeError:
-            continue  # LDS plan too large for this capacity
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            search(index, queries, k, ef, eps=eps, mode=mode, pool=pool, ws=ws)
-        e1.record()
-        torch.cuda.synchronize()
-        times[cap] = e0.elapsed_time(e1) / reps
+        peos_set_search_tuning(index, cap, waves=nw)
+        t = _time(index, queries, k, ef, pool, eps, mode, ws, reps)
+        if t is None:
+            continue
+        times[cap] = t
         if log:
-            log(f"autotune ef={ef} pool={pool} mode={mode} hash_cap={cap}: {times[cap]:.3f} ms")
-    best = min(times, key=times.get)
-    if 0 in times and times[best] > (1.0 - KEEP_DEFAULT) * times[0]:
-        best = 0
-    peos_set_search_tuning(best, 0, 0)
-    cache[key] = {"hash_cap": best, "ms": {str(c): round(t, 4) for c, t in times.items()}}
+            log(f"autotune ef={ef} pool={pool} mode={mode} waves={nw} hash_cap={cap}: {t:.3f} ms")
+    best = _pick(times)
+    peos_set_search_tuning(index, best, waves=nw)
+    index.tuned_waves = nw
+    cache[key] = {"hash_cap": best, "waves": nw,
+                  "ms": {str(c): round(t, 4) for c, t in times.items()},
+                  "waves_ms": {str(c): round(t, 4) for c, t in wtimes.items()}}
     if use_cache:
         _store(cache)
     return best, times
@@ -128,7 +162,7 @@ def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS,
                          device=dev)
         times = {}
         for cap in caps:
-            peos_set_class_tuning(c, cap, 0)
+            peos_set_class_tuning(index, c, cap)
             try:
                 search(index, qs, kt, et, eps=eps, mode=mode, pool=pool, ws=ws)
             except RuntimeError:
@@ -145,7 +179,7 @@ def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS,
         best = min(times, key=times.get)
         if 0 in times and times[best] > (1.0 - KEEP_DEFAULT) * times[0]:
             best = 0
-        peos_set_class_tuning(c, best, 0)
+        peos_set_class_tuning(index, c, best)
         chosen[c] = best
         if log:
             log(f"autotune class {c} ({len(sel)} queries, ef <= {efmax}): "

@@ -307,11 +307,47 @@ __device__ __forceinline__ void distances(const void* base, int d, const uint32_
 #define PEOS_SEARCH_WAVES_PER_EU 4
 #endif
 
+// Waves per query.  A workgroup of W = blockDim.x / 64 wavefronts searches
+// one query: wave 0 (the leader) runs the whole search; waves 1..W-1 (the
+// helpers) only gather survivor rows.  At each gather of ns >= 2 rows the
+// leader posts the count in LDS and the workgroup meets at a barrier; wave w
+// then computes the distances of rows [w c, (w+1) c), c = ceil(ns / W), and
+// the workgroup meets again.  Every row is still reduced by one lane group of
+// one wave in the fixed order, so results do not depend on W; what W buys is
+// W times the row loads in flight per query, for batches too small to fill
+// the chip with one wave per query.
+constexpr int kMaxWavesPerQuery = 4;
+enum CoopOp : uint32_t { kCoopExit = 0, kCoopTraversal = 1, kCoopFull = 2 };
+
+// the leader's gather: alone (W = 1 or a single row), or split over the
+// workgroup.  op selects the rows the helpers read (traversal copy or the
+// full-precision base).
+template <bool BF, bool WIDE, bool LONG>
+__device__ __forceinline__ void lead_distances(int nw, uint32_t* coop, const void* base, int d,
+                                               const uint32_t* Su, int ns, const float* qv,
+                                               int metric, float inv_qn, float* Sdist, uint32_t op)
+{
+    if (nw == 1 || ns < 2) {
+        distances<BF, WIDE, LONG>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+        return;
+    }
+    if (lane_id() == 0) {
+        coop[0] = op;
+        coop[1] = (uint32_t)ns;
+        coop[2] = __float_as_uint(inv_qn);
+    }
+    __syncthreads();  // rows posted
+    const int c = (ns + nw - 1) / nw;
+    distances<BF, WIDE, LONG>(base, d, Su, ns < c ? ns : c, qv, metric, inv_qn, Sdist);
+    __syncthreads();  // every wave's distances are in Sdist
+}
+
 // REGL: the candidate list is the result list alone (capacity = ef <= 64,
 // the HNSW stopping rule): entry i lives in lane i's registers (rd, ri), so
 // the pop is a ballot and the merge a register scatter through LDS staging.
 template <int MAXL, int FLAGS, bool REGL>
-__global__ __launch_bounds__(64, (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_PER_EU) void k_search(
+__global__ __launch_bounds__(kMaxWavesPerQuery * 64,
+                             (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_PER_EU) void k_search(
     SearchArgs a)
 {
     constexpr bool LONG = (FLAGS & kVariantLong) != 0;
@@ -321,13 +357,48 @@ __global__ __launch_bounds__(64, (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_
     const void* tbase = BF ? (const void*)a.base16 : (const void*)a.base;
     extern __shared__ __align__(16) unsigned char sm[];
     const int lane = lane_id();
+    const int nw = wave_uniform((int)(blockDim.x >> 6));   // waves per query
+    const int wv = wave_uniform((int)(threadIdx.x >> 6));  // this wave's rank
     // The arguments used once per query live in LDS and are read where they
     // are used, so they do not hold scalar registers across the expansion
     // loop (which would otherwise spill).
     __shared__ SearchArgs ca;
-    for (int t = lane; t < (int)(sizeof(SearchArgs) / 4); t += kWave)
-        reinterpret_cast<uint32_t*>(&ca)[t] = reinterpret_cast<const uint32_t*>(&a)[t];
+    __shared__ uint32_t coop[4];  // the leader's posted gather: op, rows, 1/|q|
+    if (wv == 0) {
+        for (int t = lane; t < (int)(sizeof(SearchArgs) / 4); t += kWave)
+            reinterpret_cast<uint32_t*>(&ca)[t] = reinterpret_cast<const uint32_t*>(&a)[t];
+    }
     wave_sync();
+    if (nw > 1) {
+        __syncthreads();
+        if (wv > 0) {
+            // helper: gather this wave's share of each posted set of rows
+            // until the leader posts the exit
+            uint32_t* Su_h = reinterpret_cast<uint32_t*>(sm);
+            float* Sd_h = reinterpret_cast<float*>(Su_h + kWave);
+            const float* qv_h = Sd_h + kWave;
+            for (;;) {
+                __syncthreads();  // rows posted
+                const uint32_t op = coop[0];
+                if (op == kCoopExit) break;
+                const int ns = (int)coop[1];
+                const float inv_qn = __uint_as_float(coop[2]);
+                const int c = (ns + nw - 1) / nw;
+                const int b = wv * c;
+                const int e = ns < b + c ? ns : b + c;
+                if (b < e) {
+                    if (op == kCoopTraversal)
+                        distances<BF, (MAXL >= 16) && BF, LONG>(tbase, a.d, Su_h + b, e - b, qv_h,
+                                                                 a.metric, inv_qn, Sd_h + b);
+                    else
+                        distances<false, false, LONG>(a.base, a.d, Su_h + b, e - b, qv_h, a.metric,
+                                                      inv_qn, Sd_h + b);
+                }
+                __syncthreads();  // distances in Sdist
+            }
+            return;
+        }
+    }
     const int d = a.d, R = a.R, L = a.L, m = a.m;
     const int hcap = a.hcap;
     const int slack = wave_uniform(ca.listslack);  // room past the capacity during a merge
@@ -359,7 +430,14 @@ __global__ __launch_bounds__(64, (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_
         uint32_t qtaken = 0;
         if (lane == 0) qtaken = atomicAdd(ca.counter, 1u);
         const uint32_t slot = wave_uniform((uint32_t)__shfl((int)qtaken, 0, kWave)) + qbegin;
-        if (slot >= qend) break;
+        if (slot >= qend) {
+            if (nw > 1) {
+                // release the helpers
+                if (lane == 0) coop[0] = kCoopExit;
+                __syncthreads();
+            }
+            break;
+        }
         const int64_t qi = ca.qperm ? (int64_t)wave_uniform(ca.qperm[slot]) : (int64_t)slot;
 
         // per-query k and ef are clamped to the launch bounds k_all, ef_all
@@ -639,7 +717,8 @@ __global__ __launch_bounds__(64, (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_
                 }
                 nvis += ns;
                 wave_sync();
-                distances<BF, (MAXL >= 16) && BF, LONG>(tbase, d, Su, ns, qv, a.metric, inv_qn, Sdist);
+                lead_distances<BF, (MAXL >= 16) && BF, LONG>(nw, coop, tbase, d, Su, ns, qv, a.metric,
+                                                             inv_qn, Sdist, kCoopTraversal);
                 st_ndist += ns;
                 wave_sync();
 
@@ -797,7 +876,8 @@ __global__ __launch_bounds__(64, (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_
                 const int cnt = nr - c0 < kWave ? nr - c0 : kWave;
                 if (lane < cnt) Su[lane] = Li[c0 + lane] & kIdMask;
                 wave_sync();
-                distances<false, false, LONG>(a.base, d, Su, cnt, qv, a.metric, inv_qn, Sdist);
+                lead_distances<false, false, LONG>(nw, coop, a.base, d, Su, cnt, qv, a.metric, inv_qn,
+                                                   Sdist, kCoopFull);
                 wave_sync();
                 if (lane < cnt) Ld[c0 + lane] = Sdist[lane];
                 wave_sync();
@@ -927,19 +1007,17 @@ __global__ void k_zero_u32(uint32_t* p, int n)
     if (i < n) p[i] = 0u;
 }
 
-// The quantile table of the compact form: entry b = T(b / bins) of step (6)
-// with w_reg = 1, w_res = 0, in double precision and rounded down to single
-// (the smallest T of its bin, since T grows with A).
-__global__ __launch_bounds__(256) void k_compact_lut(float* lut, double eta, double c_eps, int L)
+// The quantile table of the compact form, computed on the host and handed
+// to the device as a kernel argument (a kernel node, so a captured search
+// carries it), written to the workspace where the search reads it.
+struct CompactLut {
+    float v[kCompactLutBins];
+};
+
+__global__ __launch_bounds__(256) void k_store_lut(CompactLut t, float* lut)
 {
-#pragma clang fp contract(off)
     const int b = (int)threadIdx.x;
-    if (b >= kCompactLutBins) return;
-    const double A = (double)b / kCompactLutBins;
-    const double t = A * eta + c_eps * sqrt(1.0 - (double)L * A * A / (double)(L + 1));
-    float f = (float)t;
-    if ((double)f > t) f = nextafterf(f, -INFINITY);
-    lut[b] = f;
+    if (b < kCompactLutBins) lut[b] = t.v[b];
 }
 
 }  // namespace peos

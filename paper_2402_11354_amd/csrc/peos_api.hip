@@ -22,6 +22,13 @@ struct peos_graph {
     int device;
 };
 
+// launch-plan overrides of one index (0 = automatic); they change speed only
+struct PeosTuning {
+    int hash_cap = 0, listcap = 0, slots = 0, waves = 0;
+    bool no_long = false;  // never choose the long-vector variant
+};
+constexpr int kNumClassTunings = 8;  // ef classes of a split batch
+
 struct peos_index {
     const int32_t* perm;     // dimension permutation of the test, or null
     const float* sdirs;      // 64 x d SimHash vectors (PEOS_FLAG_SIMHASH), or null
@@ -36,6 +43,12 @@ struct peos_index {
     int32_t d, R, L, m, metric, flags, entry;
     int64_t node_stride, codes_off, scal_off, bf16_off;
     int device;
+    int num_cu;          // compute units of the device
+    int64_t lds_per_cu;  // LDS bytes per compute unit
+    // launch plan overrides: for every call, and per ef class of a split batch
+    std::mutex* tune_mu = nullptr;
+    PeosTuning tune;
+    PeosTuning class_tune[kNumClassTunings];
     // upper layers for the entry descent (peos_set_upper_layers), or null
     const int32_t* up_node = nullptr;
     const int32_t* up_adj = nullptr;
@@ -64,9 +77,9 @@ int fail(int code, const char* fmt, ...)
 
 constexpr int kMaxSlots = 4096;      // resident search waves at most
 constexpr int kMaxEf = 4096;
-constexpr int64_t kLdsPerCu = 160 * 1024;
-constexpr int64_t kStaticLds = 256;  // the search kernel's copy of its arguments
-constexpr int kNumCu = 256;
+// the search kernel's static LDS: its copy of the arguments and the
+// leader's posted gather (waves per query)
+constexpr int64_t kStaticLds = 272;
 
 int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
 
@@ -117,19 +130,32 @@ int check_shape(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m)
     return PEOS_OK;
 }
 
-int check_device(int* dev)
+// the current device, checked to be a gfx950 once, with its compute-unit
+// count and LDS per compute unit (the launch plans are sized from these)
+struct DeviceInfo {
+    int checked = 0;  // 1 gfx950, -1 other
+    int num_cu = 0;
+    int64_t lds_per_cu = 0;
+};
+
+int check_device(int* dev, DeviceInfo* info = nullptr)
 {
     HIP_TRY(hipGetDevice(dev));
     static std::mutex mu;
-    static int checked[64] = {0};
+    static DeviceInfo devs[64];
     std::lock_guard<std::mutex> g(mu);
     if (*dev < 0 || *dev >= 64) return fail(PEOS_EDEVICE, "device index %d", *dev);
-    if (checked[*dev] == 0) {
+    DeviceInfo& di = devs[*dev];
+    if (di.checked == 0) {
         hipDeviceProp_t p;
         HIP_TRY(hipGetDeviceProperties(&p, *dev));
-        checked[*dev] = (std::strncmp(p.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+        di.checked = (std::strncmp(p.gcnArchName, "gfx950", 6) == 0) ? 1 : -1;
+        di.num_cu = p.multiProcessorCount;
+        di.lds_per_cu = (int64_t)p.maxSharedMemoryPerMultiProcessor;
+        if (di.num_cu < 1 || di.lds_per_cu < 64 * 1024) di.checked = -1;
     }
-    if (checked[*dev] < 0) return fail(PEOS_EDEVICE, "device %d is not gfx950", *dev);
+    if (di.checked < 0) return fail(PEOS_EDEVICE, "device %d is not a gfx950 (CUs %d, LDS/CU %lld)", *dev, di.num_cu, (long long)di.lds_per_cu);
+    if (info) *info = di;
     return PEOS_OK;
 }
 
@@ -165,13 +191,37 @@ double norm_ppf(double p)
     return x - u / (1 + x * u / 2);
 }
 
-struct Tuning {
-    int hash_cap = 0, listcap = 0, slots = 0;
-    bool no_long = false;  // never choose the long-vector variant
-};
-std::mutex g_tune_mu;
-Tuning g_tune;
-Tuning g_class_tune[peos::kMaxClasses];  // per ef class of a batch (hash_cap, slots)
+static_assert(kNumClassTunings == peos::kMaxClasses, "one tuning per ef class");
+
+// The quantile table of the compact form (Sec. 4.3 reads the quantile from a
+// table): entry b = T(b / bins) of step (6) with w_reg = 1, w_res = 0,
+// evaluated in double precision on the host and rounded down to single (the
+// smallest T of its bin, since T grows with A, so the table never raises the
+// threshold).
+void compact_lut(int L, double eta, double c_eps, float* lut)
+{
+    for (int b = 0; b < peos::kCompactLutBins; ++b) {
+        const double A = (double)b / peos::kCompactLutBins;
+        const double t = A * eta + c_eps * std::sqrt(1.0 - (double)L * A * A / (double)(L + 1));
+        float f = (float)t;
+        if ((double)f > t) f = std::nextafter(f, -INFINITY);
+        lut[b] = f;
+    }
+}
+
+// the index's overrides for a launch of ef class cls (-1: no class split)
+PeosTuning tuning_of(const peos_index* ix, int cls)
+{
+    std::lock_guard<std::mutex> g(*ix->tune_mu);
+    PeosTuning t = ix->tune;
+    if (cls >= 0 && cls < kNumClassTunings) {
+        const PeosTuning& c = ix->class_tune[cls];
+        if (c.hash_cap > 0) t.hash_cap = c.hash_cap;
+        if (c.slots > 0) t.slots = c.slots;
+        if (c.waves > 0) t.waves = c.waves;
+    }
+    return t;
+}
 
 // The search kernels may use up to 64 KB of LDS; raise the limit once per
 // device (not a stream operation, so it also holds for captured launches).
@@ -199,6 +249,8 @@ int ensure_kernel_attrs(int dev)
 #undef PEOS_FNS
         for (const void* f : fns)
             HIP_TRY(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
+        HIP_TRY(hipFuncSetAttribute((const void*)peos::k_query_table,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024));
         done[dev] = true;
     }
     return PEOS_OK;
@@ -212,6 +264,7 @@ struct SearchPlan {
     bool list_in_lds;  // a list capacity was forced: keep the list in LDS
     bool regl;         // the list lives in registers (no LDS list)
     bool long_rows;    // the low-occupancy variant for long vectors
+    int waves;         // wavefronts per query (workgroup size / 64)
     int listcap, listslack, hcap, visit_limit, slots;
     int64_t lds;
     int64_t spill_words;
@@ -222,15 +275,9 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
                        int cls = -1)
 {
     SearchPlan p;
-    Tuning t;
-    {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        t = g_tune;
-        if (cls >= 0 && cls < peos::kMaxClasses) {
-            if (g_class_tune[cls].hash_cap > 0) t.hash_cap = g_class_tune[cls].hash_cap;
-            if (g_class_tune[cls].slots > 0) t.slots = g_class_tune[cls].slots;
-        }
-    }
+    const PeosTuning t = tuning_of(ix, cls);
+    const int64_t lds_cu = ix->lds_per_cu;
+    const int64_t ncu = ix->num_cu;
     const int lmin = pool < 0 ? -pool * efmax : (pool > efmax ? pool : efmax);
     // unbounded queue: room for 16 ef entries (the list of the printed Alg. 1
     // stays well below that in practice), at most 2048
@@ -260,7 +307,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     // more, 1024 to 8192.  The unbounded queue (pool = 0) visits several
     // times more nodes per list entry: 32 slots per entry, from 2048, and
     // for lists up to 64 the 16-wave fit.
-    const int64_t fit = (kLdsPerCu / 16 - kStaticLds - fixed) / 4;
+    const int64_t fit = (lds_cu / 16 - kStaticLds - fixed) / 4;
     int hc;
     if (pool != 0) {
         hc = 20 * efmax > fit ? 20 * efmax : (int)fit;
@@ -281,16 +328,36 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     // room (slack) is needed only when entries past ef are kept (pool above
     // ef, or the unbounded queue); when the capacity is ef they are dropped.
     p.lds = fixed + 4LL * hc;
-    int64_t per_cu = kLdsPerCu / (p.lds + kStaticLds);
+    int64_t per_cu = lds_cu / (p.lds + kStaticLds);
     if (per_cu < 1) per_cu = 1;
     if (per_cu > 16) per_cu = 16;
     // long vectors (d > 512, L > 8, list in LDS): when the LDS or the batch
     // allows at most 8 waves per CU anyway, the variant with the registers
     // of two waves per SIMD keeps twice the rows in flight
     p.long_rows = ix->d > 512 && ix->L > 8 && !(ix->flags & PEOS_FLAG_COMPACT) && !p.regl &&
-                  (per_cu <= 8 || nq <= 8 * kNumCu) && !t.no_long;
+                  (per_cu <= 8 || nq <= 8 * ncu) && !t.no_long;
     if (p.long_rows && per_cu > 8) per_cu = 8;
-    int64_t slots = per_cu * kNumCu;
+    // waves per query: the registers allow 16 waves per CU (8 with the
+    // long-vector variant); when the batch leaves room, give each query 2 or
+    // 4 waves (its rows gathered by all of them) as long as every query of
+    // the batch is still resident at once
+    const int64_t wpc = p.long_rows ? 8 : 16;
+    int waves = 1;
+    if (t.waves > 0) {
+        waves = t.waves;
+    } else {
+        for (int cand = peos::kMaxWavesPerQuery; cand > 1; cand >>= 1) {
+            const int64_t q_cu = per_cu < wpc / cand ? per_cu : wpc / cand;
+            if (nq <= q_cu * ncu) {
+                waves = cand;
+                break;
+            }
+        }
+    }
+    p.waves = waves;
+    if (per_cu > wpc / waves) per_cu = wpc / waves;
+    if (per_cu < 1) per_cu = 1;
+    int64_t slots = per_cu * ncu;
     if (slots > kMaxSlots) slots = kMaxSlots;
     if (t.slots > 0) slots = t.slots;
     if (slots > nq) slots = nq;
@@ -299,27 +366,32 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     return p;
 }
 
-// workspace: work counters (one per ef class) and class ranges | per-slot
-// visited bitmaps | tables | norms | query order of the class split
+// workspace: work counters (one per ef class) and class ranges | quantile
+// table of the compact form | tables | norms | query order of the class split
+// | entries of the descent | one visited bitmap per resident workgroup (last,
+// so that the offsets before it do not depend on the number of workgroups)
 struct WsLayout {
-    int64_t counter_off, ranges_off, lut_off, spill_off, tables_off, qnorm_off, qperm_off,
-        entries_off, total;
+    int64_t counter_off, ranges_off, lut_off, tables_off, qnorm_off, qperm_off, entries_off,
+        spill_off, slots, total;
 };
 
-WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words)
+// slots: visited bitmaps to hold (resident workgroups of the launch); 0 =
+// as many as a launch of nq queries may have
+WsLayout ws_layout(const peos_index* ix, int64_t nq, int64_t spill_words, int64_t slots = 0)
 {
     WsLayout w;
-    int64_t slots = nq < kMaxSlots ? nq : kMaxSlots;
+    if (slots <= 0) slots = nq < kMaxSlots ? nq : kMaxSlots;
     if (slots < 1) slots = 1;
     w.counter_off = 0;
     w.ranges_off = 64;
-    w.lut_off = 256;  // quantile table of the compact form
-    w.spill_off = w.lut_off + 4 * peos::kCompactLutBins;
-    w.tables_off = round_up(w.spill_off + slots * spill_words * 4, 256);
+    w.lut_off = 256;
+    w.tables_off = round_up(w.lut_off + 4 * peos::kCompactLutBins, 256);
     w.qnorm_off = round_up(w.tables_off + nq * (int64_t)(ix->L + 1) * ix->m * 4, 256);
     w.qperm_off = round_up(w.qnorm_off + nq * 4, 256);
-    w.entries_off = round_up(w.qperm_off + nq * 4, 256);  // entries of the descent
-    w.total = round_up(w.entries_off + nq * 4, 256);
+    w.entries_off = round_up(w.qperm_off + nq * 4, 256);
+    w.spill_off = round_up(w.entries_off + nq * 4, 256);
+    w.slots = slots;
+    w.total = round_up(w.spill_off + slots * spill_words * 4, 256);
     return w;
 }
 
@@ -371,36 +443,54 @@ extern "C" {
 
 const char* peos_last_error(void) { return g_err; }
 
-int peos_set_long_rows(int32_t enable)
+int peos_set_long_rows(peos_index* ix, int32_t enable)
 {
+    if (!ix) return fail(PEOS_EINVAL, "null index");
     if (enable != 0 && enable != 1) return fail(PEOS_EINVAL, "enable=%d", enable);
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune.no_long = enable == 0;
+    std::lock_guard<std::mutex> g(*ix->tune_mu);
+    ix->tune.no_long = enable == 0;
     return PEOS_OK;
 }
 
-int peos_set_search_tuning(int32_t hash_cap, int32_t listcap, int32_t slots)
+static int check_waves(int32_t waves)
 {
+    if (waves != 0 && waves != 1 && waves != 2 && waves != 4)
+        return fail(PEOS_EINVAL, "waves=%d not in {0, 1, 2, 4}", waves);
+    return PEOS_OK;
+}
+
+int peos_set_search_tuning(peos_index* ix, int32_t hash_cap, int32_t listcap, int32_t slots,
+                           int32_t waves)
+{
+    if (!ix) return fail(PEOS_EINVAL, "null index");
     if (hash_cap != 0 && (hash_cap < 64 || hash_cap > 16384))
         return fail(PEOS_EINVAL, "hash_cap=%d not in [64, 16384]", hash_cap);
     if (listcap < 0 || listcap > 2 * kMaxEf) return fail(PEOS_EINVAL, "listcap=%d", listcap);
     if (slots < 0 || slots > kMaxSlots) return fail(PEOS_EINVAL, "slots=%d", slots);
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune.hash_cap = hash_cap;
-    g_tune.listcap = listcap;
-    g_tune.slots = slots;
+    int rc = check_waves(waves);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(*ix->tune_mu);
+    ix->tune.hash_cap = hash_cap;
+    ix->tune.listcap = listcap;
+    ix->tune.slots = slots;
+    ix->tune.waves = waves;
     return PEOS_OK;
 }
 
-int peos_set_class_tuning(int32_t cls, int32_t hash_cap, int32_t slots)
+int peos_set_class_tuning(peos_index* ix, int32_t cls, int32_t hash_cap, int32_t slots,
+                          int32_t waves)
 {
+    if (!ix) return fail(PEOS_EINVAL, "null index");
     if (cls < 0 || cls >= peos::kMaxClasses) return fail(PEOS_EINVAL, "class %d not in [0, %d)", cls, peos::kMaxClasses);
     if (hash_cap != 0 && (hash_cap < 64 || hash_cap > 16384))
         return fail(PEOS_EINVAL, "hash_cap=%d not in [64, 16384]", hash_cap);
     if (slots < 0 || slots > kMaxSlots) return fail(PEOS_EINVAL, "slots=%d", slots);
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    g_class_tune[cls].hash_cap = hash_cap;
-    g_class_tune[cls].slots = slots;
+    int rc = check_waves(waves);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(*ix->tune_mu);
+    ix->class_tune[cls].hash_cap = hash_cap;
+    ix->class_tune[cls].slots = slots;
+    ix->class_tune[cls].waves = waves;
     return PEOS_OK;
 }
 
@@ -472,7 +562,8 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     if (index_bytes < need) return fail(PEOS_ENOSPACE, "index_bytes %zu < %zu", index_bytes, need);
     if (ws_bytes < need_ws) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %zu", ws_bytes, need_ws);
     int dev;
-    rc = check_device(&dev);
+    DeviceInfo di;
+    rc = check_device(&dev, &di);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     Layout l = layout_of(R, L, flags);
@@ -514,6 +605,11 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     if (herr) return fail(PEOS_EGRAPH, "graph has an id out of range, a self loop or a repeated neighbour");
     peos_index* ix = new (std::nothrow) peos_index;
     if (!ix) return fail(PEOS_EINVAL, "out of host memory");
+    ix->tune_mu = new (std::nothrow) std::mutex;
+    if (!ix->tune_mu) {
+        delete ix;
+        return fail(PEOS_EINVAL, "out of host memory");
+    }
     ix->perm = perm;
     ix->sdirs = (flags & PEOS_FLAG_SIMHASH) ? sdirs : nullptr;
     ix->sig_off = l.sig_off;
@@ -536,6 +632,8 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     ix->codes_off = l.codes_off;
     ix->scal_off = l.scal_off;
     ix->device = dev;
+    ix->num_cu = di.num_cu;
+    ix->lds_per_cu = di.lds_per_cu;
     *out = ix;
     return PEOS_OK;
 }
@@ -562,7 +660,12 @@ int peos_index_layout(const peos_index* ix, peos_layout* out)
     return PEOS_OK;
 }
 
-void peos_free(peos_index* ix) { delete ix; }
+void peos_free(peos_index* ix)
+{
+    if (!ix) return;
+    delete ix->tune_mu;
+    delete ix;
+}
 
 int peos_set_upper_layers(peos_index* ix, const peos_upper_layers* up)
 {
@@ -629,7 +732,13 @@ int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, fl
     a.half_out = (ix->flags & PEOS_FLAG_FP16) ? 1 : 0;
     a.perm = ix->perm;
     const int64_t blocks = (nq + 15) / 16;
-    hipLaunchKernelGGL(peos::k_query_table, dim3((unsigned)blocks), dim3(64), 0, (hipStream_t)stream, a);
+    const size_t tile = sizeof(float) * 16 * (size_t)(ix->d + 4);
+    a.staged = tile <= 64 * 1024 ? 1 : 0;
+    const size_t lds = a.staged ? tile : 0;
+    int rc = ensure_kernel_attrs(ix->device);
+    if (rc) return rc;
+    hipLaunchKernelGGL(peos::k_query_table, dim3((unsigned)blocks), dim3(64 * peos::kTableWaves),
+                       lds, (hipStream_t)stream, a);
     HIP_TRY(hipGetLastError());
     return PEOS_OK;
 }
@@ -665,21 +774,22 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     a.hcap = plan.hcap;
     a.visit_limit = plan.visit_limit;
     const dim3 grid((unsigned)plan.slots);
-    static_assert(sizeof(peos::SearchArgs) <= kStaticLds, "argument copy must fit its LDS share");
+    const dim3 block((unsigned)(64 * plan.waves));
+    static_assert(sizeof(peos::SearchArgs) + 16 <= kStaticLds, "argument copy must fit its LDS share");
     const size_t lds = (size_t)plan.lds;
 #define PEOS_LAUNCH2(ML, RG)                                                                      \
     switch (ix->flags & kFlagsAll) {                                                              \
-    case 0: hipLaunchKernelGGL((peos::k_search<ML, 0, RG>), grid, dim3(64), lds, s, a); break;     \
-    case 1: hipLaunchKernelGGL((peos::k_search<ML, 1, RG>), grid, dim3(64), lds, s, a); break;     \
-    case 2: hipLaunchKernelGGL((peos::k_search<ML, 2, RG>), grid, dim3(64), lds, s, a); break;     \
-    default: hipLaunchKernelGGL((peos::k_search<ML, 3, RG>), grid, dim3(64), lds, s, a); break;    \
+    case 0: hipLaunchKernelGGL((peos::k_search<ML, 0, RG>), grid, block, lds, s, a); break;     \
+    case 1: hipLaunchKernelGGL((peos::k_search<ML, 1, RG>), grid, block, lds, s, a); break;     \
+    case 2: hipLaunchKernelGGL((peos::k_search<ML, 2, RG>), grid, block, lds, s, a); break;     \
+    default: hipLaunchKernelGGL((peos::k_search<ML, 3, RG>), grid, block, lds, s, a); break;    \
     }
 #define PEOS_LAUNCH_LONG(ML)                                                                      \
     switch (ix->flags & kFlagsAll) {                                                              \
-    case 0: hipLaunchKernelGGL((peos::k_search<ML, 16, false>), grid, dim3(64), lds, s, a); break; \
-    case 1: hipLaunchKernelGGL((peos::k_search<ML, 17, false>), grid, dim3(64), lds, s, a); break; \
-    case 2: hipLaunchKernelGGL((peos::k_search<ML, 18, false>), grid, dim3(64), lds, s, a); break; \
-    default: hipLaunchKernelGGL((peos::k_search<ML, 19, false>), grid, dim3(64), lds, s, a); break;\
+    case 0: hipLaunchKernelGGL((peos::k_search<ML, 16, false>), grid, block, lds, s, a); break; \
+    case 1: hipLaunchKernelGGL((peos::k_search<ML, 17, false>), grid, block, lds, s, a); break; \
+    case 2: hipLaunchKernelGGL((peos::k_search<ML, 18, false>), grid, block, lds, s, a); break; \
+    default: hipLaunchKernelGGL((peos::k_search<ML, 19, false>), grid, block, lds, s, a); break;\
     }
 #define PEOS_LAUNCH(ML)                                                                           \
     if (regl) { PEOS_LAUNCH2(ML, true) } else { PEOS_LAUNCH2(ML, false) }
@@ -687,10 +797,10 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     // compact records (L <= 4): their own variants of the L <= 8 kernel
     if (ix->flags & PEOS_FLAG_COMPACT) {
         const bool bf = (ix->flags & PEOS_FLAG_BF16_BASE) != 0;
-        if (regl && bf) hipLaunchKernelGGL((peos::k_search<8, 9, true>), grid, dim3(64), lds, s, a);
-        else if (regl) hipLaunchKernelGGL((peos::k_search<8, 8, true>), grid, dim3(64), lds, s, a);
-        else if (bf) hipLaunchKernelGGL((peos::k_search<8, 9, false>), grid, dim3(64), lds, s, a);
-        else hipLaunchKernelGGL((peos::k_search<8, 8, false>), grid, dim3(64), lds, s, a);
+        if (regl && bf) hipLaunchKernelGGL((peos::k_search<8, 9, true>), grid, block, lds, s, a);
+        else if (regl) hipLaunchKernelGGL((peos::k_search<8, 8, true>), grid, block, lds, s, a);
+        else if (bf) hipLaunchKernelGGL((peos::k_search<8, 9, false>), grid, block, lds, s, a);
+        else hipLaunchKernelGGL((peos::k_search<8, 8, false>), grid, block, lds, s, a);
     } else if (ix->L <= 8) { PEOS_LAUNCH(8) }
     else if (plan.long_rows && ix->L <= 16) { PEOS_LAUNCH_LONG(16) }
     else if (plan.long_rows) { PEOS_LAUNCH_LONG(32) }
@@ -707,10 +817,12 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
                        const float* qnorms, int64_t nq, const int32_t* k, const int32_t* ef,
                        int32_t k_all, int32_t ef_all, int32_t kstride, int32_t pool, float eps,
                        int32_t mode, int64_t* ids, float* dists, int32_t* stats, void* ws,
-                       size_t ws_bytes, hipStream_t s, int slots_cap = 0)
+                       size_t ws_bytes, hipStream_t s, int slots_cap = 0, int64_t ws_slots = 0)
 {
     const int efmax = ef_all > k_all ? ef_all : k_all;
-    WsLayout w = ws_layout(ix, nq, spill_words_of(ix));
+    WsLayout w = ws_layout(ix, nq, spill_words_of(ix), ws_slots);
+    // a launch never has more resident workgroups than visited bitmaps
+    if (slots_cap <= 0 || slots_cap > w.slots) slots_cap = (int)w.slots;
     if ((int64_t)ws_bytes < w.total) return fail(PEOS_ENOSPACE, "ws_bytes %zu < %lld", ws_bytes, (long long)w.total);
     int rc = ensure_kernel_attrs(ix->device);
     if (rc) return rc;
@@ -789,8 +901,10 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     }
     if ((ix->flags & PEOS_FLAG_COMPACT) && mode == PEOS_MODE_PEOS) {
         float* lut = (float*)((char*)ws + w.lut_off);
-        hipLaunchKernelGGL(peos::k_compact_lut, dim3(1), dim3(peos::kCompactLutBins), 0, s, lut,
-                           eta, norm_ppf((double)eps), (int)ix->L);
+        peos::CompactLut t;
+        compact_lut(ix->L, eta, norm_ppf((double)eps), t.v);
+        hipLaunchKernelGGL(peos::k_store_lut, dim3(1), dim3(peos::kCompactLutBins), 0, s, t, lut);
+        HIP_TRY(hipGetLastError());
         a.aux = lut;
     }
     if (nclass == 1) return launch_search(ix, a, nq, efmax, pool, per_query, -1, counters, slots_cap, s);

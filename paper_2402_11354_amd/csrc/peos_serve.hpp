@@ -117,6 +117,33 @@ int serve_reap(peos_server* sv, bool* any)
     return PEOS_OK;
 }
 
+// enqueue one packed batch on its slot's stream: copy in, tables, search,
+// copy out, completion event
+int serve_issue(peos_server* sv, ServeSlot& sl, int64_t nqb, int kmax, int efmax, int waves)
+{
+    const peos_index* ix = sv->ix;
+    const peos_serve_config& c = sv->cfg;
+    ServeSlot* s = &sl;
+    const int d = ix->d;
+    hipStream_t st = s->stream;
+    HIP_TRY(hipMemcpyAsync(s->d_q, s->h_q, sizeof(float) * nqb * d, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->d_k, s->h_k, sizeof(int32_t) * nqb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(s->d_ef, s->h_ef, sizeof(int32_t) * nqb, hipMemcpyHostToDevice, st));
+    WsLayout w = ws_layout(ix, nqb, spill_words_of(ix));
+    float* tables = (float*)((char*)s->d_ws + w.tables_off);
+    float* qnorms = (float*)((char*)s->d_ws + w.qnorm_off);
+    int rc = peos_query_tables(ix, s->d_q, nqb, tables, qnorms, st);
+    if (rc) return rc;
+    rc = search_impl(ix, s->d_q, tables, qnorms, nqb, s->d_k, s->d_ef, kmax, efmax, c.max_k,
+                     c.pool, c.eps, c.mode, s->d_ids, s->d_dists, nullptr, s->d_ws, s->ws_bytes,
+                     st, waves);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(s->h_ids, s->d_ids, sizeof(int64_t) * nqb * c.max_k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(s->h_dists, s->d_dists, sizeof(float) * nqb * c.max_k, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipEventRecord(s->done, st));
+    return PEOS_OK;
+}
+
 int serve_dispatch(peos_server* sv)
 {
     const peos_index* ix = sv->ix;
@@ -161,22 +188,17 @@ int serve_dispatch(peos_server* sv)
             s->reqs.push_back(r);
         }
         sv->pending_q -= nqb;
-        hipStream_t st = s->stream;
-        HIP_TRY(hipMemcpyAsync(s->d_q, s->h_q, sizeof(float) * nqb * d, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(s->d_k, s->h_k, sizeof(int32_t) * nqb, hipMemcpyHostToDevice, st));
-        HIP_TRY(hipMemcpyAsync(s->d_ef, s->h_ef, sizeof(int32_t) * nqb, hipMemcpyHostToDevice, st));
-        WsLayout w = ws_layout(ix, nqb, spill_words_of(ix));
-        float* tables = (float*)((char*)s->d_ws + w.tables_off);
-        float* qnorms = (float*)((char*)s->d_ws + w.qnorm_off);
-        int rc = peos_query_tables(ix, s->d_q, nqb, tables, qnorms, st);
-        if (rc) return rc;
-        rc = search_impl(ix, s->d_q, tables, qnorms, nqb, s->d_k, s->d_ef, kmax, efmax, c.max_k,
-                         c.pool, c.eps, c.mode, s->d_ids, s->d_dists, nullptr, s->d_ws, s->ws_bytes,
-                         st, (int)waves);
-        if (rc) return rc;
-        HIP_TRY(hipMemcpyAsync(s->h_ids, s->d_ids, sizeof(int64_t) * nqb * c.max_k, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(s->h_dists, s->d_dists, sizeof(float) * nqb * c.max_k, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipEventRecord(s->done, st));
+        int rc = serve_issue(sv, *s, nqb, kmax, efmax, (int)waves);
+        if (rc) {
+            // nothing of this batch will complete: its requests go back to
+            // the head of the queue, in order, and the slot stays free once
+            // what was already enqueued on its stream has drained
+            (void)hipStreamSynchronize(s->stream);
+            for (size_t i = s->reqs.size(); i-- > 0;) sv->pending.push_front(s->reqs[i]);
+            sv->pending_q += nqb;
+            s->reqs.clear();
+            return rc;
+        }
         s->busy = true;
         s->lds = lds;
         sv->lds_inflight += lds;
@@ -211,6 +233,16 @@ int peos_serve_open(const peos_index* ix, const peos_serve_config* cfg, peos_ser
     int rc = check_device(&dev);
     if (rc) return rc;
     if (dev != ix->device) return fail(PEOS_EINVAL, "current device %d is not the index's %d", dev, ix->device);
+    // the largest request must have a launch plan that fits a workgroup's
+    // LDS (every ef class of a batch plans within it), else every batch
+    // holding one would fail at dispatch
+    {
+        const int listmax = c.max_ef > c.max_k ? c.max_ef : c.max_k;
+        SearchPlan p = plan_search(ix, c.max_batch, listmax, c.pool, true, num_classes(listmax) - 1);
+        if (p.lds + kStaticLds > 64 * 1024)
+            return fail(PEOS_EINVAL, "max_ef=%d with pool=%d needs %lld bytes of LDS per wave (64 KB at most)",
+                        c.max_ef, c.pool, (long long)p.lds);
+    }
     // memory of one slot
     const int64_t B = c.max_batch, K = c.max_k, d = ix->d;
     WsLayout w = ws_layout(ix, B, spill_words_of(ix));
@@ -230,7 +262,7 @@ int peos_serve_open(const peos_index* ix, const peos_serve_config* cfg, peos_ser
     if (!sv) return fail(PEOS_EINVAL, "out of host memory");
     sv->ix = ix;
     sv->cfg = c;
-    sv->lds_budget = c.lds_budget > 0 ? (int64_t)c.lds_budget : kLdsPerCu * kNumCu;
+    sv->lds_budget = c.lds_budget > 0 ? (int64_t)c.lds_budget : ix->lds_per_cu * ix->num_cu;
     sv->lds_inflight = 0;
     sv->launch_waves = c.launch_waves > 0 ? c.launch_waves : kMaxSlots;
     sv->pending_q = 0;
@@ -286,8 +318,19 @@ int peos_serve_submit(peos_server* sv, const float* queries, int32_t nq, int32_t
     r.dists = dists;
     sv->pending.push_back(r);
     sv->pending_q += nq;
+    const int rc = serve_dispatch(sv);
+    if (rc) {
+        // a failed dispatch put its batch back at the head of the queue; this
+        // request is then still the last one queued: take it out, so that an
+        // error means nothing of this call was queued
+        if (!sv->pending.empty() && sv->pending.back().ticket == r.ticket) {
+            sv->pending.pop_back();
+            sv->pending_q -= nq;
+        }
+        return rc;
+    }
     *ticket = r.ticket;
-    return serve_dispatch(sv);
+    return PEOS_OK;
 }
 
 int peos_serve_poll(peos_server* sv, int32_t wait, uint64_t* done, int32_t max_done, int32_t* n_done)

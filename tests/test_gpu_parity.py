@@ -4,7 +4,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from parity import compare
+from parity import check_both, compare
 
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2402_11354_amd")
@@ -37,6 +37,15 @@ class Case:
         return O.search(self.x, self.g, self.entry, q, k, ef, self.w.L, self.w.m, self.A, self.B,
                         self.w.metric, eps, mode=mode, pool=pool, precision=32)
 
+    def check(self, gpu, k, ef, eps, mode, pool=0, queries=None, min_checked=0.8, label="",
+              **kw):
+        """Both parity rules (FP64 oracle, then the exact single-precision
+        replica) on this case's inputs."""
+        q = self.q if queries is None else queries
+        return check_both(gpu, self.x, self.g, self.entry, q, k, ef, self.w.L, self.w.m, self.A,
+                          self.B, self.w.metric, eps, mode=mode, pool=pool,
+                          min_checked=min_checked, label=label or self.w.name, **kw)
+
 
 @pytest.fixture(scope="module")
 def tiny():
@@ -59,6 +68,18 @@ def angular():
 IPW = W.Workload("ip_gmm_3k_d64", 3000, 100, 64, 16, 32, 4, 16, W.IP, "gmm10", 0.1, 10, 32, 1006)
 
 
+# the benchmark's integer-valued recipe at 20,000 vectors: every distance and
+# A_r numerator is exact in single precision, so the FP64 rule checks nearly
+# every query
+SIFT_SMALL = W.SIFT_LIKE.with_sizes(n=20000, nq=100)
+
+
+@pytest.fixture(scope="module")
+def sift():
+    print("[gpu] building small SIFT-like workload", flush=True)
+    return Case(SIFT_SMALL)
+
+
 @pytest.fixture(scope="module")
 def ip():
     print("[gpu] building inner-product workload", flush=True)
@@ -79,7 +100,7 @@ def read_records(case):
     return codes[:, :, :L + 1], sc.reshape(n, R, 4)
 
 
-@pytest.mark.parametrize("which", ["tiny", "angular", "ip"])
+@pytest.mark.parametrize("which", ["tiny", "angular", "ip", "sift"])
 def test_edge_records_match_oracle(which, request):
     case = request.getfixturevalue(which)
     w = case.w
@@ -160,12 +181,7 @@ def run(case, k, ef, eps, mode, pool=0, queries=None, kstride=None):
     return ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
 
 
-def recall(case, ids, k):
-    gt, _ = O.brute_force(case.x, case.q, k, case.w.metric)
-    return np.mean([len(set(ids[i][:k]) & set(gt[i])) / k for i in range(len(ids))])
-
-
-@pytest.mark.parametrize("which", ["tiny", "angular", "ip"])
+@pytest.mark.parametrize("which", ["tiny", "angular", "ip", "sift"])
 @pytest.mark.parametrize("mode", [P.PEOS_MODE_PEOS, P.PEOS_MODE_EXHAUSTIVE])
 @pytest.mark.parametrize("pool_mul", [0, 1, 2])
 def test_search_matches_oracle(which, mode, pool_mul, request):
@@ -173,22 +189,18 @@ def test_search_matches_oracle(which, mode, pool_mul, request):
     w = case.w
     pool = pool_mul * w.ef
     ids, d, st = run(case, w.k, w.ef, w.eps, mode, pool)
-    ref = case.oracle(w.k, w.ef, w.eps, mode, pool)
-    res = compare(ids, d, st, ref, w.k)
-    print(f"[gpu] {which} mode={mode} pool={pool}: checked={res['checked']} "
-          f"fragile={res['fragile']} {res['flags']}")
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    case.check((ids, d, st), w.k, w.ef, w.eps, mode, pool,
+               min_checked=0.95 if which == "sift" else 0.65,
+               label=f"{which} mode={mode} pool={pool}")
     assert np.all(st[:, 11] & ~P.PEOS_STATUS_VISITED_SPILL == 0)
-    assert abs(recall(case, ids, w.k) - recall(case, ref["ids"], w.k)) <= 0.003 + 1e-12
 
 
 @pytest.mark.parametrize("eps", [0.05, 0.2, 0.5])
 def test_search_eps_values(tiny, eps):
     w = tiny.w
     ids, d, st = run(tiny, w.k, w.ef, eps, P.PEOS_MODE_PEOS)
-    res = compare(ids, d, st, tiny.oracle(w.k, w.ef, eps, P.PEOS_MODE_PEOS), w.k)
-    assert not res["bad"], res["bad"][:5]
+    tiny.check((ids, d, st), w.k, w.ef, eps, P.PEOS_MODE_PEOS, min_checked=0.65,
+               label=f"eps={eps}")
 
 
 def test_per_query_k_ef_ragged_batch(tiny):
@@ -202,10 +214,8 @@ def test_per_query_k_ef_ragged_batch(tiny):
     ids, d, st = P.search(tiny.index, T(q), T(k), T(ef), eps=w.eps, kstride=40)
     torch.cuda.synchronize()
     ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
-    ref = O.search(tiny.x, tiny.g, tiny.entry, q, k, ef, w.L, w.m, tiny.A, tiny.B, w.metric,
-                   w.eps, kstride=40, precision=32)
-    res = compare(ids, d, st, ref, 40)
-    assert not res["bad"], res["bad"][:5]
+    tiny.check((ids, d, st), k, ef, w.eps, P.PEOS_MODE_PEOS, queries=q, kstride=40,
+               min_checked=0.65, label="ragged batch")
     for i in range(nq):
         assert np.all(ids[i, k[i]:] == -1) and np.all(np.isinf(d[i, k[i]:]))
 
@@ -215,19 +225,17 @@ def test_visited_spill_and_pool_capacity(tiny):
     list capacity with pool = 0 behaves as pool = that capacity."""
     w = tiny.w
     try:
-        P.peos_set_search_tuning(hash_cap=100, listcap=128, slots=7)
+        P.peos_set_search_tuning(tiny.index, hash_cap=100, listcap=128, slots=7)
         ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=0)
         ids2, d2, st2 = run(tiny, w.k, 96, w.eps, P.PEOS_MODE_EXHAUSTIVE, pool=0)
     finally:
-        P.peos_set_search_tuning(0, 0, 0)
+        P.peos_set_search_tuning(tiny.index)
     assert np.all(st[:, 11] & P.PEOS_STATUS_VISITED_SPILL)
-    ref = tiny.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=128)
-    res = compare(ids, d, st, ref, w.k)
-    assert not res["bad"], res["bad"][:5]
+    tiny.check((ids, d, st), w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=128, min_checked=0.65,
+               label="spill")
     full = (st2[:, 11] & P.PEOS_STATUS_POOL_FULL) != 0
-    ref2 = tiny.oracle(w.k, 96, w.eps, P.PEOS_MODE_EXHAUSTIVE, pool=128)
-    res2 = compare(ids2, d2, st2, ref2, w.k)
-    assert not res2["bad"], res2["bad"][:5]
+    tiny.check((ids2, d2, st2), w.k, 96, w.eps, P.PEOS_MODE_EXHAUSTIVE, pool=128,
+               min_checked=0.5, label="pool capacity")
     print(f"[gpu] pool-full queries: {int(full.sum())}")
 
 
@@ -275,6 +283,7 @@ def test_duplicate_vectors_and_single_node(tiny):
     dup = Case.__new__(Case)
     dup.w, dup.x, dup.q, dup.g, dup.entry, dup.A, dup.B = w, x, tiny.q, g, entry, A, B
     dup.index, dup.qt = index, tiny.qt
+    dup.check = Case.check.__get__(dup)
     codes, sc = read_records(dup)
     rc, rs, _ = O.build_tables(x, g, w.L, w.m, A, B)
     valid = g >= 0
@@ -287,12 +296,10 @@ def test_duplicate_vectors_and_single_node(tiny):
         ids, d, st = run(dup, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool)
         ref = dup.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool)
         assert ref["counters"][:, O.COUNTERS.index("test_zero")].sum() > 0
-        res = compare(ids, d, st, ref, w.k)
-        print(f"[gpu] duplicates pool={pool}: checked={res['checked']} fragile={res['fragile']}")
-        assert not res["bad"], res["bad"][:5]
         # a twin at exactly the list's bound is a tie with delta, which marks
         # the query fragile: about a fifth of these queries meet one
-        assert res["checked"] >= 0.7 * len(ids)
+        dup.check((ids, d, st), w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool, min_checked=0.55,
+                  label=f"duplicates pool={pool}")
     # one node, no edges
     one = P.peos_build_tables(T(tiny.x[:1]), T(np.full((1, w.R), -1, np.int32)), 0, w.L, w.m,
                               tiny.At, tiny.Bt, w.metric)
@@ -304,12 +311,37 @@ def test_duplicate_vectors_and_single_node(tiny):
     np.testing.assert_allclose(d[:, 0], ref, rtol=1e-5)
 
 
-def test_large_list(tiny):
-    """ef = 256 (the largest in the sweeps) with the queue unbounded."""
-    w = tiny.w
-    ids, d, st = run(tiny, 100, 256, w.eps, P.PEOS_MODE_PEOS)
-    res = compare(ids, d, st, tiny.oracle(100, 256, w.eps, P.PEOS_MODE_PEOS), 100)
-    assert not res["bad"], res["bad"][:5]
+@pytest.mark.parametrize("which", ["tiny", "sift"])
+def test_large_list(which, request):
+    """ef = 256 (the largest in the sweeps) with the queue unbounded.  On
+    real-valued data such a list nearly always holds two distances within
+    1e-5 of each other (observed: 70 of 100 queries), so the FP64 rule checks
+    the rest; on the integer-valued case it checks every query."""
+    case = request.getfixturevalue(which)
+    w = case.w
+    ids, d, st = run(case, 100, 256, w.eps, P.PEOS_MODE_PEOS)
+    case.check((ids, d, st), 100, 256, w.eps, P.PEOS_MODE_PEOS,
+               min_checked=0.95 if which == "sift" else 0.2,
+               label=f"{which} ef=256 unbounded queue")
+
+
+@pytest.mark.parametrize("which", ["tiny", "angular", "sift"])
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_waves_per_query_change_nothing(which, pool_mul, request):
+    """1, 2 or 4 waves per query (the rows of each gather split over the
+    workgroup's waves): identical ids, distances and counters."""
+    case = request.getfixturevalue(which)
+    w = case.w
+    outs = []
+    try:
+        for nw in (1, 2, 4):
+            P.peos_set_search_tuning(case.index, waves=nw)
+            outs.append(run(case, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool_mul * w.ef))
+    finally:
+        P.peos_set_search_tuning(case.index)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
 
 
 def test_repeatable(tiny):
@@ -328,7 +360,7 @@ def test_results_do_not_depend_on_launch_plan(tiny):
     base = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
     try:
         for tune in ((1024, 0, 0), (1536, 0, 0), (4096, 256, 0), (300, 0, 5)):
-            P.peos_set_search_tuning(*tune)
+            P.peos_set_search_tuning(tiny.index, *tune)
             other = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
             assert np.array_equal(base[0], other[0]) and np.array_equal(base[1], other[1])
             st_a, st_b = base[2].copy(), other[2].copy()
@@ -336,7 +368,32 @@ def test_results_do_not_depend_on_launch_plan(tiny):
             st_b[:, 11] &= ~P.PEOS_STATUS_VISITED_SPILL
             assert np.array_equal(st_a, st_b)
     finally:
-        P.peos_set_search_tuning(0, 0, 0)
+        P.peos_set_search_tuning(tiny.index)
+
+
+def test_launch_plan_belongs_to_its_index(tiny):
+    """Overrides set on one index leave another index over the same data
+    alone, and out-of-range values are rejected."""
+    w = tiny.w
+    other = P.peos_build_tables(tiny.xt, tiny.gt, tiny.entry, w.L, w.m, tiny.At, tiny.Bt,
+                                w.metric)
+    try:
+        # a visited hash of 100 slots spills every query of `other` only
+        P.peos_set_search_tuning(other, hash_cap=100)
+        a = P.search(tiny.index, tiny.qt, w.k, w.ef, eps=w.eps, pool=w.ef)
+        b = P.search(other, tiny.qt, w.k, w.ef, eps=w.eps, pool=w.ef)
+        torch.cuda.synchronize()
+        assert not (a[2][:, 11] & P.PEOS_STATUS_VISITED_SPILL).any()
+        assert (b[2][:, 11] & P.PEOS_STATUS_VISITED_SPILL).all()
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+        for bad in (dict(hash_cap=20), dict(listcap=-1), dict(slots=5000), dict(waves=3)):
+            with pytest.raises(P.PeosError):
+                P.peos_set_search_tuning(other, **bad)
+        with pytest.raises(P.PeosError):
+            P.peos_set_class_tuning(other, 8)
+        assert P.lib().peos_set_long_rows(other.handle, 2) == P.PEOS_EINVAL
+    finally:
+        other.close()
 
 
 def test_autotune_sets_a_capacity(tiny):
@@ -350,10 +407,10 @@ def test_autotune_sets_a_capacity(tiny):
         assert cap == 0 or times[cap] <= (1 - autotune.KEEP_DEFAULT) * times[0]
         assert times[cap] == min(times.values()) or cap == 0
         ids, d, st = run(tiny, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
-        ref = tiny.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef)
-        assert not compare(ids, d, st, ref, w.k)["bad"]
+        tiny.check((ids, d, st), w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=w.ef,
+                   min_checked=0.65, label="autotuned")
     finally:
-        P.peos_set_search_tuning(0, 0, 0)
+        P.peos_set_search_tuning(tiny.index)
 
 
 # ---------------------------------------------------------------------------
@@ -369,12 +426,10 @@ def test_ef_classes_match_oracle_and_single_runs(angular):
     ids, d, st = P.search(case.index, case.qt, kt, eft, eps=w.eps, pool=1, kstride=100)
     torch.cuda.synchronize()
     ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
-    ref = O.search(case.x, case.g, case.entry, case.q, k, ef, w.L, w.m, case.A, case.B, w.metric,
-                   w.eps, kstride=100, pool=1, precision=32)
-    res = compare(ids, d, st, ref, 100)
-    print(f"[gpu] ef classes: checked={res['checked']} fragile={res['fragile']}")
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    # lists up to 256 real-valued distances: about half the queries meet two
+    # within 1e-5 of each other (observed 49 of 100 checked)
+    case.check((ids, d, st), k, ef, w.eps, P.PEOS_MODE_PEOS, pool=1, kstride=100,
+               min_checked=0.35, label="ef classes")
     for i in range(len(k)):
         assert np.all(ids[i, k[i]:] == -1)
     # each ef value alone, uniform launch (no class split)
@@ -393,11 +448,11 @@ def test_ef_class_tuning_does_not_change_results(angular):
     base = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=1, kstride=100)
     try:
         for c, (hc, sl) in enumerate([(512, 3), (1024, 0), (3000, 17), (8192, 5)]):
-            P.peos_set_class_tuning(c, hc, sl)
+            P.peos_set_class_tuning(case.index, c, hc, sl)
         other = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=1, kstride=100)
     finally:
         for c in range(8):
-            P.peos_set_class_tuning(c, 0, 0)
+            P.peos_set_class_tuning(case.index, c)
     torch.cuda.synchronize()
     assert torch.equal(base[0], other[0]) and torch.equal(base[1], other[1])
 
@@ -453,11 +508,8 @@ def test_per_query_bounded_queue_matches_oracle(angular):
     ids, d, st = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=-2, kstride=100)
     torch.cuda.synchronize()
     ids, d, st = ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
-    ref = O.search(case.x, case.g, case.entry, case.q, k, ef, w.L, w.m, case.A, case.B, w.metric,
-                   w.eps, kstride=100, pool=-2, precision=32)
-    res = compare(ids, d, st, ref, 100)
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    case.check((ids, d, st), k, ef, w.eps, P.PEOS_MODE_PEOS, pool=-2, kstride=100,
+               min_checked=0.3, label="bounded queue -2")
     assert np.all(st[:, 11] & P.PEOS_STATUS_POOL_FULL == 0)
 
 
@@ -474,11 +526,9 @@ def test_search_on_graph_with_random_long_edges():
     for pool in (0, w.ef):
         ids, d, st = P.search(idx, T(q), w.k, w.ef, eps=w.eps, pool=pool)
         torch.cuda.synchronize()
-        ref = O.search(x, g, entry, q, w.k, w.ef, w.L, w.m, A, B, w.metric, w.eps, pool=pool,
-                       precision=32)
-        res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, w.k)
-        assert not res["bad"], res["bad"][:5]
-        assert res["checked"] >= 0.8 * len(q)
+        check_both((ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()), x, g, entry, q, w.k,
+                   w.ef, w.L, w.m, A, B, w.metric, w.eps, pool=pool, min_checked=0.65,
+                   label=f"random long edges pool={pool}")
 
 
 # ---------------------------------------------------------------------------
@@ -529,11 +579,9 @@ def test_permuted_index_matches_oracle(aniso, pool):
     # search
     ids, d, st = P.search(idx, T(q), 10, 32, eps=0.1, pool=pool)
     torch.cuda.synchronize()
-    ref = O.search(x, g, entry, q, 10, 32, L, m, A, B, W.L2, 0.1, pool=pool, precision=32,
-                   perm=perm)
-    res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, 10)
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(q)
+    check_both((ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()), x, g, entry, q, 10, 32, L,
+               m, A, B, W.L2, 0.1, pool=pool, perm=perm, min_checked=0.5,
+               label=f"permuted pool={pool}")
 
 
 @pytest.mark.parametrize("pool_mul", [0, 1])
@@ -547,11 +595,9 @@ def test_rceos_is_the_L1_case(pool_mul):
     idx = P.peos_build_tables(T(x), T(g), entry, 1, 64, T(A), T(B), w.metric)
     ids, d, st = P.search(idx, T(q), w.k, w.ef, eps=w.eps, pool=pool_mul * w.ef)
     torch.cuda.synchronize()
-    ref = O.search(x, g, entry, q, w.k, w.ef, 1, 64, A, B, w.metric, w.eps,
-                   pool=pool_mul * w.ef, precision=32)
-    res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, w.k)
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(q)
+    check_both((ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()), x, g, entry, q, w.k, w.ef,
+               1, 64, A, B, w.metric, w.eps, pool=pool_mul * w.ef, min_checked=0.65,
+               label=f"rceos pool={pool_mul * w.ef}")
     assert st.cpu().numpy()[:, 6].sum() > 0  # H-vs-T tests did run
 
 
@@ -596,14 +642,9 @@ def test_simhash_search_matches_oracle(simhash_case, pool_mul, eps):
     ids, d, st = P.search(idx, case.qt, w.k, w.ef, eps=eps, mode=P.PEOS_MODE_SIMHASH,
                           pool=pool_mul * w.ef)
     torch.cuda.synchronize()
-    ref = O.search(case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B,
-                   w.metric, eps, mode=O.MODE_SIMHASH, pool=pool_mul * w.ef, precision=32,
-                   simhash=C)
-    res = compare(ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy(), ref, w.k)
-    print(f"[gpu] simhash eps={eps} pool={pool_mul * w.ef}: checked={res['checked']} "
-          f"fragile={res['fragile']}")
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(case.q)
+    case.check((ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()), w.k, w.ef, eps,
+               O.MODE_SIMHASH, pool=pool_mul * w.ef, simhash=C, min_checked=0.65,
+               label=f"simhash eps={eps} pool={pool_mul * w.ef}")
     assert st.cpu().numpy()[:, 6].sum() > 0
 
 
@@ -652,12 +693,21 @@ def test_descent_then_search_matches_oracle(which, pool_mul, bf16, request):
     ok = frag == 0
     assert ok.mean() >= 0.9
     assert np.array_equal(st[ok, P.PEOS_STAT_DESCENT], nd[ok])
+    label = f"descent {which} pool={pool_mul * w.ef} bf16={bf16}"
+    print(f"[gpu] {label}: mean descent distances {nd.mean():.1f}")
+    if not bf16:
+        # the FP64 descent reaches the same entries except on its own near ties
+        ent64, nd64, frag64 = O.descend(case.x, lay, case.q, w.metric, precision=64)
+        assert np.array_equal(ent64[ok & (frag64 == 0)], ent[ok & (frag64 == 0)])
+        case.check((ids, d, st), w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool=pool_mul * w.ef,
+                   entries=ent, entries64=ent64, extra_fragile=~ok | (frag64 != 0),
+                   min_checked=0.6, label=label)
+        return
     ref = O.search(case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B,
                    w.metric, w.eps, pool=pool_mul * w.ef, precision=32, lowp=lowp, entries=ent)
     ref["fragile"] = ref["fragile"] | np.where(ok, 0, O.F_ORDER)
     res = compare(ids, d, st, ref, w.k)
-    print(f"[gpu] descent {which} pool={pool_mul * w.ef} bf16={bf16}: checked={res['checked']} "
-          f"mean descent distances {nd.mean():.1f}")
+    print(f"[gpu] {label}: checked={res['checked']}")
     assert not res["bad"], res["bad"][:5]
     assert res["checked"] >= 0.8 * len(ids)
 
@@ -696,11 +746,11 @@ def test_maximum_degree_subspaces_and_directions(pool_mul):
                    48, 1012)
     case = Case(w)
     ids, d, st = run(case, w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool_mul * w.ef)
-    ref = case.oracle(w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool_mul * w.ef)
-    res = compare(ids, d, st, ref, w.k)
-    print(f"[gpu] max shape pool={pool_mul * w.ef}: checked={res['checked']}")
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    # R = 64 neighbours per expansion: many more list comparisons, and about
+    # half the queries meet two distances within 1e-5 (observed 23-27 of 60
+    # checked)
+    case.check((ids, d, st), w.k, w.ef, w.eps, P.PEOS_MODE_PEOS, pool_mul * w.ef,
+               min_checked=0.3, label=f"max shape pool={pool_mul * w.ef}")
     assert st[:, 6].sum() > 0
     codes, _ = read_records(case)
     rc, _, _ = O.build_tables(case.x, case.g, w.L, w.m, case.A, case.B)
@@ -708,17 +758,20 @@ def test_maximum_degree_subspaces_and_directions(pool_mul):
     assert np.array_equal(codes[valid], rc[valid]) and codes.max() >= 128
 
 
+@pytest.mark.parametrize("which", ["tiny", "sift"])
 @pytest.mark.parametrize("ef", [1024, 2048])
-def test_long_result_lists(tiny, ef):
+def test_long_result_lists(which, ef, request):
     """Result lists of 1024 and 2048 entries under the HNSW rule (the list
-    and the visited set in LDS or spilled to HBM), k = 100."""
-    w = tiny.w
-    q = tiny.q[:20]
-    ids, d, st = run(tiny, 100, ef, w.eps, P.PEOS_MODE_PEOS, ef, queries=q)
-    ref = tiny.oracle(100, ef, w.eps, P.PEOS_MODE_PEOS, ef, queries=q)
-    res = compare(ids, d, st, ref, 100)
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    and the visited set in LDS or spilled to HBM), k = 100.  Long lists of
+    real-valued distances nearly always hold two within 1e-5 of each other,
+    so on the Gaussian case the FP64 rule checks few queries; on the
+    integer-valued case no comparison is fragile."""
+    case = request.getfixturevalue(which)
+    w = case.w
+    q = case.q[:20]
+    ids, d, st = run(case, 100, ef, w.eps, P.PEOS_MODE_PEOS, ef, queries=q)
+    case.check((ids, d, st), 100, ef, w.eps, P.PEOS_MODE_PEOS, ef, queries=q,
+               min_checked=0.9 if which == "sift" else 0.0, label=f"{which} ef={ef}")
 
 
 def test_list_beyond_lds_is_rejected(tiny):

@@ -15,7 +15,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from parity import compare
+from parity import check_both, compare, compare64
 
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2402_11354_amd")
@@ -199,7 +199,9 @@ def test_half_form_against_oracle(which, flags, request):
     frag = ref["fragile"] != 0
     same = np.all(ids == ref["ids"], axis=1) & np.all(d.astype(np.float64) == ref["dist"], axis=1)
     print(f"[gpu] {which} flags={flags}: identical {same[~frag].mean():.3f} of non-fragile")
-    assert same[~frag].mean() >= 0.9
+    # observed: every non-fragile query identical; one in fifty may differ
+    # through a half rounded the other way at a decisive test
+    assert same[~frag].mean() >= 0.98
     d64 = O.brute_force(case.x, case.q, w.k, w.metric)
     valid = ids >= 0
     xs = case.x.astype(np.float64)
@@ -215,8 +217,17 @@ def test_half_form_against_oracle(which, flags, request):
     full = case.run(0, pool=w.ef)
     gt = d64[0]
     rec = lambda I: np.mean([len(set(I[i]) & set(gt[i])) / w.k for i in range(len(I))])
-    print(f"[gpu] {which} flags={flags}: recall {rec(ids):.4f} vs full {rec(full[0]):.4f}")
+    # the precision form against the FP64 oracle: distance error of every
+    # returned result and recall loss (reported; bounded as above)
+    ref64 = O.search(case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B,
+                     w.metric, w.eps, pool=w.ef, precision=64)
+    r64 = compare64(ids, d, ref64, w.k, case.x, case.q, w.metric, gt=gt, check_counters=False)
+    print(f"[gpu] {which} flags={flags}: recall {rec(ids):.4f} vs full {rec(full[0]):.4f}, "
+          f"vs FP64 oracle {r64['recall_oracle']:.4f} (same ids {r64['same_ids']:.3f}, "
+          f"largest relative distance error {r64['max_rel_err']:.2e})")
     assert rec(ids) >= rec(full[0]) - 0.005
+    assert rec(ids) >= r64["recall_oracle"] - 0.005
+    assert r64["max_rel_err"] <= 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -263,9 +274,12 @@ def test_long_vectors_match_oracle(wide, flags, pool_mul):
     order, exact parity (and the fp32 path on the same data)."""
     w = wide.w
     ids, d, st = wide.run(flags, pool=pool_mul * w.ef)
-    ref = wide.oracle(flags, pool=pool_mul * w.ef) if flags else O.search(
-        wide.x, wide.g, wide.entry, wide.q, w.k, w.ef, w.L, w.m, wide.A, wide.B, w.metric, w.eps,
-        pool=pool_mul * w.ef, precision=32)
+    if not flags:
+        check_both((ids, d, st), wide.x, wide.g, wide.entry, wide.q, w.k, w.ef, w.L, w.m, wide.A,
+                   wide.B, w.metric, w.eps, pool=pool_mul * w.ef, min_checked=0.6,
+                   label=f"wide fp32 pool={pool_mul * w.ef}")
+        return
+    ref = wide.oracle(flags, pool=pool_mul * w.ef)
     res = compare(ids, d, st, ref, w.k)
     print(f"[gpu] wide flags={flags} pool={pool_mul * w.ef}: checked={res['checked']}")
     assert not res["bad"], res["bad"][:5]
@@ -282,12 +296,35 @@ def test_long_row_variant_changes_nothing(wide, flags, pool_mul):
     w = wide.w
     a = wide.run(flags, pool=pool_mul * w.ef)
     try:
-        P.peos_set_long_rows(False)
+        P.peos_set_long_rows(wide.index(flags), False)
         b = wide.run(flags, pool=pool_mul * w.ef)
     finally:
-        P.peos_set_long_rows(True)
+        P.peos_set_long_rows(wide.index(flags), True)
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("flags", [0, P.PEOS_FLAG_BF16_BASE,
+                                   P.PEOS_FLAG_BF16_BASE | P.PEOS_FLAG_FP16])
+def test_waves_per_query_change_nothing_on_long_vectors(wide, flags):
+    """Waves per query with the long-vector variant and the bfloat16
+    re-rank (whose full-precision gathers are split too): identical
+    results for 1, 2 and 4 waves, with the variant allowed and forbidden."""
+    w = wide.w
+    ix = wide.index(flags)
+    outs = []
+    try:
+        for long_rows in (True, False):
+            P.peos_set_long_rows(ix, long_rows)
+            for nw in (1, 2, 4):
+                P.peos_set_search_tuning(ix, waves=nw)
+                outs.append(wide.run(flags, pool=0))
+    finally:
+        P.peos_set_search_tuning(ix)
+        P.peos_set_long_rows(ix, True)
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
 
 
 @pytest.fixture(scope="module")
@@ -312,18 +349,19 @@ def test_long_rows_angular_and_inner_product(which, flags, request):
     case = request.getfixturevalue(which)
     w = case.w
     ids, d, st = case.run(flags, pool=0)
-    ref = case.oracle(flags, pool=0) if flags else O.search(
-        case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B, w.metric, w.eps,
-        pool=0, precision=32)
-    res = compare(ids, d, st, ref, w.k)
-    print(f"[gpu] {which} flags={flags}: checked={res['checked']} fragile={res['fragile']}")
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    if flags:
+        res = compare(ids, d, st, case.oracle(flags, pool=0), w.k)
+        print(f"[gpu] {which} flags={flags}: checked={res['checked']} fragile={res['fragile']}")
+        assert not res["bad"], res["bad"][:5]
+        assert res["checked"] >= 0.8 * len(ids)
+    else:
+        check_both((ids, d, st), case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A,
+                   case.B, w.metric, w.eps, pool=0, min_checked=0.4, label=f"{which} fp32")
     try:
-        P.peos_set_long_rows(False)
+        P.peos_set_long_rows(case.index(flags), False)
         other = case.run(flags, pool=0)
     finally:
-        P.peos_set_long_rows(True)
+        P.peos_set_long_rows(case.index(flags), True)
     for x, y in zip((ids, d, st), other):
         assert np.array_equal(x, y)
 
@@ -341,17 +379,65 @@ def test_long_rows_simhash(wide):
         return ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
 
     ids, d, st = run()
-    ref = O.search(wide.x, wide.g, wide.entry, wide.q, w.k, w.ef, w.L, w.m, wide.A, wide.B,
-                   w.metric, 0.1, mode=O.MODE_SIMHASH, pool=0, precision=32, simhash=C)
-    res = compare(ids, d, st, ref, w.k)
-    print(f"[gpu] wide simhash: checked={res['checked']} fragile={res['fragile']}")
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.8 * len(ids)
+    check_both((ids, d, st), wide.x, wide.g, wide.entry, wide.q, w.k, w.ef, w.L, w.m, wide.A,
+               wide.B, w.metric, 0.1, mode=O.MODE_SIMHASH, pool=0, simhash=C, min_checked=0.5,
+               label="wide simhash")
     assert st[:, 6].sum() > 0
     try:
-        P.peos_set_long_rows(False)
+        P.peos_set_long_rows(idx, False)
         other = run()
     finally:
-        P.peos_set_long_rows(True)
+        P.peos_set_long_rows(idx, True)
     for x, y in zip((ids, d, st), other):
         assert np.array_equal(x, y)
+
+
+@pytest.fixture(scope="module")
+def gist_shape():
+    print("[gpu] precision: the GIST-like recipe at its own shape (d = 960, L = 16)", flush=True)
+    w = W.GIST_LIKE.with_sizes(n=3000, nq=48)
+    x = W.make_base(w)
+    g, entry = W.graph_for(w, x)
+    case = Case.__new__(Case)
+    case.w, case.x, case.q = w, x, W.make_queries(w)
+    case.g, case.entry = g, entry
+    case.A, case.B = W.directions_for(w)
+    case.xt, case.gt, case.At, case.Bt, case.qt = (T(a) for a in (case.x, case.g, case.A,
+                                                                    case.B, case.q))
+    case.idx = {}
+    return case
+
+
+@pytest.mark.parametrize("pool_mul", [0, 1])
+def test_gist_shape_fp32_and_precision_forms(gist_shape, pool_mul):
+    """The precision workload's own shape: d = 960, d' = 60, L = 16, R = 32
+    with its random long-range edges, on 3,000 vectors.  The fp32 path under
+    both parity rules; the precision form (bfloat16 traversal, half scalars
+    and tables, fp32 re-rank) against the oracle's precision form, and its
+    distance error and recall against the FP64 oracle."""
+    case = gist_shape
+    w = case.w
+    pool = pool_mul * w.ef
+    ids, d, st = case.run(0, pool=pool)
+    # lists of 128 distances near 10^3 at d = 960: nearly every query meets
+    # two within 1e-5 relative (observed 4 of 48 checked); every query's ids
+    # still equal the FP64 oracle's, and the single-precision replica checks
+    # the rest exactly
+    check_both((ids, d, st), case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A,
+               case.B, w.metric, w.eps, pool=pool, min_checked=0.05, min_same=0.95,
+               label=f"gist shape pool={pool}")
+    flags = P.PEOS_FLAG_BF16_BASE | P.PEOS_FLAG_FP16
+    pi, pd, ps = case.run(flags, pool=pool)
+    ref = case.oracle(flags, pool=pool)
+    frag = ref["fragile"] != 0
+    same = np.all(pi == ref["ids"], axis=1) & np.all(pd.astype(np.float64) == ref["dist"], axis=1)
+    gt, _ = O.brute_force(case.x, case.q, w.k, w.metric)
+    ref64 = O.search(case.x, case.g, case.entry, case.q, w.k, w.ef, w.L, w.m, case.A, case.B,
+                     w.metric, w.eps, pool=pool, precision=64)
+    r64 = compare64(pi, pd, ref64, w.k, case.x, case.q, w.metric, gt=gt, check_counters=False)
+    print(f"[gpu] gist shape precision form pool={pool}: identical {same[~frag].mean():.3f} of "
+          f"non-fragile; recall {r64['recall_gpu']:.4f} vs FP64 oracle {r64['recall_oracle']:.4f}; "
+          f"largest relative distance error {r64['max_rel_err']:.2e}")
+    assert same[~frag].mean() >= 0.95
+    assert r64["max_rel_err"] <= 1e-5
+    assert r64["recall_gpu"] >= r64["recall_oracle"] - 0.01

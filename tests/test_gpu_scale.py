@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 import workloads as W
-from parity import compare
+from parity import check_both
 
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2402_11354_amd")
@@ -121,18 +121,20 @@ def test_fullsize_search(full, name, ef, pool, eps, mode):
     d64 = ((xs[it] - qs[:, None, :]) ** 2).sum(-1).cpu().numpy()
     assert np.all(np.abs(d.astype(np.float64) - d64) <= 1e-5 * d64 + 1e-6)
     assert np.all(st[:, 11] & P.PEOS_STATUS_ZERO_QUERY == 0)
-    # the sampled queries against the oracle, one by one
+    # the sampled queries against the oracle, one by one, in FP64 (the
+    # arbiter) and in the kernel's single precision (exact replica).  On this
+    # integer-valued workload every distance and A_r numerator is exact in
+    # single precision, so only routing-test decisions within 1e-5 of their
+    # boundary are fragile: nearly every sampled query is checked.
     s = full.sample
-    ref = O.search(full.x, full.g, full.entry, full.q[s], w.k, ef, w.L, w.m, full.A, full.B,
-                   w.metric, eps, mode=mode, pool=pool, precision=32)
-    res = compare(ids[s], d[s], st[s], ref, w.k)
-    print(f"[gpu] {name}: checked={res['checked']}/{len(s)} fragile={res['fragile']} "
-          f"{res['flags']}", flush=True)
-    assert not res["bad"], res["bad"][:5]
-    assert res["checked"] >= 0.75 * len(s)
+    r32, r64 = check_both((ids[s], d[s], st[s]), full.x, full.g, full.entry, full.q[s], w.k, ef,
+                          w.L, w.m, full.A, full.B, w.metric, eps, mode=mode, pool=pool,
+                          gt=full.gt_ids[s], min_checked=0.95, label=name)
     from workloads.graph import recall_at_k
     r_gpu = recall_at_k(full.x, full.q[s], ids[s], full.gt_d[s], w.k, w.metric).mean()
+    ref = O.search(full.x, full.g, full.entry, full.q[s], w.k, ef, w.L, w.m, full.A, full.B,
+                   w.metric, eps, mode=mode, pool=pool, precision=64)
     r_orc = recall_at_k(full.x, full.q[s], ref["ids"], full.gt_d[s], w.k, w.metric).mean()
-    print(f"[gpu] {name}: recall@10 gpu={r_gpu:.4f} oracle={r_orc:.4f} "
+    print(f"[gpu] {name}: tie-aware recall@10 gpu={r_gpu:.4f} oracle={r_orc:.4f} "
           f"(all queries {recall_at_k(full.x, full.q, ids, full.gt_d, w.k, w.metric).mean():.4f})")
     assert abs(r_gpu - r_orc) <= 0.003 + 1e-12
