@@ -78,9 +78,13 @@ def main():
     ap.add_argument("--pools", default="ef,0",
                     help="candidate-list capacities to sweep: 'ef' = the HNSW stopping rule, "
                          "0 = the unbounded queue of the printed Alg. 1")
-    ap.add_argument("--epss", default="0.1,0.2", help="eps values swept for PEOs")
+    ap.add_argument("--epss", default="0.05,0.1,0.2", help="eps values swept for PEOs")
     ap.add_argument("--target", type=float, default=0.95)
-    ap.add_argument("--efs", default="16,24,32,48,64,96,128,192,256")
+    ap.add_argument("--efs", default="16,24,32,40,48,52,56,60,64,72,80,96,128,192,256")
+    ap.add_argument("--sweep-steps", type=int, default=10,
+                    help="timed steps per swept operating point")
+    ap.add_argument("--no-half", action="store_true",
+                    help="skip the sweep of records with 16-bit scalars")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="oracle CPU-baseline budget")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-only", action="store_true",
@@ -172,7 +176,7 @@ def main():
     torch.cuda.synchronize()
     log(f"edge records built in {time.time() - t0:.2f}s")
     t0 = time.time()
-    _, gt_d = W.ground_truth(x, q, w.k, w.metric, device=dev)
+    gt_ids, gt_d = W.ground_truth(x, q, w.k, w.metric, device=dev)
     log(f"ground truth in {time.time() - t0:.1f}s")
 
     nq = w.nq
@@ -188,27 +192,28 @@ def main():
     def pool_of(spec, ef):
         return ef if spec == "ef" else int(spec)
 
-    def step(cfg, ev=None):
+    def step(cfg, ev=None, ix=None):
         ef, pool, eps, mode = cfg
+        ix = index if ix is None else ix
         if ev is not None:
             ev[0].record()
-        P.peos_query_tables(index, qt, tables, qnorms)
+        P.peos_query_tables(ix, qt, tables, qnorms)
         if ev is not None:
             ev[1].record()
-        P.peos_search_tables(index, qt, tables, qnorms, w.k, ef, w.k, pool, eps, mode, ids, dists,
+        P.peos_search_tables(ix, qt, tables, qnorms, w.k, ef, w.k, pool, eps, mode, ids, dists,
                              stats, ws)
         if ev is not None:
             ev[2].record()
 
-    def timed(cfg, steps, warmup):
+    def timed(cfg, steps, warmup, ix=None):
         for _ in range(warmup):
-            step(cfg)
+            step(cfg, ix=ix)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
         torch.cuda.synchronize()
         t_start = time.perf_counter()
         for i in range(steps):
-            step(cfg, evs[i])
+            step(cfg, evs[i], ix=ix)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_start
         step_ms = np.array([e[0].elapsed_time(e[2]) for e in evs])
@@ -217,7 +222,7 @@ def main():
         return wall, step_ms, table_ms, search_ms
 
     if args.profile_only:
-        P.peos_set_search_tuning(args.hash_cap, args.listcap, args.slots)
+        P.peos_set_search_tuning(index, args.hash_cap, args.listcap, args.slots)
         cfg = (args.ef, pool_of(args.pool, args.ef), args.eps, P.PEOS_MODE_PEOS)
         wall, sms, tms, srch = timed(cfg, args.steps, args.warmup)
         log(f"profile-only {cfg}: step {sms.mean():.3f} ms search {srch.mean():.3f} ms "
@@ -233,19 +238,20 @@ def main():
                                              hash_cap=args.hash_cap)))
         return
 
-    def sweep(pool_spec, eps, mode):
+    def sweep(pool_spec, eps, mode, ix=None, tag=""):
         pts = []
         for ef in efs:
             cfg = (ef, pool_of(pool_spec, ef), eps, mode)
-            step(cfg)
+            step(cfg, ix=ix)
             torch.cuda.synchronize()
             r = float(recall_at_k(x, q, ids.cpu().numpy(), gt_d, w.k, w.metric).mean())
             st = stats.cpu().numpy()
-            wall, _, _, _ = timed(cfg, 3, 1)
-            qps = nq * 3 / wall
+            wall, _, _, _ = timed(cfg, args.sweep_steps, 2, ix=ix)
+            qps = nq * args.sweep_steps / wall
             pts.append(dict(cfg=cfg, recall=r, qps=qps, stats=st))
-            log(f"  {'PEOS' if mode == 0 else 'EXH '} pool={pool_spec} eps={eps} ef={ef}: "
-                f"recall={r:.4f} qps~{qps:.0f} exp={st[:, 0].mean():.0f} "
+            log(f"  {'PEOS' if mode == 0 else 'EXH '}{tag} pool={pool_spec} eps={eps} ef={ef}: "
+                f"recall={r:.4f} qps~{qps:.0f} exp={st[:, 0].mean():.1f} "
+                f"edges/exp={st[:, 1].sum() / max(1, st[:, 0].sum()):.1f} "
                 f"ndist={st[:, 9].mean():.0f} tests={st[:, 3].mean():.0f} "
                 f"spill={(st[:, 11] & 4 != 0).mean():.2f} full={(st[:, 11] & 2 != 0).mean():.2f}")
             if r >= args.target + 0.015:
@@ -269,6 +275,17 @@ def main():
         ex_sweeps[ps] = sweep(ps, 0.1, P.PEOS_MODE_EXHAUSTIVE)
     pe, pe_ok = best(pe_sweeps.values())
     ex, ex_ok = best(ex_sweeps.values())
+    # the same search on records with 16-bit scalars and tables (the paper's
+    # default scalar width; arithmetic stays single precision), HNSW rule
+    half_sweeps = {}
+    half_index = None
+    if not args.no_half:
+        half_index = P.peos_build_tables(xt, gt_, entry, w.L, w.m, At, Bt, w.metric,
+                                         flags=P.PEOS_FLAG_FP16)
+        for eps in epss:
+            log(f"sweep PEOS half records pool=ef eps={eps}")
+            half_sweeps[("ef", eps)] = sweep("ef", eps, P.PEOS_MODE_PEOS, ix=half_index,
+                                             tag=" half")
 
     def interpolated(sweeps):
         """QPS at exactly the target recall, linear in (recall, QPS) between
@@ -288,17 +305,17 @@ def main():
         ef, pool, eps, mode = cfg
         cap, _ = autotune.tune(index, qt, w.k, ef, pool=pool, eps=eps, mode=mode,
                                use_cache=False, log=log)
-        return cap
+        return cap, index.tuned_waves
 
-    pe_cap = tuned(pe["cfg"])
+    pe_cap, pe_waves = tuned(pe["cfg"])
     log(f"timed PEOS {pe['cfg']} hash_cap={pe_cap} ({args.steps} steps)")
     wall, step_ms, table_ms, search_ms = timed(pe["cfg"], args.steps, args.warmup)
     qps = nq * args.steps / wall
-    ex_cap = tuned(ex["cfg"])
+    ex_cap, ex_waves = tuned(ex["cfg"])
     log(f"timed EXHAUSTIVE {ex['cfg']} hash_cap={ex_cap}")
     ex_wall, ex_step_ms, _, ex_search_ms = timed(ex["cfg"], args.steps, args.warmup)
     ex_qps = nq * args.steps / ex_wall
-    P.peos_set_search_tuning(0, 0, 0)
+    P.peos_set_search_tuning(index)
 
     # algorithmic bytes of one search launch, from the kernel's own counters
     lay = index.layout()
@@ -333,11 +350,32 @@ def main():
     work_bytes = int(x.nbytes) + int(index.layout().node_stride) * w.n
     ceiling = measure_gather_ceiling(work_bytes)
 
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(x, g, entry, q, w, pe["cfg"], args.cpu_seconds)
+        cpu, ref = cpu_baseline(x, g, entry, q, w, pe["cfg"], args.cpu_seconds)
+        # the GPU's results at the headline point against the FP64 oracle's
+        # on the same queries (the oracle run that the baseline timed)
+        step(pe["cfg"])
+        torch.cuda.synchronize()
+        parity = parity_summary(x, q, w, ids.cpu().numpy(), dists.cpu().numpy(),
+                                stats.cpu().numpy(), ref, gt_ids)
 
     st = pe["stats"]
+    ip_pe, ip_ex = interpolated(pe_sweeps.values()), interpolated(ex_sweeps.values())
+    half = None
+    if half_sweeps:
+        hb, hb_ok = best(half_sweeps.values())
+        ip_h = interpolated(half_sweeps.values())
+        lay_h = half_index.layout()
+        half = {"record_bytes": int(lay_h.node_stride),
+                "record_bytes_fp32": int(index.layout().node_stride),
+                "best": {"ef": hb["cfg"][0], "eps": hb["cfg"][2], "recall": round(hb["recall"], 4),
+                         "qps": round(hb["qps"], 1), "recall_target_met": bool(hb_ok)},
+                "interpolated_at_target": ip_h,
+                "speedup_vs_exhaustive_at_target": (round(ip_h / ip_ex, 3)
+                                                    if ip_h and ip_ex else None),
+                "speedup_vs_fp32_records_at_target": (round(ip_h / ip_pe, 3)
+                                                      if ip_h and ip_pe else None)}
 
     def pts_json(d):
         out = {}
@@ -361,6 +399,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "nq": nq, "d": w.d, "R": w.R, "L": w.L,
                    "m": w.m, "eps": eps, "k": w.k, "ef": ef, "pool": pool, "hash_cap": pe_cap,
+                   "waves_per_query": pe_waves,
                    "stop_rule": "hnsw (pool=ef)" if pool == ef else "unbounded queue (Alg. 1)",
                    "metric": "l2" if w.metric == 0 else "angular"},
         "recall": round(pe["recall"], 4),
@@ -368,15 +407,19 @@ def main():
         "p50_ms": round(float(np.percentile(step_ms, 50)), 4),
         "p99_ms": round(float(np.percentile(step_ms, 99)), 4),
         "exhaustive": {"value": round(ex_qps, 1), "ef": ex["cfg"][0], "pool": ex["cfg"][1],
-                       "hash_cap": ex_cap,
+                       "hash_cap": ex_cap, "waves_per_query": ex_waves,
                        "recall": round(ex["recall"], 4), "recall_target_met": bool(ex_ok),
                        "p99_ms": round(float(np.percentile(ex_step_ms, 99)), 4),
                        "search_ms": round(float(ex_search_ms.mean()), 4),
                        "ndist_per_query": round(float(ex["stats"][:, 9].mean()), 1)},
         "speedup_vs_exhaustive": round(qps / ex_qps, 3),
-        "interpolated_at_target": {"peos": interpolated(pe_sweeps.values()),
-                                   "exhaustive": interpolated(ex_sweeps.values()),
-                                   "note": "sweep timing (3 steps per point)"},
+        "interpolated_at_target": {"peos": ip_pe, "exhaustive": ip_ex,
+                                   "speedup": (round(ip_pe / ip_ex, 3)
+                                               if ip_pe and ip_ex else None),
+                                   "note": f"QPS linear in recall between the two swept ef "
+                                           f"bracketing recall {args.target}, best over the "
+                                           f"sweeps; {args.sweep_steps} timed steps per point; "
+                                           f"ef grid {args.efs}, eps {args.epss}"},
         "per_query": {"ndist": round(float(st[:, 9].mean()), 1),
                       "tests": round(float(st[:, 3].mean()), 1),
                       "expansions": round(float(st[:, 0].mean()), 1),
@@ -394,7 +437,10 @@ def main():
                      "gather_ceiling": ceiling,
                      "frac_of_gather_ceiling": round(achieved / ceiling, 4) if ceiling else None},
         "cpu_baseline": cpu,
-        "sweep": {"peos": pts_json(pe_sweeps), "exhaustive": pts_json(ex_sweeps)},
+        "parity": parity,
+        "half_scalars": half,
+        "sweep": {"peos": pts_json(pe_sweeps), "exhaustive": pts_json(ex_sweeps),
+                  "peos_half_records": pts_json(half_sweeps)},
     }
     print(json.dumps(out), flush=True)
 
@@ -504,7 +550,7 @@ def batched(args):
             wall = time.perf_counter() - t0
             gr.close()
             for c in range(8):
-                P.peos_set_class_tuning(c, 0, 0)
+                P.peos_set_class_tuning(index, c)
             ms = np.array([a.elapsed_time(b) for a, b in evs])
             st = stats.cpu().numpy()
             ii = ids.cpu().numpy()
@@ -550,11 +596,12 @@ def precision(args):
 
     import paper_2402_11354_amd as P
     import workloads as W
+    from paper_2402_11354_amd import autotune
 
-    if args.no_long_rows:
-        P.peos_set_long_rows(False)
     name = args.workload if args.workload != "sift_like_1m_d128" else "gist_like_1m_d960"
     w, x, q, g, entry, index, gt_d = _setup(name, args.n, args.nq, 100)
+    if args.no_long_rows:
+        P.peos_set_long_rows(index, False)
     dev = torch.device("cuda:0")
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     A, B = W.directions_for(w)
@@ -575,6 +622,10 @@ def precision(args):
         for label, ix in (("fp32", index), ("precision", lowp)):
             pts = []
             for ef in efs:
+                # waves per query for this point (the batch of 1,000 queries
+                # leaves the chip room for 2 or 4 waves each)
+                autotune.tune(ix, qt, k, ef, pool=ef, eps=w.eps, caps=(0,), waves=(1, 2, 4),
+                              reps=2, use_cache=False)
                 ids, dd, st = P.search(ix, qt, k, ef, eps=w.eps, pool=ef, ws=ws)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
@@ -590,10 +641,10 @@ def precision(args):
                     d64 = 1.0 - (xs[ids] * qs[:, None, :]).sum(-1) / qs.norm(dim=1)[:, None]
                 err = ((dd.double() - d64).abs() / d64.clamp(min=1e-30)).max().item()
                 pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
-                                max_rel_dist_err=err,
+                                max_rel_dist_err=err, waves_per_query=ix.tuned_waves,
                                 **alg_rate(st.cpu().numpy(), ix.layout(), k, ef, qps)))
                 log(f"precision k={k} {label} ef={ef}: recall={rec:.4f} qps={qps:.0f} "
-                    f"max rel err={err:.2e}")
+                    f"max rel err={err:.2e} waves/query={ix.tuned_waves}")
             ok = [p_ for p_ in pts if p_["recall"] >= args.target]
             rows[label] = dict(points=pts, at_target=(max(ok, key=lambda p_: p_["qps"])
                                                       if ok else None))
@@ -919,26 +970,67 @@ def cpu_baseline(x, g, entry, q, w, cfg, budget_s):
 
     ef, pool, eps, mode = cfg
     A, B = W.directions_for(w)
-    threads = min(16, os.cpu_count() or 1)
+    threads, host_cpus = cpu_share()
+    out = {}
 
     def run(nq, nthreads):
         t0 = time.perf_counter()
-        oracle.search(x, g, entry, q[:nq], w.k, ef, w.L, w.m, A, B, w.metric, eps, mode=mode,
-                      pool=pool, nthreads=nthreads)
+        out["ref"] = oracle.search(x, g, entry, q[:nq], w.k, ef, w.L, w.m, A, B, w.metric, eps,
+                                   mode=mode, pool=pool, nthreads=nthreads, precision=64)
         return time.perf_counter() - t0
 
     n = 32
     dt = run(n, threads)
     n2 = int(min(len(q), max(n, n * budget_s / max(dt, 1e-3))))
     dt = run(n2, threads)
-    log(f"cpu baseline: {n2} queries in {dt:.1f}s on {threads} threads")
+    ref = out["ref"]
+    log(f"cpu baseline: {n2} queries in {dt:.1f}s on {threads} threads ({host_cpus} visible)")
     n1 = int(min(len(q), max(8, n2 / max(1.0, dt) * 2.0 / threads)))
     dt1 = run(n1, 1)
     log(f"cpu baseline: {n1} queries in {dt1:.1f}s on 1 thread")
     return {"value": round(n2 / dt, 2), "unit": "queries/s", "cores": threads, "kind": "oracle",
+            "host_cpus": host_cpus,
             "sample": f"first {n2} of the {len(q)} queries at the same ef/pool/eps "
-                      f"(float64 oracle, {threads} threads); single thread: first {n1}",
-            "value_1thread": round(n1 / dt1, 2)}
+                      f"(float64 oracle, one query per task on {threads} threads, the host "
+                      f"CPU share of this process); single thread: first {n1}",
+            "value_1thread": round(n1 / dt1, 2)}, ref
+
+
+def cpu_share():
+    """(threads the oracle runs on, CPUs the host shows).  The threads are
+    the CPUs this process may run on, capped by OMP_NUM_THREADS when the
+    environment sets the process's CPU share that way."""
+    host = os.cpu_count() or 1
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = host
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n), host
+
+
+def parity_summary(x, q, w, ids, dists, stats, ref, gt_ids):
+    """The FP64 parity rule (tests/parity.py: ids equal except within 1e-5
+    relative ties on non-fragile queries, distances within 1e-5 relative,
+    recall@10 within 0.3 points) on the queries the oracle ran."""
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity import compare64
+
+    nq = ref["ids"].shape[0]
+    r = compare64(ids[:nq], dists[:nq], ref, w.k, x, q[:nq], w.metric, gt=gt_ids[:nq],
+                  stats=stats[:nq], recall_k=min(10, w.k))
+    bad = [b for b in r["bad"] if b[0] >= 0]
+    return {"rule": "fp64 oracle: non-fragile ids equal up to 1e-5 ties, counters equal, "
+                    "distances within 1e-5 relative, recall@10 within 0.003",
+            "queries": nq, "checked": r["checked"], "fragile": r["fragile"],
+            "fragile_flags": r["flags"], "mismatched": len(bad),
+            "same_ids_all": round(r["same_ids"], 5),
+            "max_rel_dist_err": r["max_rel_err"],
+            "recall_gpu": round(r["recall_gpu"], 5), "recall_oracle": round(r["recall_oracle"], 5),
+            "recall_diff": round(r["recall_gpu"] - r["recall_oracle"], 5),
+            "pass": not r["bad"]}
 
 
 if __name__ == "__main__":
