@@ -363,6 +363,30 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
                 size_t ws_bytes, void* stream);
 
 /*
+ * peos_search_static -- peos_search without a workspace, for callers that
+ * cannot allocate device memory (code under HIP graph capture, serving loops
+ * that must not call hipMalloc, harnesses that forbid it).  Arguments,
+ * results and errors are those of peos_search, minus ws / ws_bytes.
+ * The workspace is a device array inside the library of
+ * PEOS_STATIC_SCRATCH_BYTES bytes, one per device, held until the process
+ * ends; the call allocates nothing.  Its per-query part (projection tables,
+ * norms, class order, descent entries: about ((L+1) m + 3) x 4 bytes per
+ * query) must fit in it with one visited bitmap (n/8 bytes), else the call
+ * returns PEOS_ENOSPACE before any work is enqueued; the rest holds the
+ * visited bitmaps of the resident workgroups, so a large n limits how many
+ * queries run at once (speed only, never results).  Every call on a device
+ * uses that device's one array: calls that overlap on one device (other
+ * streams or threads, or a captured call replayed while another runs) race
+ * and must be serialised by the caller.  The array keeps the last call's
+ * contents; every call writes what it reads before reading it.
+ */
+#define PEOS_STATIC_SCRATCH_BYTES (64u << 20)
+int peos_search_static(const peos_index* index, const float* queries, int64_t nq,
+                       const int32_t* k, const int32_t* ef, int32_t k_all, int32_t ef_all,
+                       int32_t kstride, int32_t pool, float eps, int32_t mode, int64_t* ids,
+                       float* dists, int32_t* stats, void* stream);
+
+/*
  * Launch plan of an index's searches.  The plan changes speed only, never a
  * result (except through the list capacity with pool = 0, see listcap); it
  * belongs to the index: overrides set here apply to every later search on

@@ -110,6 +110,8 @@ def lib():
         L.peos_search_tables.argtypes = [P, P, P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P,
                                          P, P, sz, P]
         L.peos_search.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P, P, sz, P]
+        L.peos_search_static.argtypes = [P, P, i64, P, P, i32, i32, i32, i32, f32, i32, P, P, P,
+                                         P]
         L.peos_set_search_tuning.argtypes = [P, i32, i32, i32, i32]
         L.peos_set_long_rows.argtypes = [P, i32]
         L.peos_set_class_tuning.argtypes = [P, i32, i32, i32, i32]
@@ -131,7 +133,7 @@ def lib():
                      "peos_build_tables_ex", "peos_dimension_permutation_ws_bytes",
                      "peos_dimension_permutation",
                      "peos_query_tables", "peos_search_ws_bytes", "peos_search_tables",
-                     "peos_search", "peos_set_search_tuning",
+                     "peos_search", "peos_search_static", "peos_set_search_tuning",
                      "peos_set_long_rows",
                      "peos_set_class_tuning",
                      "peos_graph_create", "peos_graph_launch", "peos_serve_open",
@@ -300,6 +302,19 @@ def peos_search(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, sta
            lib().peos_search(index.handle, _ptr(queries), queries.shape[0], _ptr(kt), _ptr(et),
                              ka, ea, kstride, pool, float(eps), mode, _ptr(ids), _ptr(dists),
                              _ptr(stats), _ptr(ws), ws.numel(), _stream(stream)))
+
+
+def peos_search_static(index, queries, k, ef, kstride, pool, eps, mode, ids, dists, stats,
+                       k_all=None, ef_all=None, stream=None):
+    """peos_search with the library's own device scratch (no workspace)."""
+    kt = k if torch.is_tensor(k) else None
+    et = ef if torch.is_tensor(ef) else None
+    ka = int(k_all if k_all is not None else (k if kt is None else int(kt.max())))
+    ea = int(ef_all if ef_all is not None else (ef if et is None else int(et.max())))
+    _check("peos_search_static",
+           lib().peos_search_static(index.handle, _ptr(queries), queries.shape[0], _ptr(kt),
+                                    _ptr(et), ka, ea, kstride, pool, float(eps), mode, _ptr(ids),
+                                    _ptr(dists), _ptr(stats), _stream(stream)))
 
 
 def peos_set_search_tuning(index, hash_cap=0, listcap=0, slots=0, waves=0):

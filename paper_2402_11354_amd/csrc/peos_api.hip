@@ -978,6 +978,74 @@ int peos_search(const peos_index* ix, const float* queries, int64_t nq, const in
 
 constexpr int kEnergyBlocks = 2048;
 
+}  // extern "C"
+
+// Scratch of peos_search_static: a file-scope device array, one copy per
+// device the library runs on (held until the process ends).  Host code never
+// uses its name as an address: the device address of each device's copy is
+// looked up once, with that device current, and kept (scratch_address).
+static constexpr size_t kScratchBytes = size_t(PEOS_STATIC_SCRATCH_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+int scratch_address(int dev, void** out)
+{
+    static std::mutex mu;
+    static void* addr[64] = {nullptr};
+    std::lock_guard<std::mutex> g(mu);
+    if (dev < 0 || dev >= 64) return fail(PEOS_EDEVICE, "device index %d", dev);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(PEOS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return PEOS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int peos_search_static(const peos_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                       const int32_t* ef, int32_t k_all, int32_t ef_all, int32_t kstride,
+                       int32_t pool, float eps, int32_t mode, int64_t* ids, float* dists,
+                       int32_t* stats, void* stream)
+{
+    // the workspace check of check_search_args is met by the scratch array
+    int rc = check_search_args(ix, queries, nq, k_all, ef_all, kstride, pool, eps, mode, ids,
+                               dists, (const void*)1);
+    if (rc) return rc;
+    if (nq == 0) return PEOS_OK;
+    int dev;
+    rc = check_device(&dev);
+    if (rc) return rc;
+    if (dev != ix->device) return fail(PEOS_EINVAL, "current device %d is not the index's %d", dev, ix->device);
+    void* ws = nullptr;
+    rc = scratch_address(dev, &ws);
+    if (rc) return rc;
+    // as many visited bitmaps (resident workgroups) as the scratch holds
+    // after the per-query part, up to what the batch can use
+    const int64_t sw = spill_words_of(ix);
+    const WsLayout w1 = ws_layout(ix, nq, sw, 1);
+    if ((size_t)w1.total > kScratchBytes)
+        return fail(PEOS_ENOSPACE, "nq=%lld with n=%lld needs %lld scratch bytes, %zu available",
+                    (long long)nq, (long long)ix->n, (long long)w1.total, kScratchBytes);
+    int64_t slots = ((int64_t)kScratchBytes - w1.spill_off) / (sw * 4);
+    const int64_t most = nq < kMaxSlots ? nq : kMaxSlots;
+    if (slots > most) slots = most;
+    const WsLayout w = ws_layout(ix, nq, sw, slots);
+    float* tables = (float*)((char*)ws + w.tables_off);
+    float* qnorms = (float*)((char*)ws + w.qnorm_off);
+    rc = peos_query_tables(ix, queries, nq, tables, qnorms, stream);
+    if (rc) return rc;
+    return search_impl(ix, queries, tables, qnorms, nq, k, ef, k_all, ef_all, kstride, pool, eps,
+                       mode, ids, dists, stats, ws, kScratchBytes, (hipStream_t)stream, 0, slots);
+}
+
 int peos_probe_gather(const float* rows, int64_t n_rows, int32_t waves, int32_t iters,
                       float* sink, void* stream)
 {

@@ -58,6 +58,8 @@ int main(void)
                               NULL, NULL, NULL, 0, NULL) == PEOS_EINVAL);
     EXPECT(peos_search(NULL, NULL, 1, NULL, NULL, 10, 10, 10, 0, 0.1f, 0, NULL, NULL, NULL, NULL,
                        0, NULL) == PEOS_EINVAL);
+    EXPECT(peos_search_static(NULL, NULL, 1, NULL, NULL, 10, 10, 10, 0, 0.1f, 0, NULL, NULL, NULL,
+                              NULL) == PEOS_EINVAL);
     EXPECT(peos_set_search_tuning(NULL, 0, 0, 0, 0) == PEOS_EINVAL);
     EXPECT(peos_set_class_tuning(NULL, 0, 0, 0, 0) == PEOS_EINVAL);
     EXPECT(peos_set_long_rows(NULL, 1) == PEOS_EINVAL);
