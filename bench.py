@@ -93,6 +93,8 @@ def main():
     ap.add_argument("--pool", default="ef")
     ap.add_argument("--eps", type=float, default=0.1)
     ap.add_argument("--hash-cap", type=int, default=0, help="with --profile-only: visited-hash capacity")
+    ap.add_argument("--exhaustive", action="store_true",
+                    help="with --profile-only: time the search with the test off")
     ap.add_argument("--slots", type=int, default=0,
                     help="with --profile-only: resident waves of the persistent grid")
     ap.add_argument("--listcap", type=int, default=0,
@@ -223,7 +225,8 @@ def main():
 
     if args.profile_only:
         P.peos_set_search_tuning(index, args.hash_cap, args.listcap, args.slots)
-        cfg = (args.ef, pool_of(args.pool, args.ef), args.eps, P.PEOS_MODE_PEOS)
+        cfg = (args.ef, pool_of(args.pool, args.ef), args.eps,
+               P.PEOS_MODE_EXHAUSTIVE if args.exhaustive else P.PEOS_MODE_PEOS)
         wall, sms, tms, srch = timed(cfg, args.steps, args.warmup)
         log(f"profile-only {cfg}: step {sms.mean():.3f} ms search {srch.mean():.3f} ms "
             f"qps {nq * args.steps / wall:.0f}")
@@ -422,6 +425,15 @@ def main():
                                            f"ef grid {args.efs}, eps {args.epss}"},
         "per_query": {"ndist": round(float(st[:, 9].mean()), 1),
                       "tests": round(float(st[:, 3].mean()), 1),
+                      "tests_by_kind": {"a_ge_1_fail": round(float(st[:, 4].mean()), 1),
+                                        "a_le_0_pass": round(float(st[:, 5].mean()), 1),
+                                        "h_vs_t": round(float(st[:, 6].mean()), 1),
+                                        "zero_edge": round(float(st[:, 7].mean()), 1)},
+                      "h_vs_t_pass_rate": round(float(
+                          (st[:, 8].sum() - st[:, 5].sum())
+                          / max(1, st[:, 6].sum())), 4),
+                      "edges": round(float(st[:, 1].mean()), 1),
+                      "visited_skips": round(float(st[:, 2].mean()), 1),
                       "expansions": round(float(st[:, 0].mean()), 1),
                       "pass_rate": round(float(st[:, 8].sum() / max(1, st[:, 3].sum())), 4),
                       "alg_bytes": round(pe_bytes / nq, 1)},
@@ -497,6 +509,15 @@ def _setup(name, n, nq, gt_k):
     _, gt_d = W.ground_truth(x, q, gt_k, w.metric, device=dev)
     log(f"ground truth in {time.time() - t0:.1f}s")
     return w, x, q, g, entry, index, gt_d
+
+
+def _interp(pts, target):
+    """QPS at exactly the target recall, linear between the two points of the
+    (recall, QPS) sweep that bracket it; None if none do."""
+    for (r0, q0), (r1, q1) in zip(pts, pts[1:]):
+        if r0 < target <= r1:
+            return round(q0 + (target - r0) / (r1 - r0) * (q1 - q0), 1)
+    return None
 
 
 def _recall(x, q, ids, gt_d, k, metric):
@@ -648,6 +669,33 @@ def precision(args):
             ok = [p_ for p_ in pts if p_["recall"] >= args.target]
             rows[label] = dict(points=pts, at_target=(max(ok, key=lambda p_: p_["qps"])
                                                       if ok else None))
+        if k == 10 and not args.prec_ef:
+            # the same sweep with the test off (exhaustive-neighbour search)
+            pts = []
+            for ef in efs:
+                autotune.tune(index, qt, k, ef, pool=ef, eps=w.eps, mode=P.PEOS_MODE_EXHAUSTIVE,
+                              caps=(0,), waves=(1, 2, 4), reps=2, use_cache=False)
+                ids, dd, st = P.search(index, qt, k, ef, mode=P.PEOS_MODE_EXHAUSTIVE, pool=ef,
+                                       ws=ws)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(args.steps):
+                    P.search(index, qt, k, ef, mode=P.PEOS_MODE_EXHAUSTIVE, pool=ef, ws=ws)
+                torch.cuda.synchronize()
+                qps = nq * args.steps / (time.perf_counter() - t0)
+                rec = float(_recall(x, q, ids.cpu().numpy(), gt_d[:, :k], k, w.metric).mean())
+                pts.append(dict(ef=ef, recall=round(rec, 4), qps=round(qps, 1),
+                                waves_per_query=index.tuned_waves,
+                                **alg_rate(st.cpu().numpy(), index.layout(), k, ef, qps)))
+                log(f"precision k={k} exhaustive ef={ef}: recall={rec:.4f} qps={qps:.0f} "
+                    f"waves/query={index.tuned_waves}")
+            ok = [p_ for p_ in pts if p_["recall"] >= args.target]
+            rows["exhaustive_fp32"] = dict(points=pts, at_target=(max(ok, key=lambda p_: p_["qps"])
+                                                                  if ok else None))
+            rows["interpolated_at_target"] = {
+                lab: _interp([(p_["recall"], p_["qps"]) for p_ in rows[lab]["points"]],
+                             args.target)
+                for lab in ("fp32", "precision", "exhaustive_fp32")}
         loss = [round(a_["recall"] - b_["recall"], 4)
                 for a_, b_ in zip(rows["fp32"]["points"], rows["precision"]["points"])]
         rows["recall_loss_at_equal_ef"] = dict(zip([str(e) for e in efs], loss))
