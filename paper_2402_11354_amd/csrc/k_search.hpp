@@ -33,6 +33,9 @@ constexpr int kFlagCompact = 8;
 // launch variant, not an index flag: long vectors at low occupancy (at most
 // two waves per SIMD, so a wave has the registers for 2 x 16 rows in flight)
 constexpr int kVariantLong = 16;
+// Fourth dword of a raw buffer resource on CDNA: data format 32 bits (a
+// resource with no data format reads zeros), no swizzle, no index stride.
+constexpr int kBufferRsrcWord3 = 0x00020000;
 constexpr int kCompactLutBins = 256;
 
 struct SearchArgs {
@@ -345,6 +348,28 @@ __device__ __forceinline__ void lead_distances(int nw, uint32_t* coop, const voi
 // REGL: the candidate list is the result list alone (capacity = ef <= 64,
 // the HNSW stopping rule): entry i lives in lane i's registers (rd, ri), so
 // the pop is a ballot and the merge a register scatter through LDS staging.
+// N consecutive dwords at byte offset off of a buffer, in loads of up to 16
+// bytes (zeros where the range ends)
+template <int N>
+__device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, int off, uint32_t* w)
+{
+    int i = 0;
+#pragma unroll
+    for (; i + 4 <= N; i += 4) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 4 * i, 0, 0);
+        w[i] = v[0]; w[i + 1] = v[1]; w[i + 2] = v[2]; w[i + 3] = v[3];
+    }
+    if constexpr (N % 4 == 3) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b96(rs, off + 4 * i, 0, 0);
+        w[i] = v[0]; w[i + 1] = v[1]; w[i + 2] = v[2];
+    } else if constexpr (N % 4 == 2) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b64(rs, off + 4 * i, 0, 0);
+        w[i] = v[0]; w[i + 1] = v[1];
+    } else if constexpr (N % 4 == 1) {
+        w[i] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * i, 0, 0);
+    }
+}
+
 template <int MAXL, int FLAGS, bool REGL>
 __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                              (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_PER_EU) void k_search(
@@ -555,48 +580,52 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                 const bool testing = (a.mode == 0 || a.mode == 2) && full;
                 st_texp += testing ? 1 : 0;
 
-                // ids, codes and scalars depend on v only: one round trip
-                int32_t u = -1;
-                float4 sc4 = make_float4(0.f, 0.f, 0.f, 0.f);
+                // ids, codes and scalars depend on v only: one round trip.
+                // Every lane issues the same loads in straight-line code, the
+                // id first, so that the visited filter waits for the id alone
+                // while the record is in flight: lanes past R read edge R-1's
+                // again, and the record is read through a buffer resource
+                // whose range is the node's record, or empty when the
+                // expansion runs no test (out-of-range buffer loads return
+                // zero without touching memory).
+                const int le = lane < R ? lane : R - 1;
+                int32_t u = a.graph[(int64_t)vid * R + le];
+                const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+                    const_cast<uint8_t*>(a.rec) + (int64_t)vid * a.node_stride, 0,
+                    testing ? a.node_stride : 0, kBufferRsrcWord3);
+                float4 sc4;
                 uint32_t cw[NCW];
-#pragma unroll
-                for (int i = 0; i < NCW; ++i) cw[i] = 0u;
                 uint32_t csc = 0u;  // compact: the two scalar codes of the edge
-                if (lane < R) {
-                    u = a.graph[(int64_t)vid * R + lane];
-                    if (testing && CP) {
-                        // node header {g_lo, g_step, i_lo, i_step}, 4 code
-                        // bytes and 2 scalar bytes of the edge
-                        const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
-                        sc4 = *reinterpret_cast<const float4*>(rv);
-                        cw[0] = reinterpret_cast<const uint32_t*>(rv + a.codes_off)[lane];
-                        csc = reinterpret_cast<const uint16_t*>(rv + a.scal_off)[lane];
-                    } else if (testing) {
-                        const uint8_t* rv = a.rec + (int64_t)vid * a.node_stride;
-                        if (H16) {
-                            // halves: g_e/|e|, 1/|e|, w_reg, sqrt(L) w_res
-                            const uint2 h = reinterpret_cast<const uint2*>(rv + a.scal_off)[lane];
-                            sc4 = make_float4((float)__builtin_bit_cast(_Float16, (uint16_t)(h.x & 0xffffu)),
-                                              (float)__builtin_bit_cast(_Float16, (uint16_t)(h.x >> 16)),
-                                              (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y & 0xffffu)),
-                                              (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y >> 16)));
-                        } else {
-                            sc4 = reinterpret_cast<const float4*>(rv + a.scal_off)[lane];
-                        }
-                        if (a.mode == 2) {
-                            // SimHash: the edge's sign bits in place of its codes
-                            const uint2 sg2 = reinterpret_cast<const uint2*>(rv + a.sig_off)[lane];
-                            cw[0] = sg2.x;
-                            if (NCW > 1) cw[1 % NCW] = sg2.y;
-                        } else {
-                            const uint32_t* cb =
-                                reinterpret_cast<const uint32_t*>(rv + a.codes_off) + lane * NCW;
+                if (CP) {
+                    // node header {g_lo, g_step, i_lo, i_step}, 4 code bytes
+                    // and 2 scalar bytes of the edge
+                    sc4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
+                    cw[0] = __builtin_amdgcn_raw_buffer_load_b32(rs, a.codes_off + 4 * le, 0, 0);
 #pragma unroll
-                            for (int i = 0; i < NCW; ++i)
-                                cw[i] = cb[i];  // zero past the codes of L
-                        }
+                    for (int i = 1; i < NCW; ++i) cw[i] = 0u;
+                    csc = __builtin_amdgcn_raw_buffer_load_b16(rs, a.scal_off + 2 * le, 0, 0);
+                } else {
+                    if (H16) {
+                        // halves: g_e/|e|, 1/|e|, w_reg, sqrt(L) w_res
+                        const uint2 h = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, a.scal_off + 8 * le, 0, 0));
+                        sc4 = make_float4((float)__builtin_bit_cast(_Float16, (uint16_t)(h.x & 0xffffu)),
+                                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h.x >> 16)),
+                                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y & 0xffffu)),
+                                          (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y >> 16)));
+                    } else {
+                        sc4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, a.scal_off + 16 * le, 0, 0));
                     }
+                    // the edge's codes, or in SimHash mode its two signature
+                    // dwords (the dwords read past them, zero or another
+                    // edge's bytes within the record, are cleared): one load
+                    // shape for both modes
+                    const bool sim = a.mode == 2;
+                    const int cb = sim ? a.sig_off + 8 * le : a.codes_off + 4 * NCW * le;
+                    load_words<NCW>(rs, cb, cw);  // zero past the codes of L
+#pragma unroll
+                    for (int i = 2; i < NCW; ++i) cw[i] = sim ? 0u : cw[i];
                 }
+                if (lane >= R) u = -1;
                 const float sg = sc4.x, se = sc4.y, sw = sc4.z, sr = sc4.w;
                 const bool valid = u >= 0;
                 lc_edges += valid ? 1 : 0;
