@@ -271,6 +271,9 @@ struct SearchPlan {
 };
 
 // per_query: k or ef given per query (then queries may have ef below efmax)
+// resident waves per CU that the search kernel's registers allow (four SIMDs)
+constexpr int64_t kSearchWavesPerCu = 4 * PEOS_SEARCH_WAVES_PER_EU;
+
 SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bool per_query,
                        int cls = -1)
 {
@@ -307,7 +310,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     // more, 1024 to 8192.  The unbounded queue (pool = 0) visits several
     // times more nodes per list entry: 32 slots per entry, from 2048, and
     // for lists up to 64 the 16-wave fit.
-    const int64_t fit = (lds_cu / 16 - kStaticLds - fixed) / 4;
+    const int64_t fit = (lds_cu / kSearchWavesPerCu - kStaticLds - fixed) / 4;
     int hc;
     if (pool != 0) {
         hc = 20 * efmax > fit ? 20 * efmax : (int)fit;
@@ -330,7 +333,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     p.lds = fixed + 4LL * hc;
     int64_t per_cu = lds_cu / (p.lds + kStaticLds);
     if (per_cu < 1) per_cu = 1;
-    if (per_cu > 16) per_cu = 16;
+    if (per_cu > kSearchWavesPerCu) per_cu = kSearchWavesPerCu;
     // long vectors (d > 512, L > 8, list in LDS): when the LDS or the batch
     // allows at most 8 waves per CU anyway, the variant with the registers
     // of two waves per SIMD keeps twice the rows in flight
@@ -341,7 +344,7 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
     // long-vector variant); when the batch leaves room, give each query 2 or
     // 4 waves (its rows gathered by all of them) as long as every query of
     // the batch is still resident at once
-    const int64_t wpc = p.long_rows ? 8 : 16;
+    const int64_t wpc = p.long_rows ? 8 : kSearchWavesPerCu;
     int waves = 1;
     if (t.waves > 0) {
         waves = t.waves;
@@ -734,7 +737,10 @@ int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, fl
     const int64_t blocks = (nq + 15) / 16;
     const size_t tile = sizeof(float) * 16 * (size_t)(ix->d + 4);
     a.staged = tile <= 64 * 1024 ? 1 : 0;
-    const size_t lds = a.staged ? tile : 0;
+    // staged rows; with m = 16 the parts of the full-space tile reuse them
+    // (at least 4 waves x 64 lanes x 4 floats)
+    const size_t parts = ix->m == 16 ? sizeof(float) * 4 * 64 * peos::kTableWaves : 0;
+    const size_t lds = a.staged ? std::max(tile, parts) : 0;
     int rc = ensure_kernel_attrs(ix->device);
     if (rc) return rc;
     hipLaunchKernelGGL(peos::k_query_table, dim3((unsigned)blocks), dim3(64 * peos::kTableWaves),
