@@ -589,7 +589,8 @@ def batched(args):
                      ndist=round(float(st[:, 9].mean()), 1),
                      expansions=round(float(st[:, 0].mean()), 1),
                      gbs=round(float(alg / (ms.mean() / 1e3) / 1e9), 1),
-                     class_hash_caps={str(c): v for c, v in caps.items()})
+                     class_hash_caps={str(c): v for c, v in caps.items()},
+                     class_waves={str(c): v for c, v in index.tuned_class_waves.items()})
             out[f"{label}_{rule}"] = r
             log(f"batched {label} {rule}: {r}")
     pe, ex = out["peos_queue_2ef"], out["exhaustive_queue_2ef"]

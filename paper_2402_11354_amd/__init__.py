@@ -33,6 +33,7 @@ PEOS_FLAG_BF16_BASE = 1
 PEOS_FLAG_FP16 = 2
 PEOS_FLAG_SIMHASH = 4
 PEOS_FLAG_COMPACT = 8
+PEOS_STAT_STATUS = 11
 PEOS_STAT_DESCENT = 12
 PEOS_STAT_TEST_EXPANSIONS = 13
 PEOS_NSTATS = 14
@@ -180,6 +181,7 @@ class PeosIndex:
         self.handle = handle
         self._keep = keep
         self.tuned_waves = 0  # waves per query the autotuner chose (0 = automatic)
+        self.tuned_class_waves = {}  # the same per ef class (autotune.tune_classes)
 
     def layout(self):
         return peos_index_layout(self)

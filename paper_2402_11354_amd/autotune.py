@@ -142,15 +142,20 @@ def ef_classes(k, ef):
     return cls
 
 
-def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS, reps=2,
-                 log=None):
-    """Pick the visited-hash capacity of every ef class of a batch with
-    per-query k and ef (host arrays), timing each class on its own queries,
-    and set it with peos_set_class_tuning.  Returns {class: hash_cap}."""
+def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS, waves=WAVES,
+                 reps=2, log=None):
+    """Pick the launch plan of every ef class of a batch with per-query k and
+    ef (host arrays), timing each class on its own queries: first the waves
+    per query (the library's automatic choice, or 1, 2, 4: a class whose
+    lists and visited hash take much LDS runs few workgroups per CU, and more
+    waves per workgroup keep more rows in flight), then the visited-hash
+    capacity at that choice; set with peos_set_class_tuning.  Returns
+    {class: hash_cap}; the chosen waves are in index.tuned_class_waves."""
     import numpy as np
     from . import peos_set_class_tuning
     cls = ef_classes(k, ef)
     chosen = {}
+    index.tuned_class_waves = {}
     dev = queries.device
     for c in np.unique(cls).tolist():
         sel = np.nonzero(cls == c)[0]
@@ -160,13 +165,13 @@ def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS,
         efmax = int(max(ef[sel].max(), k[sel].max()))
         ws = torch.empty(peos_search_ws_bytes(index, len(sel), efmax, pool), dtype=torch.uint8,
                          device=dev)
-        times = {}
-        for cap in caps:
-            peos_set_class_tuning(index, c, cap)
+
+        def timed(cap, nw):
+            peos_set_class_tuning(index, c, cap, 0, nw)
             try:
                 search(index, qs, kt, et, eps=eps, mode=mode, pool=pool, ws=ws)
             except RuntimeError:
-                continue
+                return None
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
@@ -175,13 +180,25 @@ def tune_classes(index, queries, k, ef, pool=1, eps=0.1, mode=0, caps=HASH_CAPS,
                 search(index, qs, kt, et, eps=eps, mode=mode, pool=pool, ws=ws)
             e1.record()
             torch.cuda.synchronize()
-            times[cap] = e0.elapsed_time(e1) / reps
-        best = min(times, key=times.get)
-        if 0 in times and times[best] > (1.0 - KEEP_DEFAULT) * times[0]:
-            best = 0
-        peos_set_class_tuning(index, c, best)
+            return e0.elapsed_time(e1) / reps
+
+        wtimes = {}
+        for nw in waves:
+            t = timed(0, nw)
+            if t is not None:
+                wtimes[nw] = t
+        nw = _pick(wtimes) if wtimes else 0
+        times = {}
+        for cap in caps:
+            t = timed(cap, nw)
+            if t is not None:
+                times[cap] = t
+        best = _pick(times)
+        peos_set_class_tuning(index, c, best, 0, nw)
         chosen[c] = best
+        index.tuned_class_waves[c] = nw
         if log:
-            log(f"autotune class {c} ({len(sel)} queries, ef <= {efmax}): "
+            log(f"autotune class {c} ({len(sel)} queries, ef <= {efmax}): waves "
+                + " ".join(f"{x}:{t:.3f}ms" for x, t in wtimes.items()) + f" -> {nw}; hash "
                 + " ".join(f"{cp}:{t:.3f}ms" for cp, t in times.items()) + f" -> {best}")
     return chosen

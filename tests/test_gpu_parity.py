@@ -442,19 +442,35 @@ def test_ef_classes_match_oracle_and_single_runs(angular):
         assert np.array_equal(dd.cpu().numpy(), d[sel])
 
 
-def test_ef_class_tuning_does_not_change_results(angular):
+@pytest.mark.parametrize("pool", [1, -2])
+def test_ef_class_tuning_does_not_change_results(angular, pool):
+    """Per-class visited-hash capacity, grid size and waves per query change
+    speed only: ids, distances and counters are identical."""
     case, w = angular, angular.w
     k, ef = W.query_params(w, len(case.q), seed=2)
-    base = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=1, kstride=100)
+    base = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=pool, kstride=100)
     try:
-        for c, (hc, sl) in enumerate([(512, 3), (1024, 0), (3000, 17), (8192, 5)]):
-            P.peos_set_class_tuning(case.index, c, hc, sl)
-        other = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=1, kstride=100)
+        for c, (hc, sl, nw) in enumerate([(512, 3, 2), (1024, 0, 4), (3000, 17, 1), (8192, 5, 2)]):
+            P.peos_set_class_tuning(case.index, c, hc, sl, nw)
+        other = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=pool, kstride=100)
+        for c in range(4):
+            P.peos_set_class_tuning(case.index, c, 0, 0, 4)
+        third = P.search(case.index, case.qt, T(k), T(ef), eps=w.eps, pool=pool, kstride=100)
     finally:
         for c in range(8):
             P.peos_set_class_tuning(case.index, c)
     torch.cuda.synchronize()
-    assert torch.equal(base[0], other[0]) and torch.equal(base[1], other[1])
+
+    def counters(st):
+        # every counter, and the status bits but the spill bit (which depends
+        # on the visited-hash capacity by design)
+        st = st.cpu().numpy().copy()
+        st[:, P.PEOS_STAT_STATUS] &= ~P.PEOS_STATUS_VISITED_SPILL
+        return st
+
+    for o in (other, third):
+        assert torch.equal(base[0], o[0]) and torch.equal(base[1], o[1])
+        assert np.array_equal(counters(base[2]), counters(o[2]))
 
 
 @pytest.mark.parametrize("per_query", [False, True])
