@@ -99,6 +99,8 @@ def main():
                     help="with --profile-only: resident waves of the persistent grid")
     ap.add_argument("--listcap", type=int, default=0,
                     help="with --profile-only: force an LDS list of this capacity")
+    ap.add_argument("--waves", type=int, default=0,
+                    help="with --profile-only: waves per query (0 = the library's choice)")
     ap.add_argument("--mode", default="headline",
                     choices=("headline", "batched", "serving", "precision", "compact",
                              "descent"),
@@ -224,7 +226,7 @@ def main():
         return wall, step_ms, table_ms, search_ms
 
     if args.profile_only:
-        P.peos_set_search_tuning(index, args.hash_cap, args.listcap, args.slots)
+        P.peos_set_search_tuning(index, args.hash_cap, args.listcap, args.slots, args.waves)
         cfg = (args.ef, pool_of(args.pool, args.ef), args.eps,
                P.PEOS_MODE_EXHAUSTIVE if args.exhaustive else P.PEOS_MODE_PEOS)
         wall, sms, tms, srch = timed(cfg, args.steps, args.warmup)
