@@ -57,9 +57,11 @@ struct SearchArgs {
     float* dists;
     int32_t* stats;
     uint32_t* counter;  // work counter, zero before launch
-    uint32_t* spill;    // per-slot visited bitmaps
+    uint32_t* spill;    // per slot: visited bitmap, then the list of ids set after a spill
     const int32_t* entries;  // per-query entry nodes (upper-layer descent), or null
-    int32_t spill_words;
+    int32_t spill_words;         // per-slot stride of spill
+    int32_t spill_bitmap_words;  // bitmap words (n bits, whole 16-byte blocks)
+    int32_t spill_list_cap;      // ids the list holds (0: no list)
     int32_t n, nq;      // both below 2^31
     int k_all, ef_all, kstride;
     int d, R, L, m, metric, mode, entry;
@@ -445,6 +447,13 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
     float* Ld = REGL ? reinterpret_cast<float*>(hash) : Lr;
     uint32_t* Li = REGL ? hash + kWave : reinterpret_cast<uint32_t*>(Lr) + lds_list;
     uint32_t* bitmap = a.spill + (int64_t)blockIdx.x * a.spill_words;
+    // The bitmap is cleared whole when this workgroup first spills; after
+    // that a spilled query lists the ids it sets past the hash's and clears
+    // just their words when it ends, so the next spill finds it clear (the
+    // whole clear writes n/8 bytes, which at 10M nodes costs more than the
+    // query's search).  A query that overflows the list leaves it unknown.
+    uint32_t* slist = bitmap + a.spill_bitmap_words;
+    bool bm_unknown = true;
 
     uint32_t qbegin = 0, qend = wave_uniform((uint32_t)ca.nq);
     if (ca.qperm) {
@@ -539,6 +548,7 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
             size = 1;
             int nvis = 1;
             bool spilled = false;
+            int nlist = 0;  // ids set in the bitmap after the spill
             st_ndist = 1;
             int lb = 0;  // every entry before lb is expanded
             wave_sync();
@@ -726,10 +736,12 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
 
                 // visited := visited + survivors
                 if (!spilled && nvis + ns > a.visit_limit) {
-                    for (int w = lane; w < (a.spill_words >> 2); w += kWave)
-                        reinterpret_cast<uint4*>(bitmap)[w] = make_uint4(0u, 0u, 0u, 0u);
-                    __threadfence();
-                    wave_sync();
+                    if (bm_unknown) {
+                        for (int w = lane; w < (a.spill_bitmap_words >> 2); w += kWave)
+                            reinterpret_cast<uint4*>(bitmap)[w] = make_uint4(0u, 0u, 0u, 0u);
+                        __threadfence();
+                        wave_sync();
+                    }
                     for (int t = lane; t < hcap; t += kWave) {
                         const uint32_t k = hash[t];
                         if (k != kEmpty) atomicOr(bitmap + (k >> 5), 1u << (k & 31u));
@@ -737,13 +749,21 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                     __threadfence();
                     wave_sync();
                     spilled = true;
+                    bm_unknown = true;
+                    nlist = 0;
                     status |= kStatusSpill;
                 }
                 if (pass) {
-                    if (spilled) atomicOr(bitmap + ((uint32_t)u >> 5), 1u << ((uint32_t)u & 31u));
-                    else hash_insert(hash, (uint32_t)hcap, (uint32_t)u);
-                    Su[popc(smask & lanemask_lt())] = (uint32_t)u;
+                    const int t = popc(smask & lanemask_lt());
+                    if (spilled) {
+                        atomicOr(bitmap + ((uint32_t)u >> 5), 1u << ((uint32_t)u & 31u));
+                        if (nlist + t < a.spill_list_cap) slist[nlist + t] = (uint32_t)u;
+                    } else {
+                        hash_insert(hash, (uint32_t)hcap, (uint32_t)u);
+                    }
+                    Su[t] = (uint32_t)u;
                 }
+                if (spilled) nlist += ns;
                 nvis += ns;
                 wave_sync();
                 lead_distances<BF, (MAXL >= 16) && BF, LONG>(nw, coop, tbase, d, Su, ns, qv, a.metric,
@@ -882,6 +902,19 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                 lb = lb < efq ? lb : efq;
                 lb = lb < minpos ? lb : minpos;
                 wave_sync();
+            }
+            if (spilled && nlist <= a.spill_list_cap) {
+                // clear the words this query set: the ids the hash held at
+                // the spill (it is unchanged since), then the listed ones
+                __threadfence();  // the list's stores, before it is read back
+                for (int t = lane; t < hcap; t += kWave) {
+                    const uint32_t k = hash[t];
+                    if (k != kEmpty) bitmap[k >> 5] = 0u;
+                }
+                for (int i = lane; i < nlist; i += kWave) bitmap[slist[i] >> 5] = 0u;
+                __threadfence();
+                wave_sync();
+                bm_unknown = false;
             }
             if (REGL) {
                 // the list to LDS for the output (and the re-rank)

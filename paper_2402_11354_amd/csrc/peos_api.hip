@@ -258,7 +258,12 @@ int ensure_kernel_attrs(int dev)
 
 // words of one visited bitmap: n bits, a whole number of 16-byte blocks (so
 // a slot's bitmap is cleared with 16-byte stores)
-int64_t spill_words_of(const peos_index* ix) { return round_up((ix->n + 31) / 32, 4); }
+// per-slot spill region: the visited bitmap (n bits in whole 16-byte
+// blocks), then, from n = 2^19 on, a list of 4,096 ids that lets a spilled
+// query clear just the words it set (below that a whole clear is cheap)
+int64_t spill_bitmap_words_of(const peos_index* ix) { return round_up((ix->n + 31) / 32, 4); }
+int64_t spill_list_cap_of(const peos_index* ix) { return spill_bitmap_words_of(ix) >= 16384 ? 4096 : 0; }
+int64_t spill_words_of(const peos_index* ix) { return spill_bitmap_words_of(ix) + spill_list_cap_of(ix); }
 
 struct SearchPlan {
     bool list_in_lds;  // a list capacity was forced: keep the list in LDS
@@ -775,6 +780,8 @@ static int launch_search(const peos_index* ix, const peos::SearchArgs& base_args
     peos::SearchArgs a = base_args;
     a.counter = const_cast<uint32_t*>(counter);
     a.spill_words = (int32_t)plan.spill_words;
+    a.spill_bitmap_words = (int32_t)spill_bitmap_words_of(ix);
+    a.spill_list_cap = (int32_t)spill_list_cap_of(ix);
     a.listcap = plan.listcap;
     a.listslack = plan.listslack;
     a.hcap = plan.hcap;
@@ -856,6 +863,8 @@ static int search_impl(const peos_index* ix, const float* queries, const float* 
     a.counter = nullptr;
     a.spill = (uint32_t*)((char*)ws + w.spill_off);
     a.spill_words = 0;
+    a.spill_bitmap_words = 0;
+    a.spill_list_cap = 0;
     a.n = (int32_t)ix->n;
     a.nq = (int32_t)nq;
     a.k_all = k_all;

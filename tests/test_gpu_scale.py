@@ -138,3 +138,37 @@ def test_fullsize_search(full, name, ef, pool, eps, mode):
     print(f"[gpu] {name}: tie-aware recall@10 gpu={r_gpu:.4f} oracle={r_orc:.4f} "
           f"(all queries {recall_at_k(full.x, full.q, ids, full.gt_d, w.k, w.metric).mean():.4f})")
     assert abs(r_gpu - r_orc) <= 0.003 + 1e-12
+
+
+def test_fullsize_spilled_visited_sets(full):
+    """With a visited hash far too small nearly every query moves its visited
+    set to the HBM bitmap.  With 16 resident workgroups each runs about 125
+    queries in turn: a spilled query clears the bitmap words it set, so the
+    next spill by that workgroup finds the bitmap clear, and a query that
+    sets more than the cleanup list holds (the unbounded queue at ef = 256)
+    leaves it to be cleared whole.  Ids, distances and counters equal those
+    of the run whose hash does not spill (the status bit aside)."""
+    w = full.w
+    nq = 2000
+    q = full.qt[:nq]
+
+    def run(hash_cap, slots, ef, pool):
+        P.peos_set_search_tuning(full.index, hash_cap, 0, slots)
+        try:
+            ids, d, st = P.search(full.index, q, w.k, ef, eps=0.2, pool=pool)
+            torch.cuda.synchronize()
+        finally:
+            P.peos_set_search_tuning(full.index)
+        return ids.cpu().numpy(), d.cpu().numpy(), st.cpu().numpy()
+
+    for ef, pool in ((64, 64), (256, 0)):
+        print(f"[gpu] spilled visited sets: ef={ef} pool={pool}", flush=True)
+        a = run(8192, 0, ef, pool)
+        b = run(256, 16, ef, pool)
+        spill = P.PEOS_STATUS_VISITED_SPILL
+        assert (b[2][:, P.PEOS_STAT_STATUS] & spill != 0).mean() > 0.95
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        sa, sb = a[2].copy(), b[2].copy()
+        sa[:, P.PEOS_STAT_STATUS] &= ~spill
+        sb[:, P.PEOS_STAT_STATUS] &= ~spill
+        assert np.array_equal(sa, sb)
