@@ -14,11 +14,11 @@
 // Per expansion of v (delta read once, before the neighbours are tested):
 //   lane j < R loads neighbour id j of v and, when R is full and the test is
 //   on, edge j's L+1 code bytes and four scalars (all three loads depend on v
-//   only, so they are issued together); visited filter; routing test of step
-//   (6); survivors are marked visited and their vectors gathered by groups of
-//   lanes (64/ns... lanes per vector, so every survivor's load is in flight at
-//   once); survivors closer than delta (or all, while R is not full) are
-//   merged into the list.
+//   only, so they are issued together, the id first); visited filter;
+//   routing test of step (6); survivors are marked visited and their vectors
+//   gathered by groups of lanes (64/ns... lanes per vector, so every
+//   survivor's load is in flight at once); survivors closer than delta (or
+//   all, while R is not full) are merged into the list.
 #pragma once
 
 #include "peos_device.hpp"
@@ -347,9 +347,6 @@ __device__ __forceinline__ void lead_distances(int nw, uint32_t* coop, const voi
     __syncthreads();  // every wave's distances are in Sdist
 }
 
-// REGL: the candidate list is the result list alone (capacity = ef <= 64,
-// the HNSW stopping rule): entry i lives in lane i's registers (rd, ri), so
-// the pop is a ballot and the merge a register scatter through LDS staging.
 // N consecutive dwords at byte offset off of a buffer, in loads of up to 16
 // bytes (zeros where the range ends)
 template <int N>
@@ -372,6 +369,9 @@ __device__ __forceinline__ void load_words(__amdgpu_buffer_rsrc_t rs, int off, u
     }
 }
 
+// REGL: the candidate list is the result list alone (capacity = ef <= 64,
+// the HNSW stopping rule): entry i lives in lane i's registers (rd, ri), so
+// the pop is a ballot and the merge a register scatter through LDS staging.
 template <int MAXL, int FLAGS, bool REGL>
 __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                              (FLAGS & kVariantLong) ? 2 : PEOS_SEARCH_WAVES_PER_EU) void k_search(
@@ -617,13 +617,15 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                 } else {
                     if (H16) {
                         // halves: g_e/|e|, 1/|e|, w_reg, sqrt(L) w_res
-                        const uint2 h = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, a.scal_off + 8 * le, 0, 0));
+                        const uint2 h = __builtin_bit_cast(
+                            uint2, __builtin_amdgcn_raw_buffer_load_b64(rs, a.scal_off + 8 * le, 0, 0));
                         sc4 = make_float4((float)__builtin_bit_cast(_Float16, (uint16_t)(h.x & 0xffffu)),
                                           (float)__builtin_bit_cast(_Float16, (uint16_t)(h.x >> 16)),
                                           (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y & 0xffffu)),
                                           (float)__builtin_bit_cast(_Float16, (uint16_t)(h.y >> 16)));
                     } else {
-                        sc4 = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rs, a.scal_off + 16 * le, 0, 0));
+                        sc4 = __builtin_bit_cast(
+                            float4, __builtin_amdgcn_raw_buffer_load_b128(rs, a.scal_off + 16 * le, 0, 0));
                     }
                     // the edge's codes, or in SimHash mode its two signature
                     // dwords (the dwords read past them, zero or another
