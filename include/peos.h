@@ -181,8 +181,9 @@ int peos_index_bytes(int64_t n, int32_t d, int32_t R, int32_t L, int32_t m, int3
  *   graph   n x R int32 neighbour ids, -1 = no edge; ids in [0, n), no self
  *           loops and no repeated id within a row.
  *   entry   entry node v0 of the search (Alg. 1), in [0, n).
- *   dirs_a  L x m x (d/L) float: vectors a^i_j of subspace i (step (2)).
- *   dirs_b  m x d float: full-space vectors b_j (step (2)).
+ *   dirs_a  L x m x (d/L) float: vectors a^i_j of subspace i (step (2)),
+ *           16-byte aligned (the projection table reads them as float4).
+ *   dirs_b  m x d float: full-space vectors b_j (step (2)), 16-byte aligned.
  *   metric  PEOS_METRIC_*.
  *   index_mem / index_bytes  caller buffer sized by peos_index_bytes, 16-byte aligned.
  *   ws / ws_bytes            build workspace (peos_index_bytes).

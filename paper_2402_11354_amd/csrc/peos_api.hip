@@ -562,8 +562,9 @@ int peos_build_tables_ex(const float* base, int64_t n, int32_t d, const int32_t*
     if (rc) return rc;
     if (!base || !graph || !dirs_a || !dirs_b || !index_mem || !ws)
         return fail(PEOS_EINVAL, "null device pointer");
-    if (((uintptr_t)base & 15u) != 0 || ((uintptr_t)index_mem & 15u) != 0)
-        return fail(PEOS_EINVAL, "base and index_mem must be 16-byte aligned");
+    if (((uintptr_t)base & 15u) != 0 || ((uintptr_t)index_mem & 15u) != 0 ||
+        ((uintptr_t)dirs_a & 15u) != 0 || ((uintptr_t)dirs_b & 15u) != 0)
+        return fail(PEOS_EINVAL, "base, dirs_a, dirs_b and index_mem must be 16-byte aligned");
     if (entry < 0 || entry >= n) return fail(PEOS_EINVAL, "entry=%d out of range", entry);
     if (metric != PEOS_METRIC_L2 && metric != PEOS_METRIC_ANGULAR && metric != PEOS_METRIC_IP)
         return fail(PEOS_EINVAL, "metric=%d", metric);
