@@ -171,6 +171,31 @@ def test_query_tables_ragged_tail(tiny):
         np.testing.assert_allclose(tables.cpu().numpy(), ref, rtol=0, atol=2e-5)
 
 
+@pytest.mark.parametrize("d,L,m", [(100, 5, 32), (36, 3, 16), (1104, 4, 16), (128, 8, 128)])
+def test_query_tables_odd_shapes(d, L, m):
+    """Shapes off the workloads' path: K not a multiple of 16 (the last
+    coordinates step by step), subspaces shorter than 16, m > 16 (whole
+    tiles dealt out, no split), m = 128, and rows too long to stage in LDS
+    (read from global memory).  37 queries: a ragged last tile."""
+    rng = np.random.default_rng(d + L + m)
+    n, R, nq = 64, 8, 37
+    x = rng.standard_normal((n, d)).astype(np.float32)
+    g = ((np.arange(n)[:, None] + 1 + np.arange(R)[None, :]) % n).astype(np.int32)
+    A = rng.standard_normal((L, m, d // L)).astype(np.float32)
+    B = rng.standard_normal((m, d)).astype(np.float32)
+    q = rng.standard_normal((nq, d)).astype(np.float32)
+    ix = P.peos_build_tables(T(x), T(g), 0, L, m, T(A), T(B), P.PEOS_METRIC_L2)
+    tables = torch.full((nq, L + 1, m), np.nan, dtype=torch.float32, device=dev())
+    norms = torch.empty(nq, dtype=torch.float32, device=dev())
+    P.peos_query_tables(ix, T(q), tables, norms)
+    torch.cuda.synchronize()
+    ref = np.stack([O.query_table(q[i], L, m, A, B) for i in range(nq)])
+    np.testing.assert_allclose(tables.cpu().numpy(), ref, rtol=0, atol=2e-5)
+    np.testing.assert_allclose(norms.cpu().numpy(), np.linalg.norm(q.astype(np.float64), axis=1),
+                               rtol=2e-6)
+    ix.close()
+
+
 # ---------------------------------------------------------------------------
 # Alg. 1 + Alg. 2: search
 # ---------------------------------------------------------------------------
