@@ -117,6 +117,8 @@ def main():
                     help="compact mode: subspaces of the compact records (1..4)")
     ap.add_argument("--no-long-rows", action="store_true",
                     help="forbid the long-vector search variant (for comparisons)")
+    ap.add_argument("--prec-workload", default="gist_like_1m_d960",
+                    help="precision mode: the workload (the 960-d one by default)")
     ap.add_argument("--prec-ef", type=int, default=0,
                     help="precision mode: time only k = 10 at this ef (for profiler runs)")
     ap.add_argument("--gather-probe", action="store_true",
@@ -622,7 +624,7 @@ def precision(args):
     import workloads as W
     from paper_2402_11354_amd import autotune
 
-    name = args.workload if args.workload != "sift_like_1m_d128" else "gist_like_1m_d960"
+    name = args.prec_workload
     w, x, q, g, entry, index, gt_d = _setup(name, args.n, args.nq, 100)
     if args.no_long_rows:
         P.peos_set_long_rows(index, False)
