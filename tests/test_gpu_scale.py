@@ -167,6 +167,10 @@ def test_fullsize_spilled_visited_sets(full):
         b = run(256, 16, ef, pool)
         spill = P.PEOS_STATUS_VISITED_SPILL
         assert (b[2][:, P.PEOS_STAT_STATUS] & spill != 0).mean() > 0.95
+        if pool == 0:
+            # some queries set more bitmap bits after their spill than the
+            # cleanup list holds (4,096 ids past the 224 the hash held)
+            assert (b[2][:, 9] > 4096 + 256).any()
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
         sa, sb = a[2].copy(), b[2].copy()
         sa[:, P.PEOS_STAT_STATUS] &= ~spill
