@@ -302,7 +302,11 @@ int peos_query_tables(const peos_index* index, const float* queries, int64_t nq,
 /*
  * peos_search_ws_bytes -- workspace of peos_search / peos_search_tables for
  * nq queries with list sizes up to efmax and candidate-pool capacity `pool`
- * (as in peos_search).  Output *ws_bytes (host).  Errors: PEOS_EINVAL.
+ * (as in peos_search): per query the projection table, norm, class order and
+ * descent entry, and per resident workgroup (at most min(nq, 4096)) a spill
+ * region for queries whose visited set outgrows the LDS hash (a bitmap of n
+ * bits and, from n = 2^19 on, a list of 4,096 ids).  Output *ws_bytes
+ * (host).  Errors: PEOS_EINVAL.
  */
 int peos_search_ws_bytes(const peos_index* index, int64_t nq, int32_t efmax, int32_t pool,
                          size_t* ws_bytes);
@@ -372,10 +376,12 @@ int peos_search(const peos_index* index, const float* queries, int64_t nq, const
  * PEOS_STATIC_SCRATCH_BYTES bytes, one per device, held until the process
  * ends; the call allocates nothing.  Its per-query part (projection tables,
  * norms, class order, descent entries: about ((L+1) m + 3) x 4 bytes per
- * query) must fit in it with one visited bitmap (n/8 bytes), else the call
- * returns PEOS_ENOSPACE before any work is enqueued; the rest holds the
- * visited bitmaps of the resident workgroups, so a large n limits how many
- * queries run at once (speed only, never results).  Every call on a device
+ * query) must fit in it with one workgroup's spill region (the visited
+ * bitmap, n/8 bytes, and from n = 2^19 on a 16 KB list of the ids a spilled
+ * query set), else the call returns PEOS_ENOSPACE before any work is
+ * enqueued; the rest holds the spill regions of the resident workgroups,
+ * so a large n limits how many queries run at once (speed only, never
+ * results).  Every call on a device
  * uses that device's one array: calls that overlap on one device (other
  * streams or threads, or a captured call replayed while another runs) race
  * and must be serialised by the caller.  The array keeps the last call's
