@@ -350,6 +350,26 @@ def test_large_list(which, request):
                label=f"{which} ef=256 unbounded queue")
 
 
+def test_bf16_traversal_is_exact_on_integer_data(sift):
+    """The integer-valued workload's coordinates (0..255) are bfloat16
+    values, so the bfloat16 traversal copy computes the same distances as the
+    fp32 rows: with fp32 scalars and tables the precision index's ids,
+    distances and counters equal the full-precision index's, for both
+    stopping rules."""
+    w = sift.w
+    ix = P.peos_build_tables(sift.xt, sift.gt, sift.entry, w.L, w.m, sift.At, sift.Bt, w.metric,
+                             flags=P.PEOS_FLAG_BF16_BASE)
+    try:
+        for ef, pool in ((64, 64), (32, 0)):
+            a = P.search(sift.index, sift.qt, w.k, ef, eps=0.2, pool=pool)
+            b = P.search(ix, sift.qt, w.k, ef, eps=0.2, pool=pool)
+            torch.cuda.synchronize()
+            for u, v in zip(a, b):
+                assert torch.equal(u, v)
+    finally:
+        ix.close()
+
+
 @pytest.mark.parametrize("which", ["tiny", "angular", "sift"])
 @pytest.mark.parametrize("pool_mul", [0, 1])
 def test_waves_per_query_change_nothing(which, pool_mul, request):
