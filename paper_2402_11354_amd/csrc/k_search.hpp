@@ -741,15 +741,13 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
                     if (bm_unknown) {
                         for (int w = lane; w < (a.spill_bitmap_words >> 2); w += kWave)
                             reinterpret_cast<uint4*>(bitmap)[w] = make_uint4(0u, 0u, 0u, 0u);
-                        __threadfence();
-                        wave_sync();
+                        wave_mem_order();
                     }
                     for (int t = lane; t < hcap; t += kWave) {
                         const uint32_t k = hash[t];
                         if (k != kEmpty) atomicOr(bitmap + (k >> 5), 1u << (k & 31u));
                     }
-                    __threadfence();
-                    wave_sync();
+                    wave_mem_order();
                     spilled = true;
                     bm_unknown = true;
                     nlist = 0;
@@ -908,14 +906,13 @@ __global__ __launch_bounds__(kMaxWavesPerQuery * 64,
             if (spilled && nlist <= a.spill_list_cap) {
                 // clear the words this query set: the ids the hash held at
                 // the spill (it is unchanged since), then the listed ones
-                __threadfence();  // the list's stores, before it is read back
+                wave_mem_order();  // the list's stores, before it is read back
                 for (int t = lane; t < hcap; t += kWave) {
                     const uint32_t k = hash[t];
                     if (k != kEmpty) bitmap[k >> 5] = 0u;
                 }
                 for (int i = lane; i < nlist; i += kWave) bitmap[slist[i] >> 5] = 0u;
-                __threadfence();
-                wave_sync();
+                wave_mem_order();
                 bm_unknown = false;
             }
             if (REGL) {

@@ -309,24 +309,24 @@ SearchPlan plan_search(const peos_index* ix, int64_t nq, int efmax, int pool, bo
                           (p.regl ? 0 : 8LL * (lc + p.listslack)) + 4LL * 2 * 64;
     // visited hash.  A query that fills 7/8 of it moves to the HBM bitmap,
     // where every visited test is a memory round trip on its chain.  With a
-    // bounded list: about 26 slots per list entry (on the measured graphs
-    // the visited sets of 99% of the queries then stay in LDS: at ef = 72 and
-    // 96 the default of 20 slots per entry spilled 27% and 41% of the
-    // queries and searched 11% and 19% slower), but no more than lets the
-    // batch's queries share the CUs (ceil(nq / CUs) of them, at most 11 per
-    // CU: past that residency matters more than the odd spill), and at least
-    // what fits the LDS share of the 16 waves per CU the kernel's registers
-    // allow; 1024 to 8192.  The unbounded queue (pool = 0) visits several
-    // times more nodes per list entry: 32 slots per entry, from 2048, and
-    // for lists up to 64 the 16-wave fit.
+    // bounded list: 20 slots per list entry (on the 1M SIFT-like graph a
+    // quarter to two fifths of the queries then spill at ef = 72 to 128, and
+    // that beats a hash large enough to keep them all, which costs resident
+    // waves: 26 slots per entry searched 5-9% slower), but no more than lets
+    // the batch's queries share the CUs (ceil(nq / CUs) of them, at most 11
+    // per CU: a small batch at a large ef keeps every query resident), and at
+    // least what fits the LDS share of the 16 waves per CU the kernel's
+    // registers allow; 1024 to 8192.  The unbounded queue (pool = 0) visits
+    // several times more nodes per list entry: 32 slots per entry, from 2048,
+    // and for lists up to 64 the 16-wave fit.
     const int64_t fit = (lds_cu / kSearchWavesPerCu - kStaticLds - fixed) / 4;
     int hc;
     if (pool != 0) {
         int64_t q_cu = (nq + ncu - 1) / ncu;
         q_cu = q_cu < 1 ? 1 : (q_cu > 11 ? 11 : q_cu);
         const int64_t share = (lds_cu / q_cu - kStaticLds - fixed) / 4;
-        int64_t want = round_up(26LL * efmax, 256);
-        if (want > share) want = share / 256 * 256;
+        int64_t want = 20LL * efmax;
+        if (want > share) want = share;
         hc = (int)(want > fit ? want : fit);
     } else {
         hc = 2048;

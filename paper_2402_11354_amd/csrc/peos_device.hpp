@@ -25,6 +25,18 @@ __device__ __forceinline__ void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Ordering point for one wave's own global-memory accesses (the visited
+// bitmap and its cleanup list, which only the wave that searches the query
+// touches).  A wave's accesses to one address reach memory in issue order,
+// so no cache write-back or invalidation is needed (an agent-scope fence
+// would write back the whole L2 of the XCD, at every spill); this keeps the
+// compiler from moving accesses across it and orders the wave's lanes.
+__device__ __forceinline__ void wave_mem_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // lanes below this one
 __device__ __forceinline__ uint64_t lanemask_lt()
 {
