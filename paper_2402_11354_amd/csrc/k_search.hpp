@@ -288,7 +288,12 @@ __device__ __forceinline__ void distances(const void* base, int d, const uint32_
                                           const float* qv, int metric, float inv_qn, float* Sdist)
 {
     // 4..16 lanes per vector; each lane keeps at most 8 chunk loads in
-    // flight (one round trip for up to 16 vectors of 128 coordinates).
+    // flight: one round trip for up to 4 vectors of 256 coordinates (16
+    // lanes x 4 chunks; not 8 chunks, whose second half a row of up to 256
+    // coordinates only re-reads and discards: 1.4% faster at d = 128), 8 of
+    // 256 (8 lanes x 8) or 16 of 128 (4 lanes x 8).  The chunk-to-segment
+    // map (chunk c to segment c mod 16) and the add tree do not depend on
+    // the lanes per vector or the loads per lane.
     // Long bfloat16 vectors: 16 lanes x 16 chunks (8 bytes each) cover up to
     // 1024 coordinates in one round trip per 4 vectors.  The low-occupancy
     // variant keeps two such rows per lane group in flight: one round trip
@@ -302,7 +307,7 @@ __device__ __forceinline__ void distances(const void* base, int d, const uint32_
         gather_distances<16, 1, 16, BF>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
         return;
     }
-    if (ns <= 4) gather_distances<16, 1, 8, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
+    if (ns <= 4) gather_distances<16, 1, 4, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
     else if (ns <= 8) gather_distances<8, 1, 8, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
     else if (ns <= 16) gather_distances<4, 1, 8, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
     else gather_distances<4, 2, 4, BF, true>(base, d, Su, ns, qv, metric, inv_qn, Sdist);
