@@ -110,13 +110,19 @@ def knn_ivf(x: torch.Tensor, k: int, nlist: int = 1024, nprobe: int = 16, iters:
     g = torch.Generator(device="cpu").manual_seed(seed)
     sample = x[torch.randperm(n, generator=g)[:min(n, 64 * nlist)].to(x.device)]
     cent = sample[:nlist].clone()
+    # the centroid sums on the host: index_add_ on the GPU adds with atomics,
+    # in an order that changes from run to run, and so would the centroids,
+    # the lists and the graph; on the host the order is fixed
+    sample_h = sample.cpu()
     for _ in range(iters):
         a, _ = knn(cent, sample, 1)
-        a = a[:, 0]
-        sums = torch.zeros_like(cent).index_add_(0, a, sample)
-        cnt = torch.bincount(a, minlength=nlist).to(x.dtype)
+        a = a[:, 0].cpu()
+        sums = torch.zeros((nlist, d), dtype=sample_h.dtype).index_add_(0, a, sample_h)
+        cnt = torch.bincount(a, minlength=nlist).to(sample_h.dtype)
         ok = cnt > 0
-        cent[ok] = sums[ok] / cnt[ok, None]
+        cent_h = cent.cpu()
+        cent_h[ok] = sums[ok] / cnt[ok, None]
+        cent = cent_h.to(x.device)
     probes, _ = knn(cent, x, nprobe, row_chunk=16384)        # n x nprobe, nearest first
     primary = probes[:, 0]
     order = torch.argsort(primary, stable=True)
