@@ -117,8 +117,9 @@ def knn_ivf(x: torch.Tensor, k: int, nlist: int = 1024, nprobe: int = 16, iters:
     for _ in range(iters):
         a, _ = knn(cent, sample, 1)
         a = a[:, 0].cpu()
-        sums = torch.zeros((nlist, d), dtype=sample_h.dtype).index_add_(0, a, sample_h)
-        cnt = torch.bincount(a, minlength=nlist).to(sample_h.dtype)
+        nc = cent.shape[0]  # nlist, or fewer for a sample smaller than that
+        sums = torch.zeros((nc, d), dtype=sample_h.dtype).index_add_(0, a, sample_h)
+        cnt = torch.bincount(a, minlength=nc).to(sample_h.dtype)
         ok = cnt > 0
         cent_h = cent.cpu()
         cent_h[ok] = sums[ok] / cnt[ok, None]
