@@ -171,12 +171,16 @@ def test_query_tables_ragged_tail(tiny):
         np.testing.assert_allclose(tables.cpu().numpy(), ref, rtol=0, atol=2e-5)
 
 
-@pytest.mark.parametrize("d,L,m", [(100, 5, 32), (36, 3, 16), (1104, 4, 16), (128, 8, 128)])
+@pytest.mark.parametrize("d,L,m", [(100, 5, 32), (36, 3, 16), (1104, 4, 16), (128, 8, 128),
+                                   (128, 32, 16), (640, 20, 16), (32, 2, 16), (64, 4, 16)])
 def test_query_tables_odd_shapes(d, L, m):
     """Shapes off the workloads' path: K not a multiple of 16 (the last
     coordinates step by step), subspaces shorter than 16, m > 16 (whole
-    tiles dealt out, no split), m = 128, and rows too long to stage in LDS
-    (read from global memory).  37 queries: a ragged last tile."""
+    tiles dealt out, no split), m = 128, rows too long to stage in LDS (read
+    from global memory), more than four subspace tiles per wave (L = 20, 32),
+    waves with no full-space group or no tile (L = 2), and the one-round-trip
+    form with one group per wave (d = 64, L = 4).  37 queries: a ragged last
+    tile."""
     rng = np.random.default_rng(d + L + m)
     n, R, nq = 64, 8, 37
     x = rng.standard_normal((n, d)).astype(np.float32)
