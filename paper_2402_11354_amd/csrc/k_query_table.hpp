@@ -122,7 +122,8 @@ __device__ __forceinline__ void one_round(floatx4& part, floatx4 (&acc)[4], cons
 
 // m = 16, staged rows, no permutation (every workload's shape), a body of
 // its own in which every wave takes the norms itself (no barrier between
-// the norms and the products) and no load waits behind another's wait.
+// the norms and the products) and the loads of each round trip are issued
+// together as straight-line code.
 // The full-space tile (K = d, L times a subspace tile's K) is split over the
 // waves, four K groups per round trip, and the parts summed at the end in
 // the order (p0 + p1) + (p2 + p3); the subspace tiles go round robin (tile
