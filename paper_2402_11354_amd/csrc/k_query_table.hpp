@@ -84,21 +84,21 @@ __device__ __forceinline__ floatx4 mfma_groups(floatx4 acc, const float* av, con
 
 // One round trip for a wave's whole work when it is at most 4 full-space
 // groups (N of them, from group g0) and at most 4 subspace tiles of exactly
-// one group each (d / L = 16): every load first, then the MFMAs in each
-// accumulator's order.
-template <int N>
+// one group each (d / L = 16; T tile slots, at least the wave's tiles): every
+// load first, then the MFMAs in each accumulator's order.
+template <int N, int T>
 __device__ __forceinline__ void one_round(floatx4& part, floatx4 (&acc)[4], const float* ql,
                                           const float* brow, int g0, const float* const (&at)[4],
                                           const float* const (&bt)[4], int k4)
 {
-    float4 bq[N > 0 ? N : 1], aq[N > 0 ? N : 1], tb[4], ta[4];
+    float4 bq[N > 0 ? N : 1], aq[N > 0 ? N : 1], tb[T], ta[T];
 #pragma unroll
     for (int u = 0; u < N; ++u) {
         bq[u] = *reinterpret_cast<const float4*>(brow + 16 * (g0 + u) + k4);
         aq[u] = *reinterpret_cast<const float4*>(ql + 16 * (g0 + u) + k4);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < T; ++u) {
         tb[u] = *reinterpret_cast<const float4*>(bt[u] + k4);
         ta[u] = *reinterpret_cast<const float4*>(at[u] + k4);
     }
@@ -110,13 +110,27 @@ __device__ __forceinline__ void one_round(floatx4& part, floatx4 (&acc)[4], cons
         part = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[u].w, bq[u].w, part, 0, 0, 0);
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < T; ++u) {
         floatx4 c = {0.f, 0.f, 0.f, 0.f};
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(ta[u].x, tb[u].x, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(ta[u].y, tb[u].y, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(ta[u].z, tb[u].z, c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(ta[u].w, tb[u].w, c, 0, 0, 0);
         acc[u] = c;
+    }
+}
+
+template <int T>
+__device__ __forceinline__ void one_round_n(int n0, floatx4& part, floatx4 (&acc)[4], const float* ql,
+                                            const float* brow, int g0, const float* const (&at)[4],
+                                            const float* const (&bt)[4], int k4)
+{
+    switch (n0) {
+    case 4: one_round<4, T>(part, acc, ql, brow, g0, at, bt, k4); break;
+    case 3: one_round<3, T>(part, acc, ql, brow, g0, at, bt, k4); break;
+    case 2: one_round<2, T>(part, acc, ql, brow, g0, at, bt, k4); break;
+    case 1: one_round<1, T>(part, acc, ql, brow, g0, at, bt, k4); break;
+    default: one_round<0, T>(part, acc, ql, brow, g0, at, bt, k4); break;
     }
 }
 
@@ -172,13 +186,9 @@ __device__ __forceinline__ void query_table16(const QueryTableArgs& a, float* qs
     const bool single = dp == 16 && n0 <= 4 && ntw >= 1 && ntw <= 4;
     if (single) {
         tile_ptrs(0, at, bt);
-        switch (n0) {
-        case 4: one_round<4>(part, acc, ql, brow, g0, at, bt, 4 * kq); break;
-        case 3: one_round<3>(part, acc, ql, brow, g0, at, bt, 4 * kq); break;
-        case 2: one_round<2>(part, acc, ql, brow, g0, at, bt, 4 * kq); break;
-        case 1: one_round<1>(part, acc, ql, brow, g0, at, bt, 4 * kq); break;
-        default: one_round<0>(part, acc, ql, brow, g0, at, bt, 4 * kq); break;
-        }
+        if (ntw == 1) one_round_n<1>(n0, part, acc, ql, brow, g0, at, bt, 4 * kq);
+        else if (ntw == 2) one_round_n<2>(n0, part, acc, ql, brow, g0, at, bt, 4 * kq);
+        else one_round_n<4>(n0, part, acc, ql, brow, g0, at, bt, 4 * kq);
     } else {
         int j = g0;
         for (; j + 4 <= g1; j += 4) part = mfma_groups<4>(part, ql, brow, j, 4 * kq);
