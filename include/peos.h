@@ -294,7 +294,8 @@ int peos_set_upper_layers(peos_index* index, const peos_upper_layers* layers);
  *            PEOS_FLAG_FP16.
  *   qnorms   out, nq float: |q| (0 for a zero query, whose table is 0).
  * Runs the dense query-by-direction product on the matrix cores.
- * Errors: PEOS_EINVAL (null pointer with nq > 0, nq < 0), PEOS_EHIP.
+ * Errors: PEOS_EINVAL (null pointer with nq > 0, nq < 0, queries not 16-byte
+ * aligned), PEOS_EHIP.
  */
 int peos_query_tables(const peos_index* index, const float* queries, int64_t nq, float* tables,
                       float* qnorms, void* stream);

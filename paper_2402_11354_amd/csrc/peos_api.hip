@@ -737,6 +737,7 @@ int peos_query_tables(const peos_index* ix, const float* queries, int64_t nq, fl
     if (nq < 0) return fail(PEOS_EINVAL, "nq=%lld", (long long)nq);
     if (nq == 0) return PEOS_OK;
     if (!queries || !tables || !qnorms) return fail(PEOS_EINVAL, "null device pointer");
+    if (((uintptr_t)queries & 15u) != 0) return fail(PEOS_EINVAL, "queries must be 16-byte aligned");
     peos::QueryTableArgs a;
     a.queries = queries;
     a.dirs_a = ix->dirs_a;

@@ -293,6 +293,17 @@ def test_edge_cases(tiny):
         P.search(tiny.index, tiny.qt, w.k, w.ef, eps=0.0)
     with pytest.raises(P.PeosError):
         P.search(tiny.index, tiny.qt, w.k, w.ef, eps=0.7)
+    # queries not 16-byte aligned (a view one float into a buffer): both the
+    # table entry point and the search reject them before any launch
+    buf = torch.zeros(3 * w.d + 1, dtype=torch.float32, device=dev())
+    mis = buf[1:].view(3, w.d)
+    assert mis.data_ptr() % 16 != 0
+    tables = torch.empty((3, w.L + 1, w.m), dtype=torch.float32, device=dev())
+    norms = torch.empty(3, dtype=torch.float32, device=dev())
+    with pytest.raises(P.PeosError):
+        P.peos_query_tables(tiny.index, mis, tables, norms)
+    with pytest.raises(P.PeosError):
+        P.search(tiny.index, mis, w.k, w.ef)
 
 
 def test_duplicate_vectors_and_single_node(tiny):
